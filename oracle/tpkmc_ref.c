@@ -1,0 +1,704 @@
+/*
+ * tpkmc_ref.c -- plain FP64 CPU oracle of the collision step of the
+ * test-particle kinetic Monte Carlo method (Sagert et al., arXiv:1210.8084).
+ *
+ * TEST INFRASTRUCTURE ONLY: used by the test-suite, the smoke check and the
+ * CPU baseline of the benchmark; never by the GPU library.  It shares no
+ * code with the GPU sources.  Build with -ffp-contract=off (no FMA), so that
+ * every product below is rounded on its own.
+ *
+ * One step, in the order of Sec. 3 (flow chart, Fig. 2):
+ *   1. sort particles into c-bins                      (Sec. 3)
+ *   2. partner search over the bin and its neighbours  (Sec. 3, Fig. 1)
+ *      with the three criteria: negative crossing number chi (Sec. 2.4,
+ *      crossing-number equation), real overlap times t_o (Sec. 2.4, the
+ *      overlap-time quadratic), smallest distance between final partners
+ *   3. keep only unambiguous partners                  (end of Sec. 3)
+ *   4. isotropic elastic scattering in the centre-of-mass frame (Sec. 3)
+ *   5. position update split at t_poca, free streaming otherwise (Sec. 3)
+ *   6. walls, then o-bin moments (Sec. 4, bulk velocity, stress tensor,
+ *      pressure and temperature equations)
+ */
+#include "tpkmc_ref.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10, from the description in Salmon, Moraes, Dror and Shaw,     */
+/* "Parallel random numbers: as easy as 1, 2, 3" (SC'11): ten rounds of two  */
+/* 32x32->64 multiplications; the high halves are XORed with the other two   */
+/* words and the round key, the words are permuted, and the key is bumped by */
+/* the Weyl constants (golden ratio and sqrt(3)-1 in 32-bit fixed point).    */
+/* ------------------------------------------------------------------------ */
+void ref_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t p0 = (uint64_t)M0 * (uint64_t)x0;
+        uint64_t p1 = (uint64_t)M1 * (uint64_t)x2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t y0 = hi1 ^ x1 ^ k0;
+        uint32_t y1 = lo1;
+        uint32_t y2 = hi0 ^ x3 ^ k1;
+        uint32_t y3 = lo0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+        k0 += W0;
+        k1 += W1;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* Uniform double in [0, 1) from two 32-bit words: 27 + 26 = 53 bits. */
+static double unit_double(uint32_t a, uint32_t b)
+{
+    double hi = (double)(a >> 5);
+    double lo = (double)(b >> 6);
+    return (hi * 67108864.0 + lo) * (1.0 / 9007199254740992.0);
+}
+
+/* Outgoing directions are "random and opposite" (Sec. 3); the random unit
+ * vector is drawn with Marsaglia's 1972 rejection method, which needs only a
+ * square root.  The counter names the pair and the draw. */
+int ref_direction(uint64_t seed, uint64_t step, uint32_t instance,
+                  uint32_t idA, uint32_t idB, double n[3])
+{
+    uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
+    for (uint32_t attempt = 0; attempt < 256u; ++attempt) {
+        uint32_t ctr[4] = { (uint32_t)step, idA, idB, (instance << 8) | attempt };
+        uint32_t w[4];
+        ref_philox4x32_10(ctr, key, w);
+        double u1 = unit_double(w[0], w[1]);
+        double u2 = unit_double(w[2], w[3]);
+        double x1 = 2.0 * u1 - 1.0;
+        double x2 = 2.0 * u2 - 1.0;
+        double s = x1 * x1 + x2 * x2;
+        if (s < 1.0) {
+            double q = sqrt(1.0 - s);
+            n[0] = (2.0 * x1) * q;
+            n[1] = (2.0 * x2) * q;
+            n[2] = 1.0 - 2.0 * s;
+            return (int)attempt + 1;
+        }
+    }
+    n[0] = 0.0; n[1] = 0.0; n[2] = 1.0;
+    return 256;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Grid                                                                      */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    double L[3], w[3], inv_w[3], halfL[3], inv_wo[3];
+    double D2;
+    int32_t n[3], bc[3], no[3];
+    int64_t C, B;
+} derived;
+
+static int derive(const ref_grid* g, const ref_params* p, derived* G)
+{
+    if (!g) return -1;
+    G->C = 1; G->B = 1;
+    for (int a = 0; a < 3; ++a) {
+        if (g->ncell[a] < 1 || g->nobin[a] < 1) return -1;
+        if (!(g->hi[a] > g->lo[a])) return -1;
+        if (g->bc[a] < 0 || g->bc[a] > 2) return -1;
+        G->n[a] = g->ncell[a];
+        G->no[a] = g->nobin[a];
+        G->bc[a] = g->bc[a];
+        G->L[a] = g->hi[a] - g->lo[a];
+        G->w[a] = G->L[a] / (double)g->ncell[a];
+        G->inv_w[a] = (double)g->ncell[a] / G->L[a];
+        G->inv_wo[a] = (double)g->nobin[a] / G->L[a];
+        G->halfL[a] = 0.5 * G->L[a];
+        G->C *= g->ncell[a];
+        G->B *= g->nobin[a];
+    }
+    if (p) {
+        if (!(p->sigma >= 0.0) || !(p->dt > 0.0) || !(p->mass > 0.0)) return -1;
+        if (p->instance >= (1u << 24)) return -1;
+        /* sigma = 4 pi r_eff^2 and d_min <= r_eff,A + r_eff,B = 2 r_eff
+         * (Sec. 2.4), so the largest accepted d_min^2 is sigma / pi. */
+        G->D2 = p->sigma / M_PI;
+    } else {
+        G->D2 = 0.0;
+    }
+    return 0;
+}
+
+/* Bin along one axis: floor((x - lo) / w), clamped into [0, n-1]. */
+static int32_t axis_bin(double x, double lo, double inv_w, int32_t n)
+{
+    double t = (x - lo) * inv_w;
+    if (!(t >= 0.0)) return 0;
+    if (t >= (double)n) return n - 1;
+    return (int32_t)t;
+}
+
+int32_t ref_cell_of(const ref_grid* g, double x, double y, double z, int32_t c[3])
+{
+    derived G;
+    if (derive(g, NULL, &G)) return -1;
+    int32_t cx = axis_bin(x, g->lo[0], G.inv_w[0], G.n[0]);
+    int32_t cy = axis_bin(y, g->lo[1], G.inv_w[1], G.n[1]);
+    int32_t cz = axis_bin(z, g->lo[2], G.inv_w[2], G.n[2]);
+    if (c) { c[0] = cx; c[1] = cy; c[2] = cz; }
+    return cx + G.n[0] * (cy + G.n[1] * cz);
+}
+
+/* The bin itself and its 8 (2D) / 26 (3D) neighbours (Sec. 3): every cell
+ * whose index differs by at most one on each axis, wrapping on periodic
+ * axes, dropped outside the grid otherwise, listed once each. */
+static int stencil(const derived* G, int64_t c, int64_t out[27])
+{
+    int32_t cx = (int32_t)(c % G->n[0]);
+    int32_t cy = (int32_t)((c / G->n[0]) % G->n[1]);
+    int32_t cz = (int32_t)(c / ((int64_t)G->n[0] * G->n[1]));
+    int count = 0;
+    for (int dz = -1; dz <= 1; ++dz) {
+        int32_t z = cz + dz;
+        if (G->bc[2] == REF_BC_PERIODIC) z = ((z % G->n[2]) + G->n[2]) % G->n[2];
+        else if (z < 0 || z >= G->n[2]) continue;
+        for (int dy = -1; dy <= 1; ++dy) {
+            int32_t y = cy + dy;
+            if (G->bc[1] == REF_BC_PERIODIC) y = ((y % G->n[1]) + G->n[1]) % G->n[1];
+            else if (y < 0 || y >= G->n[1]) continue;
+            for (int dx = -1; dx <= 1; ++dx) {
+                int32_t x = cx + dx;
+                if (G->bc[0] == REF_BC_PERIODIC) x = ((x % G->n[0]) + G->n[0]) % G->n[0];
+                else if (x < 0 || x >= G->n[0]) continue;
+                int64_t cell = x + (int64_t)G->n[0] * (y + (int64_t)G->n[1] * z);
+                int seen = 0;
+                for (int k = 0; k < count; ++k)
+                    if (out[k] == cell) seen = 1;
+                if (!seen) out[count++] = cell;
+            }
+        }
+    }
+    return count;
+}
+
+int ref_stencil(const ref_grid* g, int32_t c, int32_t out[27])
+{
+    derived G;
+    if (derive(g, NULL, &G)) return -1;
+    if (c < 0 || c >= G.C) return -1;
+    int64_t tmp[27];
+    int k = stencil(&G, c, tmp);
+    for (int i = 0; i < k; ++i) out[i] = (int32_t)tmp[i];
+    return k;
+}
+
+/* Adjacency of two c-bins written as a predicate (used by the brute-force
+ * search, independent of the enumeration above). */
+static int adjacent(const derived* G, int64_t c1, int64_t c2)
+{
+    int64_t a[3], b[3];
+    a[0] = c1 % G->n[0]; a[1] = (c1 / G->n[0]) % G->n[1]; a[2] = c1 / ((int64_t)G->n[0] * G->n[1]);
+    b[0] = c2 % G->n[0]; b[1] = (c2 / G->n[0]) % G->n[1]; b[2] = c2 / ((int64_t)G->n[0] * G->n[1]);
+    for (int k = 0; k < 3; ++k) {
+        int64_t d = a[k] - b[k];
+        if (d < 0) d = -d;
+        if (G->bc[k] == REF_BC_PERIODIC && G->n[k] - d < d) d = G->n[k] - d;
+        if (d > 1) return 0;
+    }
+    return 1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The three criteria (Sec. 2.4 and the list in Sec. 3)                      */
+/* ------------------------------------------------------------------------ */
+/* Relative position with the minimum image on periodic axes. */
+static void rel(const derived* G, const double ri[3], const double vi[3],
+                const double rj[3], const double vj[3], double r[3], double u[3])
+{
+    for (int a = 0; a < 3; ++a) {
+        r[a] = ri[a] - rj[a];
+        if (G->bc[a] == REF_BC_PERIODIC) {
+            if (r[a] > G->halfL[a]) r[a] = r[a] - G->L[a];
+            else if (r[a] < -G->halfL[a]) r[a] = r[a] + G->L[a];
+        }
+        u[a] = vi[a] - vj[a];
+    }
+}
+
+static int test_pair(const derived* G, double dt,
+                     const double ri[3], const double vi[3],
+                     const double rj[3], const double vj[3],
+                     double* d2_out, double* tp_out)
+{
+    double r[3], u[3];
+    rel(G, ri, vi, rj, vj, r, u);
+    /* Criterion 1, chi < 0: with straight-line motion v_rel is constant and
+     * r_rel(t + dt) = r + u dt, so chi = s0 * s1 with s0 = r.u and
+     * s1 = r.u + |u|^2 dt; chi < 0 <=> s0 < 0 < s1. */
+    double s0 = (r[0] * u[0] + r[1] * u[1]) + r[2] * u[2];
+    if (!(s0 < 0.0)) return 0;
+    double vv = (u[0] * u[0] + u[1] * u[1]) + u[2] * u[2];
+    double s1 = s0 + vv * dt;
+    if (!(s1 > 0.0)) return 0;
+    /* Time and separation at the point of closest approach (Sec. 3,
+     * t_poca equation). */
+    double tp = -s0 / vv;
+    double q[3];
+    for (int a = 0; a < 3; ++a) q[a] = r[a] + tp * u[a];
+    double d2 = (q[0] * q[0] + q[1] * q[1]) + q[2] * q[2];
+    /* Criterion 2: the overlap times are real exactly when the discriminant
+     * of the quadratic is non-negative, i.e. when d_min^2 <= D^2. */
+    if (!(d2 <= G->D2)) return 0;
+    *d2_out = d2;
+    *tp_out = tp;
+    return 1;
+}
+
+int ref_pair_test(const ref_grid* g, const ref_params* p,
+                  const double ri[3], const double vi[3],
+                  const double rj[3], const double vj[3],
+                  double* d2, double* tp)
+{
+    derived G;
+    if (derive(g, p, &G)) return -1;
+    return test_pair(&G, p->dt, ri, vi, rj, vj, d2, tp);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Particle views and binning                                                */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int64_t n;
+    const double *x, *y, *z, *vx, *vy, *vz;
+    const uint32_t* id;
+    const uint8_t* alive;
+} view;
+
+static int finite6(const view* V, int64_t i)
+{
+    return isfinite(V->x[i]) && isfinite(V->y[i]) && isfinite(V->z[i]) &&
+           isfinite(V->vx[i]) && isfinite(V->vy[i]) && isfinite(V->vz[i]);
+}
+
+/* A particle takes part in the partner search when it is alive and all of
+ * its coordinates are finite. */
+static int usable(const view* V, int64_t i)
+{
+    if (V->alive && !V->alive[i]) return 0;
+    return finite6(V, i);
+}
+
+static void load(const view* V, int64_t i, double r[3], double v[3])
+{
+    r[0] = V->x[i]; r[1] = V->y[i]; r[2] = V->z[i];
+    v[0] = V->vx[i]; v[1] = V->vy[i]; v[2] = V->vz[i];
+}
+
+/* Cell lists by a plain counting sort: cell[i] (-1 if not usable),
+ * first[c]..first[c+1] indexes member[]. */
+typedef struct {
+    int64_t* cell;
+    int64_t* first;
+    int64_t* member;
+} bins;
+
+static int make_bins(const derived* G, const ref_grid* g, const view* V, bins* Bn)
+{
+    Bn->cell = (int64_t*)malloc(sizeof(int64_t) * (size_t)(V->n > 0 ? V->n : 1));
+    Bn->first = (int64_t*)calloc((size_t)G->C + 1, sizeof(int64_t));
+    Bn->member = (int64_t*)malloc(sizeof(int64_t) * (size_t)(V->n > 0 ? V->n : 1));
+    if (!Bn->cell || !Bn->first || !Bn->member) return -1;
+    for (int64_t i = 0; i < V->n; ++i) {
+        if (!usable(V, i)) { Bn->cell[i] = -1; continue; }
+        int32_t cx = axis_bin(V->x[i], g->lo[0], G->inv_w[0], G->n[0]);
+        int32_t cy = axis_bin(V->y[i], g->lo[1], G->inv_w[1], G->n[1]);
+        int32_t cz = axis_bin(V->z[i], g->lo[2], G->inv_w[2], G->n[2]);
+        Bn->cell[i] = cx + (int64_t)G->n[0] * (cy + (int64_t)G->n[1] * cz);
+        Bn->first[Bn->cell[i] + 1] += 1;
+    }
+    for (int64_t c = 0; c < G->C; ++c) Bn->first[c + 1] += Bn->first[c];
+    int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)G->C);
+    if (!fill) return -1;
+    memcpy(fill, Bn->first, sizeof(int64_t) * (size_t)G->C);
+    for (int64_t i = 0; i < V->n; ++i)
+        if (Bn->cell[i] >= 0) Bn->member[fill[Bn->cell[i]]++] = i;
+    free(fill);
+    return 0;
+}
+
+static void free_bins(bins* Bn)
+{
+    free(Bn->cell); free(Bn->first); free(Bn->member);
+}
+
+/* Criterion 3: the closest candidate, ties to the lower id. */
+static void consider(const derived* G, double dt, const view* V, int64_t j,
+                     const double ri[3], const double vi[3],
+                     int64_t* bj, double* bd2, uint64_t* ncand)
+{
+    double rj[3], vj[3], d2, tp;
+    load(V, j, rj, vj);
+    if (!test_pair(G, dt, ri, vi, rj, vj, &d2, &tp)) return;
+    *ncand += 1;
+    if (*bj < 0 || d2 < *bd2 || (d2 == *bd2 && V->id[j] < V->id[*bj])) {
+        *bj = j;
+        *bd2 = d2;
+    }
+}
+
+static void best_of(const derived* G, double dt, const view* V, const bins* Bn,
+                    int mode, int64_t i, int64_t* bj_out, double* bd2_out, uint64_t* ncand)
+{
+    int64_t bj = -1;
+    double bd2 = 0.0;
+    *bj_out = -1; *bd2_out = 0.0;
+    if (Bn->cell[i] < 0) return;
+    double ri[3], vi[3];
+    load(V, i, ri, vi);
+    if (mode == REF_MODE_BINNED) {
+        int64_t nb[27];
+        int k = stencil(G, Bn->cell[i], nb);
+        for (int s = 0; s < k; ++s)
+            for (int64_t m = Bn->first[nb[s]]; m < Bn->first[nb[s] + 1]; ++m) {
+                int64_t j = Bn->member[m];
+                if (j != i) consider(G, dt, V, j, ri, vi, &bj, &bd2, ncand);
+            }
+    } else {
+        for (int64_t j = 0; j < V->n; ++j) {
+            if (j == i || Bn->cell[j] < 0) continue;
+            if (mode == REF_MODE_BRUTE && !adjacent(G, Bn->cell[i], Bn->cell[j])) continue;
+            consider(G, dt, V, j, ri, vi, &bj, &bd2, ncand);
+        }
+    }
+    *bj_out = bj;
+    *bd2_out = bd2;
+}
+
+static int nthreads_or_default(int nthreads)
+{
+#ifdef _OPENMP
+    return nthreads > 0 ? nthreads : omp_get_max_threads();
+#else
+    (void)nthreads;
+    return 1;
+#endif
+}
+
+static uint64_t search_all(const derived* G, double dt, const view* V, const bins* Bn,
+                           int mode, int nthreads, int64_t* best, double* best_d2)
+{
+    uint64_t total = 0;
+    int nt = nthreads_or_default(nthreads);
+    (void)nt;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : total) num_threads(nt)
+    for (int64_t i = 0; i < V->n; ++i) {
+        uint64_t nc = 0;
+        best_of(G, dt, V, Bn, mode, i, &best[i], &best_d2[i], &nc);
+        total += nc;
+    }
+    return total;
+}
+
+static int check_common(const derived* G, const ref_grid* g, const ref_params* p, int64_t n,
+                        const void* x, const void* y, const void* z,
+                        const void* vx, const void* vy, const void* vz, const void* id)
+{
+    (void)G; (void)g; (void)p;
+    if (n < 0) return -1;
+    if (n > 0 && (!x || !y || !z || !vx || !vy || !vz || !id)) return -1;
+    return 0;
+}
+
+int ref_best(const ref_grid* g, const ref_params* p, int64_t n,
+             const double* x, const double* y, const double* z,
+             const double* vx, const double* vy, const double* vz,
+             const uint32_t* id, const uint8_t* alive, int mode, int nthreads,
+             int64_t* best, double* best_d2)
+{
+    derived G;
+    if (derive(g, p, &G)) return -1;
+    if (check_common(&G, g, p, n, x, y, z, vx, vy, vz, id)) return -1;
+    if (mode < 0 || mode > 2 || (n > 0 && (!best || !best_d2))) return -1;
+    view V = { n, x, y, z, vx, vy, vz, id, alive };
+    bins Bn;
+    if (make_bins(&G, g, &V, &Bn)) { free_bins(&Bn); return -2; }
+    search_all(&G, p->dt, &V, &Bn, mode, nthreads, best, best_d2);
+    free_bins(&Bn);
+    return 0;
+}
+
+int ref_best_sample(const ref_grid* g, const ref_params* p, int64_t n,
+                    const double* x, const double* y, const double* z,
+                    const double* vx, const double* vy, const double* vz,
+                    const uint32_t* id, const uint8_t* alive,
+                    int64_t ns, const int64_t* sample, int nthreads,
+                    int64_t* best, double* best_d2)
+{
+    derived G;
+    if (derive(g, p, &G)) return -1;
+    if (check_common(&G, g, p, n, x, y, z, vx, vy, vz, id)) return -1;
+    if (ns < 0 || (ns > 0 && (!sample || !best || !best_d2))) return -1;
+    for (int64_t k = 0; k < ns; ++k)
+        if (sample[k] < 0 || sample[k] >= n) return -1;
+    view V = { n, x, y, z, vx, vy, vz, id, alive };
+    bins Bn;
+    if (make_bins(&G, g, &V, &Bn)) { free_bins(&Bn); return -2; }
+    int nt = nthreads_or_default(nthreads);
+    (void)nt;
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nt)
+    for (int64_t k = 0; k < ns; ++k) {
+        uint64_t nc = 0;
+        best_of(&G, p->dt, &V, &Bn, REF_MODE_BINNED, sample[k], &best[k], &best_d2[k], &nc);
+    }
+    free_bins(&Bn);
+    return 0;
+}
+
+uint64_t ref_count_tests(const ref_grid* g, int64_t n,
+                         const double* x, const double* y, const double* z,
+                         const double* vx, const double* vy, const double* vz,
+                         const uint8_t* alive)
+{
+    derived G;
+    if (derive(g, NULL, &G) || n < 0) return 0;
+    static const uint32_t no_id = 0;
+    view V = { n, x, y, z, vx, vy, vz, &no_id, alive };
+    bins Bn;
+    if (make_bins(&G, g, &V, &Bn)) { free_bins(&Bn); return 0; }
+    uint64_t total = 0;
+    for (int64_t c = 0; c < G.C; ++c) {
+        uint64_t nc = (uint64_t)(Bn.first[c + 1] - Bn.first[c]);
+        total += nc * (nc - (nc > 0 ? 1 : 0)) / 2;
+        int64_t nb[27];
+        int k = stencil(&G, c, nb);
+        for (int s = 0; s < k; ++s)
+            if (nb[s] > c) total += nc * (uint64_t)(Bn.first[nb[s] + 1] - Bn.first[nb[s]]);
+    }
+    free_bins(&Bn);
+    return total;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Compensated (Neumaier) summation for the global sums.                     */
+/* ------------------------------------------------------------------------ */
+typedef struct { double s, c; } nsum;
+static void nadd(nsum* a, double v)
+{
+    double t = a->s + v;
+    if (fabs(a->s) >= fabs(v)) a->c += (a->s - t) + v;
+    else a->c += (v - t) + a->s;
+    a->s = t;
+}
+static double nval(const nsum* a) { return a->s + a->c; }
+
+/* ------------------------------------------------------------------------ */
+/* One step                                                                  */
+/* ------------------------------------------------------------------------ */
+int ref_step(const ref_grid* g, const ref_params* p, int64_t n,
+             double* x, double* y, double* z,
+             double* vx, double* vy, double* vz,
+             const uint32_t* id, uint8_t* alive, int mode, int nthreads,
+             uint32_t* pairs, int64_t pair_cap,
+             uint64_t* counters, double* moments, double* globals)
+{
+    derived G;
+    if (derive(g, p, &G)) return -1;
+    if (check_common(&G, g, p, n, x, y, z, vx, vy, vz, id)) return -1;
+    if (mode < 0 || mode > 2 || pair_cap < 0) return -1;
+    for (int a = 0; a < 3; ++a)
+        if (G.bc[a] == REF_BC_ABSORB && !alive) return -1;
+    const double dt = p->dt, m = p->mass;
+    view V = { n, x, y, z, vx, vy, vz, id, alive };
+    uint64_t cnt[8] = { 0 };
+
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    int64_t* best = (int64_t*)malloc(sizeof(int64_t) * nn);
+    double* best_d2 = (double*)malloc(sizeof(double) * nn);
+    int64_t* partner = (int64_t*)malloc(sizeof(int64_t) * nn);
+    double* nvel = (double*)malloc(sizeof(double) * 3 * nn);
+    double* vir = (double*)calloc(3 * nn, sizeof(double));
+    double* tpoca = (double*)malloc(sizeof(double) * nn);
+    bins Bn = { 0, 0, 0 };
+    int rc = 0;
+    if (!best || !best_d2 || !partner || !nvel || !vir || !tpoca) { rc = -2; goto done; }
+
+    /* Diagnostics on the incoming state. */
+    for (int64_t i = 0; i < n; ++i) {
+        if (alive && !alive[i]) continue;
+        if (!finite6(&V, i)) { cnt[REF_CNT_NONFINITE]++; continue; }
+        if (fabs(vx[i]) * dt > G.w[0] || fabs(vy[i]) * dt > G.w[1] || fabs(vz[i]) * dt > G.w[2])
+            cnt[REF_CNT_FAST]++;
+    }
+
+    /* 1. Sort into c-bins. */
+    if (make_bins(&G, g, &V, &Bn)) { rc = -2; goto done; }
+    for (int64_t c = 0; c < G.C; ++c) {
+        uint64_t nc = (uint64_t)(Bn.first[c + 1] - Bn.first[c]);
+        cnt[REF_CNT_TESTS] += nc * (nc - (nc > 0 ? 1 : 0)) / 2;
+        int64_t nb[27];
+        int k = stencil(&G, c, nb);
+        for (int s = 0; s < k; ++s)
+            if (nb[s] > c) cnt[REF_CNT_TESTS] += nc * (uint64_t)(Bn.first[nb[s] + 1] - Bn.first[nb[s]]);
+    }
+
+    /* 2. Closest candidate of every particle. */
+    cnt[REF_CNT_CAND] = search_all(&G, dt, &V, &Bn, mode, nthreads, best, best_d2);
+    for (int64_t i = 0; i < n; ++i)
+        if (best[i] >= 0) cnt[REF_CNT_HAVE_BEST]++;
+
+    /* 3. Unambiguous partners: i and j chose each other. */
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t j = best[i];
+        partner[i] = (j >= 0 && best[j] == i) ? j : -1;
+    }
+
+    /* 4. Scattering of every accepted pair, visited once from its lower id. */
+    int64_t npairs = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t j = partner[i];
+        if (j < 0 || !(id[i] < id[j])) continue;
+        const int64_t A = i, B = j;
+        double rA[3], vA[3], rB[3], vB[3], r[3], u[3], nhat[3];
+        load(&V, A, rA, vA);
+        load(&V, B, rB, vB);
+        rel(&G, rA, vA, rB, vB, r, u);
+        double s0 = (r[0] * u[0] + r[1] * u[1]) + r[2] * u[2];
+        double vv = (u[0] * u[0] + u[1] * u[1]) + u[2] * u[2];
+        double tp = -s0 / vv;
+        ref_direction(p->seed, p->step, p->instance, id[A], id[B], nhat);
+        /* Centre-of-mass frame, equal masses: the relative speed g is kept
+         * and the outgoing velocities are opposite along nhat. */
+        double gr = sqrt(vv);
+        double h = 0.5 * gr;
+        for (int a = 0; a < 3; ++a) {
+            double vcm = 0.5 * (vA[a] + vB[a]);
+            nvel[3 * A + a] = vcm + h * nhat[a];
+            nvel[3 * B + a] = vcm - h * nhat[a];
+        }
+        tpoca[A] = tp;
+        tpoca[B] = tp;
+        /* Virial term of the stress tensor: separation at the point of
+         * closest approach times the momentum transfer, half per particle. */
+        for (int a = 0; a < 3; ++a) {
+            double sep = r[a] + tp * u[a];
+            double dpA = m * (nvel[3 * A + a] - vA[a]);
+            double dpB = m * (nvel[3 * B + a] - vB[a]);
+            vir[3 * A + a] = 0.5 * sep * dpA / dt;
+            vir[3 * B + a] = 0.5 * (-sep) * dpB / dt;
+        }
+        if (pairs && npairs < pair_cap) {
+            pairs[2 * npairs] = id[A];
+            pairs[2 * npairs + 1] = id[B];
+        }
+        npairs++;
+    }
+    cnt[REF_CNT_PAIRS] = (uint64_t)npairs;
+
+    /* 5. Positions: split at t_poca for colliders, free streaming otherwise;
+     * then the walls. */
+    double* pos[3] = { x, y, z };
+    double* vel[3] = { vx, vy, vz };
+    for (int64_t i = 0; i < n; ++i) {
+        if (alive && !alive[i]) continue;
+        for (int a = 0; a < 3; ++a) {
+            double xa = pos[a][i], va = vel[a][i];
+            double xn, vn;
+            if (partner[i] >= 0) {
+                vn = nvel[3 * i + a];
+                xn = (xa + va * tpoca[i]) + vn * (dt - tpoca[i]);
+            } else {
+                vn = va;
+                xn = xa + va * dt;
+            }
+            pos[a][i] = xn;
+            vel[a][i] = vn;
+        }
+        int gone = 0;
+        for (int a = 0; a < 3; ++a) {
+            double lo = g->lo[a], hi = g->hi[a];
+            double xn = pos[a][i];
+            if (G.bc[a] == REF_BC_REFLECT) {
+                if (xn < lo) { pos[a][i] = lo + (lo - xn); vel[a][i] = -vel[a][i]; }
+                else if (xn > hi) { pos[a][i] = hi - (xn - hi); vel[a][i] = -vel[a][i]; }
+            } else if (G.bc[a] == REF_BC_PERIODIC) {
+                if (xn < lo) xn = xn + G.L[a];
+                if (xn >= hi) xn = xn - G.L[a];
+                pos[a][i] = xn;
+            } else {
+                if (xn < lo || xn >= hi) gone = 1;
+            }
+        }
+        if (gone) { alive[i] = 0; cnt[REF_CNT_ABSORBED]++; }
+    }
+
+    /* 6. Moments of the post-step state per o-bin, and global sums. */
+    nsum gp[3] = { { 0, 0 }, { 0, 0 }, { 0, 0 } }, ge = { 0, 0 }, gv = { 0, 0 }, gm = { 0, 0 };
+    double vmax2 = 0.0;
+    int64_t* ob = (int64_t*)malloc(sizeof(int64_t) * nn);
+    if (!ob) { rc = -2; goto done; }
+    if (moments) memset(moments, 0, sizeof(double) * (size_t)G.B * REF_M_STRIDE);
+    for (int64_t i = 0; i < n; ++i) {
+        ob[i] = -1;
+        if (alive && !alive[i]) continue;
+        if (!finite6(&V, i)) continue;
+        cnt[REF_CNT_ALIVE]++;
+        int32_t bx = axis_bin(x[i], g->lo[0], G.inv_wo[0], G.no[0]);
+        int32_t by = axis_bin(y[i], g->lo[1], G.inv_wo[1], G.no[1]);
+        int32_t bz = axis_bin(z[i], g->lo[2], G.inv_wo[2], G.no[2]);
+        ob[i] = bx + (int64_t)G.no[0] * (by + (int64_t)G.no[1] * bz);
+        double v2 = (vx[i] * vx[i] + vy[i] * vy[i]) + vz[i] * vz[i];
+        nadd(&gp[0], m * vx[i]);
+        nadd(&gp[1], m * vy[i]);
+        nadd(&gp[2], m * vz[i]);
+        nadd(&ge, 0.5 * m * v2);
+        nadd(&gm, m);
+        nadd(&gv, (vir[3 * i] + vir[3 * i + 1]) + vir[3 * i + 2]);
+        if (v2 > vmax2) vmax2 = v2;
+        if (moments) {
+            double* M = moments + ob[i] * REF_M_STRIDE;
+            M[REF_M_COUNT] += 1.0;
+            M[REF_M_PX] += m * vx[i];
+            M[REF_M_PX + 1] += m * vy[i];
+            M[REF_M_PX + 2] += m * vz[i];
+            M[REF_M_VIRX] += vir[3 * i];
+            M[REF_M_VIRX + 1] += vir[3 * i + 1];
+            M[REF_M_VIRX + 2] += vir[3 * i + 2];
+            if (partner[i] >= 0) M[REF_M_NCOLL] += 1.0;
+        }
+    }
+    if (moments) {
+        /* Second pass: spread around the bin's bulk velocity. */
+        for (int64_t i = 0; i < n; ++i) {
+            if (ob[i] < 0) continue;
+            double* M = moments + ob[i] * REF_M_STRIDE;
+            double mass_bin = m * M[REF_M_COUNT];
+            double vb[3] = { M[REF_M_PX] / mass_bin, M[REF_M_PX + 1] / mass_bin, M[REF_M_PX + 2] / mass_bin };
+            double dv0 = vx[i] - vb[0], dv1 = vy[i] - vb[1], dv2 = vz[i] - vb[2];
+            M[REF_M_CXX] += m * dv0 * dv0;
+            M[REF_M_CXX + 1] += m * dv1 * dv1;
+            M[REF_M_CXX + 2] += m * dv2 * dv2;
+        }
+    }
+    free(ob);
+    if (globals) {
+        globals[REF_G_PX] = nval(&gp[0]);
+        globals[REF_G_PY] = nval(&gp[1]);
+        globals[REF_G_PZ] = nval(&gp[2]);
+        globals[REF_G_EKIN] = nval(&ge);
+        globals[REF_G_VMAX2] = vmax2;
+        globals[REF_G_VIRIAL] = nval(&gv);
+        globals[REF_G_MASS] = nval(&gm);
+        globals[REF_G_RESERVED] = 0.0;
+    }
+    if (counters) memcpy(counters, cnt, sizeof(cnt));
+
+done:
+    free_bins(&Bn);
+    free(best); free(best_d2); free(partner); free(nvel); free(vir); free(tpoca);
+    return rc;
+}
