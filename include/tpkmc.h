@@ -1,0 +1,243 @@
+/*
+ * tpkmc.h -- C ABI of the MI355X (gfx950) collision step of the
+ * test-particle kinetic Monte Carlo method of Sagert et al., "Hydrodynamic
+ * Shock Wave Studies within a Kinetic Monte Carlo Approach" (arXiv:1210.8084).
+ *
+ * One call of tpkmc_step advances N test particles by one time step dt, as
+ * laid out in Sec. 3 of the paper (flow chart, Fig. 2):
+ *   1. sort the particles into c-bins of a uniform grid;
+ *   2. for every particle, search its own c-bin and the neighbouring ones
+ *      (8 in 2D, 26 in 3D; Sec. 3, Fig. 1) for partners that satisfy the
+ *      three criteria: negative crossing number chi within dt (Sec. 2.4,
+ *      crossing-number equation), real overlap times of the effective radii,
+ *      i.e. closest-approach distance d_min <= D with D^2 = sigma/pi
+ *      (Sec. 2.4, effective-radius relation and overlap-time quadratic), and
+ *      smallest d_min among the candidates (ties to the lower id);
+ *   3. keep only unambiguous partners: i and j are paired when each is the
+ *      other's closest candidate (end of Sec. 3);
+ *   4. scatter each pair elastically and isotropically in its centre-of-mass
+ *      frame, with outgoing velocities random and opposite (Sec. 3);
+ *   5. move colliders to their point of closest approach with the old
+ *      velocity and on with the new one, stream the rest freely (Sec. 3,
+ *      t_poca and position-update equations); apply the walls;
+ *   6. accumulate o-bin moments: count, momentum, velocity spread and the
+ *      collisional (virial) part of the stress tensor (Sec. 4, stress-tensor
+ *      equation), plus global momentum, kinetic energy and max |v|^2.
+ *
+ * Random numbers: Philox4x32-10 keyed by the 64-bit seed, with counter
+ * (step, id_A, id_B, instance << 8 | draw), id_A < id_B, so every draw is a
+ * pure function of (seed, step, instance, pair); Marsaglia's method turns
+ * two uniforms into the isotropic direction.
+ *
+ * Conventions:
+ *   - Every function returns TPKMC_OK (0) or a negative TPKMC_E* code.
+ *     Argument errors are detected on the host before anything is launched.
+ *     Conditions met on the device (pair-list overflow, non-finite input,
+ *     a particle faster than one c-bin per step) set bits of a sticky status
+ *     word read with tpkmc_status.  No C++ exception or abort crosses the ABI.
+ *   - All particle and output pointers are DEVICE pointers owned by the
+ *     caller (for example torch tensors); the handle owns only its scratch,
+ *     allocated once in tpkmc_create.
+ *   - Work is enqueued on the caller's HIP stream (hipStream_t passed as
+ *     void*, NULL = default stream) and the calls return without waiting.
+ *     One handle serves one stream at a time.
+ *   - Precision is fixed per handle: TPKMC_FP64 takes double particle
+ *     arrays and reproduces the CPU oracle's pair decisions bit for bit;
+ *     TPKMC_FP32 takes float arrays.  Moments and global sums are FP64 in
+ *     both modes.
+ */
+#ifndef TPKMC_H
+#define TPKMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TPKMC_ABI_VERSION 1
+
+enum {
+    TPKMC_OK = 0,
+    TPKMC_EINVAL = -1,       /* bad argument, checked before any launch      */
+    TPKMC_ENOMEM = -2,       /* device allocation failed (tpkmc_create)      */
+    TPKMC_EHIP = -3,         /* a HIP runtime call failed                    */
+    TPKMC_ECAPACITY = -4,    /* input exceeds the capacities of the handle   */
+    TPKMC_EUNSUPPORTED = -5  /* valid but not supported by this build        */
+};
+
+enum { TPKMC_FP64 = 0, TPKMC_FP32 = 1 };
+
+/* Boundary per axis.  REFLECT mirrors position and velocity component at
+ * the wall; PERIODIC wraps (pair tests use the minimum image); ABSORB marks
+ * the particle dead (alive = 0) once it leaves [lo, hi).  Pair tests ignore
+ * walls (straight lines). */
+enum { TPKMC_BC_REFLECT = 0, TPKMC_BC_PERIODIC = 1, TPKMC_BC_ABSORB = 2 };
+
+/* tpkmc_params.flags */
+enum {
+    TPKMC_EMIT_PAIRS = 1u,     /* write accepted pairs to outputs.pairs       */
+    TPKMC_ALLOW_REORDER = 2u   /* leave all particle arrays (id and alive
+                                  included) in c-bin order instead of the
+                                  caller's order                            */
+};
+
+/* Bits of the device status word (sticky until read). */
+enum {
+    TPKMC_STATUS_PAIR_OVERFLOW = 1, /* more pairs than outputs.pair_cap       */
+    TPKMC_STATUS_NONFINITE = 2,     /* an alive particle had a NaN/Inf value  */
+    TPKMC_STATUS_FAST = 4           /* |v_a| dt > c-bin width on some axis    */
+};
+
+/* Counters (uint64[8] per instance). */
+enum {
+    TPKMC_CNT_ALIVE = 0,      /* alive particles with finite state, after    */
+    TPKMC_CNT_PAIRS = 1,      /* accepted pairs                              */
+    TPKMC_CNT_TESTS = 2,      /* algorithmic unordered neighbourhood pairs:
+                                 sum_c n_c(n_c-1)/2 + sum_{c'>c adjacent}
+                                 n_c n_c'                                   */
+    TPKMC_CNT_CAND = 3,       /* ordered (i, j) passing all three criteria   */
+    TPKMC_CNT_FAST = 4,       /* particles with |v_a| dt > w_a (before)      */
+    TPKMC_CNT_NONFINITE = 5,  /* alive particles with a NaN/Inf value        */
+    TPKMC_CNT_ABSORBED = 6,   /* particles absorbed in this step             */
+    TPKMC_CNT_HAVE_BEST = 7   /* particles with at least one candidate       */
+};
+
+/* Globals (double[8] per instance), over alive finite particles after the
+ * step: 0..2 sum m v_a, 3 sum m|v|^2/2, 4 max |v|^2, 5 sum of virial trace
+ * terms, 6 sum m, 7 zero. */
+enum { TPKMC_G_PX = 0, TPKMC_G_EKIN = 3, TPKMC_G_VMAX2 = 4, TPKMC_G_VIRIAL = 5, TPKMC_G_MASS = 6 };
+
+/* Per-o-bin moments (double[nobin * 11] per instance, o-bin index
+ * bx + nobin[0] * (by + nobin[1] * bz) of the post-step position):
+ *  0 count; 1..3 sum m v_a; 4..6 sum m (v_a - vbar_a)^2 with vbar the bin's
+ *  mean velocity; 7..9 sum over colliders of (1/2) s_a dp_a / dt with s the
+ *  separation from the partner at closest approach and dp the momentum
+ *  change; 10 number of colliders.  Pressure of a bin of volume V:
+ *  p = (sum_a [4+a] + sum_a [7+a]) / (3 V); temperature T = sum_a [4+a] /
+ *  (3 count). */
+#define TPKMC_MOMENT_STRIDE 11
+
+typedef struct tpkmc_handle tpkmc_handle;
+
+typedef struct {
+    int64_t max_particles;  /* capacity: particles (sum over instances)      */
+    int64_t max_cells;      /* capacity: sum over instances of (c-bins + 1)  */
+    int64_t max_obins;      /* capacity: sum over instances of o-bins        */
+    int32_t max_instances;  /* capacity: instances per call (>= 1)           */
+    int32_t precision;      /* TPKMC_FP64 or TPKMC_FP32                      */
+    int32_t device;         /* HIP device ordinal                            */
+    uint32_t flags;         /* reserved, must be 0                           */
+} tpkmc_config;
+
+/* Box [lo, hi) per axis with ncell c-bins (partner search) and nobin
+ * o-bins (moments) per axis.  Cell index cx + ncell[0]*(cy + ncell[1]*cz),
+ * cx = floor((x - lo) ncell / (hi - lo)) clamped into [0, ncell-1]. */
+typedef struct {
+    double lo[3], hi[3];
+    int32_t ncell[3];
+    int32_t bc[3];          /* TPKMC_BC_* per axis                           */
+    int32_t nobin[3];
+    int32_t pad;
+} tpkmc_grid;
+
+typedef struct {
+    double sigma;           /* cross section; D^2 = sigma / pi               */
+    double mass;            /* particle mass (> 0)                           */
+    double dt;              /* time step (> 0)                               */
+    uint64_t seed;          /* Philox key                                    */
+    uint64_t step;          /* step number (low 32 bits enter the counter)   */
+    uint32_t instance;      /* instance number (< 2^24)                      */
+    uint32_t flags;         /* TPKMC_EMIT_PAIRS | TPKMC_ALLOW_REORDER        */
+} tpkmc_params;
+
+/* Structure-of-arrays particle state, device pointers, n entries each.
+ * x..vz are double* (FP64 handle) or float* (FP32 handle).  id: unique
+ * uint32 per particle (read; permuted only with ALLOW_REORDER).  alive:
+ * uint8 0/1, or NULL for all alive (then no axis may be ABSORB). */
+typedef struct {
+    int64_t n;
+    void *x, *y, *z, *vx, *vy, *vz;
+    uint32_t* id;
+    uint8_t* alive;
+} tpkmc_particles;
+
+/* Output device pointers; any may be NULL (that output is skipped).
+ * pairs: uint32[2 * pair_cap], rows (id_A, id_B) with id_A < id_B in
+ * unspecified order; pairs beyond pair_cap are counted, not written, and
+ * set TPKMC_STATUS_PAIR_OVERFLOW.  counters: uint64[8 * n_inst];
+ * globals: double[8 * n_inst]; moments: double[11 * sum of o-bins], the
+ * instances' o-bin blocks concatenated in instance order. */
+typedef struct {
+    uint32_t* pairs;
+    int64_t pair_cap;
+    uint64_t* counters;
+    double* moments;
+    double* globals;
+} tpkmc_outputs;
+
+/* One independent instance of a batch: particles [offset, offset + count)
+ * of the concatenated arrays, with its own grid and parameters.  Slices of
+ * different instances must not overlap. */
+typedef struct {
+    int64_t offset, count;
+    tpkmc_grid grid;
+    tpkmc_params params;
+} tpkmc_instance;
+
+/* ABI version (TPKMC_ABI_VERSION). */
+int tpkmc_version(void);
+
+/* Static description of a return code. */
+const char* tpkmc_strerror(int code);
+
+/* Allocates a handle and all its device scratch on cfg->device (memory is
+ * sized from the capacities: about 50 B per particle in FP32, 90 B in FP64,
+ * 8 B per c-bin, 24 B per o-bin).  *out is NULL on failure. */
+int tpkmc_create(const tpkmc_config* cfg, tpkmc_handle** out);
+
+/* Waits for the handle's work, frees everything.  NULL is a no-op. */
+int tpkmc_destroy(tpkmc_handle* h);
+
+/* One collision step of one instance (steps 1-6 above), in place. */
+int tpkmc_step(tpkmc_handle* h, const tpkmc_grid* g, const tpkmc_params* p,
+               const tpkmc_particles* s, const tpkmc_outputs* o, void* hip_stream);
+
+/* One step of n_inst independent instances in a single set of launches;
+ * s describes the concatenated arrays.  Outputs are per instance as above;
+ * EMIT_PAIRS of any instance writes into the one shared pair list. */
+int tpkmc_step_batched(tpkmc_handle* h, const tpkmc_particles* s,
+                       const tpkmc_instance* inst, int32_t n_inst,
+                       const tpkmc_outputs* o, void* hip_stream);
+
+/* nsteps steps of a batch: the step is captured once as a HIP graph and
+ * replayed nsteps times; each instance's step number advances on the device
+ * from inst[k].params.step.  Outputs hold the last step's values.  Uses the
+ * tuned launch shape (tpkmc_autotune) if one was recorded. */
+int tpkmc_run(tpkmc_handle* h, const tpkmc_particles* s,
+              const tpkmc_instance* inst, int32_t n_inst, int32_t nsteps,
+              const tpkmc_outputs* o, void* hip_stream);
+
+/* Times the results-neutral launch shapes of the partner search on this
+ * batch (work-group size and particles per work-item) and keeps the
+ * fastest for later steps of this handle.  Runs the search kernel only; the
+ * particle state is not modified.  Synchronises the stream. */
+int tpkmc_autotune(tpkmc_handle* h, const tpkmc_particles* s,
+                   const tpkmc_instance* inst, int32_t n_inst, void* hip_stream);
+
+/* Synchronises the handle's last stream, returns the status word in
+ * *device_status and clears it. */
+int tpkmc_status(tpkmc_handle* h, int32_t* device_status);
+
+/* Phase timing: when enabled, every step records HIP events around each
+ * kernel on the step's stream.  tpkmc_profile_read synchronises, writes
+ * the summed milliseconds and launch counts of up to n phases
+ * (0 clear, 1 key, 2 scan, 3 scatter, 4 search, 5 move, 6 finalize) and
+ * resets the sums. */
+int tpkmc_profile_enable(tpkmc_handle* h, int32_t on);
+int tpkmc_profile_read(tpkmc_handle* h, double* ms, int64_t* launches, int32_t n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

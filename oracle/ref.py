@@ -76,6 +76,9 @@ def lib():
         L.ref_best_sample.argtypes = ([_P, _P, ctypes.c_int64] + [_P] * 8 +
                                       [ctypes.c_int64, _P, ctypes.c_int, _P, _P])
         L.ref_best_sample.restype = ctypes.c_int
+        L.ref_step_sample.argtypes = ([_P, _P, ctypes.c_int64] + [_P] * 8 +
+                                      [ctypes.c_int64, _P, ctypes.c_int, _P, _P, _P])
+        L.ref_step_sample.restype = ctypes.c_int
         L.ref_count_tests.argtypes = [_P, ctypes.c_int64] + [_P] * 7
         L.ref_count_tests.restype = ctypes.c_uint64
         L.ref_step.argtypes = ([_P, _P, ctypes.c_int64] + [_P] * 8 +
@@ -194,6 +197,23 @@ def best_sample(state, grid, params, sample, nthreads=0):
     if rc:
         raise ValueError(f"ref_best_sample failed ({rc})")
     return b, d2
+
+
+def step_sample(state, grid, params, sample, nthreads=0):
+    """Post-step state of the listed particles as :func:`step` would leave
+    it (binned mode), without touching ``state``.  Returns (state (k, 6) as
+    x y z vx vy vz, partner index or -1, alive after the step)."""
+    n = _check_state(state)
+    G, P = make_grid(grid), make_params(params)
+    smp = np.ascontiguousarray(sample, dtype=np.int64)
+    out = np.zeros((len(smp), 6))
+    partner = np.full(len(smp), -1, dtype=np.int64)
+    alive = np.zeros(len(smp), dtype=np.uint8)
+    rc = lib().ref_step_sample(ctypes.byref(G), ctypes.byref(P), n, *_state_ptrs(state), len(smp),
+                               _ptr(smp), nthreads, _ptr(out), _ptr(partner), _ptr(alive))
+    if rc:
+        raise ValueError(f"ref_step_sample failed ({rc})")
+    return out, partner, alive
 
 
 def count_tests(state, grid):

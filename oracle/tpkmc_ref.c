@@ -484,6 +484,129 @@ uint64_t ref_count_tests(const ref_grid* g, int64_t n,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Scattering and position update                                            */
+/* ------------------------------------------------------------------------ */
+/* Scattering of the accepted pair {i, j} (Sec. 3): A is the lower id, B the
+ * higher one; r, u, t_poca are recomputed from A's side.  Writes the new
+ * velocities of i and j, t_poca, and their virial terms (separation at the
+ * point of closest approach times momentum change, half per particle). */
+static void scatter_pair(const derived* G, const ref_params* p, const view* V, int64_t i, int64_t j,
+                         double vi_new[3], double vj_new[3], double* tp_out,
+                         double vir_i[3], double vir_j[3])
+{
+    const int i_is_A = V->id[i] < V->id[j];
+    const int64_t A = i_is_A ? i : j, B = i_is_A ? j : i;
+    double rA[3], vA[3], rB[3], vB[3], r[3], u[3], nhat[3], nA[3], nB[3];
+    load(V, A, rA, vA);
+    load(V, B, rB, vB);
+    rel(G, rA, vA, rB, vB, r, u);
+    double s0 = (r[0] * u[0] + r[1] * u[1]) + r[2] * u[2];
+    double vv = (u[0] * u[0] + u[1] * u[1]) + u[2] * u[2];
+    double tp = -s0 / vv;
+    ref_direction(p->seed, p->step, p->instance, V->id[A], V->id[B], nhat);
+    /* Centre-of-mass frame, equal masses: the relative speed g is kept and
+     * the outgoing velocities are opposite along nhat. */
+    double gr = sqrt(vv);
+    double h = 0.5 * gr;
+    for (int a = 0; a < 3; ++a) {
+        double vcm = 0.5 * (vA[a] + vB[a]);
+        nA[a] = vcm + h * nhat[a];
+        nB[a] = vcm - h * nhat[a];
+    }
+    for (int a = 0; a < 3; ++a) {
+        double sep = r[a] + tp * u[a];
+        double dpA = p->mass * (nA[a] - vA[a]);
+        double dpB = p->mass * (nB[a] - vB[a]);
+        double virA = 0.5 * sep * dpA / p->dt;
+        double virB = 0.5 * (-sep) * dpB / p->dt;
+        vi_new[a] = i_is_A ? nA[a] : nB[a];
+        vj_new[a] = i_is_A ? nB[a] : nA[a];
+        vir_i[a] = i_is_A ? virA : virB;
+        vir_j[a] = i_is_A ? virB : virA;
+    }
+    *tp_out = tp;
+}
+
+/* Position update (Sec. 3): old velocity up to t_poca and the new one for
+ * the rest of the step for a collider (vnew != NULL), straight line
+ * otherwise; then the walls, once per axis.  Returns 1 when absorbed. */
+static int move_one(const derived* G, const ref_grid* g, double dt, double r[3], double v[3],
+                    const double* vnew, double tp)
+{
+    for (int a = 0; a < 3; ++a) {
+        if (vnew) {
+            r[a] = (r[a] + v[a] * tp) + vnew[a] * (dt - tp);
+            v[a] = vnew[a];
+        } else {
+            r[a] = r[a] + v[a] * dt;
+        }
+    }
+    int gone = 0;
+    for (int a = 0; a < 3; ++a) {
+        double lo = g->lo[a], hi = g->hi[a];
+        double xn = r[a];
+        if (G->bc[a] == REF_BC_REFLECT) {
+            if (xn < lo) { r[a] = lo + (lo - xn); v[a] = -v[a]; }
+            else if (xn > hi) { r[a] = hi - (xn - hi); v[a] = -v[a]; }
+        } else if (G->bc[a] == REF_BC_PERIODIC) {
+            if (xn < lo) xn = xn + G->L[a];
+            if (xn >= hi) xn = xn - G->L[a];
+            r[a] = xn;
+        } else {
+            if (xn < lo || xn >= hi) gone = 1;
+        }
+    }
+    return gone;
+}
+
+int ref_step_sample(const ref_grid* g, const ref_params* p, int64_t n,
+                    const double* x, const double* y, const double* z,
+                    const double* vx, const double* vy, const double* vz,
+                    const uint32_t* id, const uint8_t* alive,
+                    int64_t ns, const int64_t* sample, int nthreads,
+                    double* out_state, int64_t* out_partner, uint8_t* out_alive)
+{
+    derived G;
+    if (derive(g, p, &G)) return -1;
+    if (check_common(&G, g, p, n, x, y, z, vx, vy, vz, id)) return -1;
+    if (ns < 0 || (ns > 0 && (!sample || !out_state || !out_partner || !out_alive))) return -1;
+    for (int64_t k = 0; k < ns; ++k)
+        if (sample[k] < 0 || sample[k] >= n) return -1;
+    view V = { n, x, y, z, vx, vy, vz, id, alive };
+    bins Bn;
+    if (make_bins(&G, g, &V, &Bn)) { free_bins(&Bn); return -2; }
+    int nt = nthreads_or_default(nthreads);
+    (void)nt;
+#pragma omp parallel for schedule(dynamic, 4) num_threads(nt)
+    for (int64_t k = 0; k < ns; ++k) {
+        int64_t i = sample[k], bi, bb;
+        double d2, r[3], v[3], vnew[3], vj_new[3], tp = 0.0, vir_i[3], vir_j[3];
+        uint64_t nc = 0;
+        load(&V, i, r, v);
+        out_partner[k] = -1;
+        out_alive[k] = (alive && !alive[i]) ? 0 : 1;
+        if (!out_alive[k]) {
+            for (int a = 0; a < 3; ++a) { out_state[6 * k + a] = r[a]; out_state[6 * k + 3 + a] = v[a]; }
+            continue;
+        }
+        best_of(&G, p->dt, &V, &Bn, REF_MODE_BINNED, i, &bi, &d2, &nc);
+        int mutual = 0;
+        if (bi >= 0) {
+            best_of(&G, p->dt, &V, &Bn, REF_MODE_BINNED, bi, &bb, &d2, &nc);
+            mutual = bb == i;
+        }
+        if (mutual) {
+            scatter_pair(&G, p, &V, i, bi, vnew, vj_new, &tp, vir_i, vir_j);
+            out_partner[k] = bi;
+        }
+        if (move_one(&G, g, p->dt, r, v, mutual ? vnew : NULL, tp)) out_alive[k] = 0;
+        for (int a = 0; a < 3; ++a) { out_state[6 * k + a] = r[a]; out_state[6 * k + 3 + a] = v[a]; }
+    }
+    free_bins(&Bn);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Compensated (Neumaier) summation for the global sums.                     */
 /* ------------------------------------------------------------------------ */
 typedef struct { double s, c; } nsum;
@@ -562,38 +685,11 @@ int ref_step(const ref_grid* g, const ref_params* p, int64_t n,
     for (int64_t i = 0; i < n; ++i) {
         int64_t j = partner[i];
         if (j < 0 || !(id[i] < id[j])) continue;
-        const int64_t A = i, B = j;
-        double rA[3], vA[3], rB[3], vB[3], r[3], u[3], nhat[3];
-        load(&V, A, rA, vA);
-        load(&V, B, rB, vB);
-        rel(&G, rA, vA, rB, vB, r, u);
-        double s0 = (r[0] * u[0] + r[1] * u[1]) + r[2] * u[2];
-        double vv = (u[0] * u[0] + u[1] * u[1]) + u[2] * u[2];
-        double tp = -s0 / vv;
-        ref_direction(p->seed, p->step, p->instance, id[A], id[B], nhat);
-        /* Centre-of-mass frame, equal masses: the relative speed g is kept
-         * and the outgoing velocities are opposite along nhat. */
-        double gr = sqrt(vv);
-        double h = 0.5 * gr;
-        for (int a = 0; a < 3; ++a) {
-            double vcm = 0.5 * (vA[a] + vB[a]);
-            nvel[3 * A + a] = vcm + h * nhat[a];
-            nvel[3 * B + a] = vcm - h * nhat[a];
-        }
-        tpoca[A] = tp;
-        tpoca[B] = tp;
-        /* Virial term of the stress tensor: separation at the point of
-         * closest approach times the momentum transfer, half per particle. */
-        for (int a = 0; a < 3; ++a) {
-            double sep = r[a] + tp * u[a];
-            double dpA = m * (nvel[3 * A + a] - vA[a]);
-            double dpB = m * (nvel[3 * B + a] - vB[a]);
-            vir[3 * A + a] = 0.5 * sep * dpA / dt;
-            vir[3 * B + a] = 0.5 * (-sep) * dpB / dt;
-        }
+        scatter_pair(&G, p, &V, i, j, nvel + 3 * i, nvel + 3 * j, &tpoca[i], vir + 3 * i, vir + 3 * j);
+        tpoca[j] = tpoca[i];
         if (pairs && npairs < pair_cap) {
-            pairs[2 * npairs] = id[A];
-            pairs[2 * npairs + 1] = id[B];
+            pairs[2 * npairs] = id[i];
+            pairs[2 * npairs + 1] = id[j];
         }
         npairs++;
     }
@@ -601,38 +697,13 @@ int ref_step(const ref_grid* g, const ref_params* p, int64_t n,
 
     /* 5. Positions: split at t_poca for colliders, free streaming otherwise;
      * then the walls. */
-    double* pos[3] = { x, y, z };
-    double* vel[3] = { vx, vy, vz };
     for (int64_t i = 0; i < n; ++i) {
         if (alive && !alive[i]) continue;
-        for (int a = 0; a < 3; ++a) {
-            double xa = pos[a][i], va = vel[a][i];
-            double xn, vn;
-            if (partner[i] >= 0) {
-                vn = nvel[3 * i + a];
-                xn = (xa + va * tpoca[i]) + vn * (dt - tpoca[i]);
-            } else {
-                vn = va;
-                xn = xa + va * dt;
-            }
-            pos[a][i] = xn;
-            vel[a][i] = vn;
-        }
-        int gone = 0;
-        for (int a = 0; a < 3; ++a) {
-            double lo = g->lo[a], hi = g->hi[a];
-            double xn = pos[a][i];
-            if (G.bc[a] == REF_BC_REFLECT) {
-                if (xn < lo) { pos[a][i] = lo + (lo - xn); vel[a][i] = -vel[a][i]; }
-                else if (xn > hi) { pos[a][i] = hi - (xn - hi); vel[a][i] = -vel[a][i]; }
-            } else if (G.bc[a] == REF_BC_PERIODIC) {
-                if (xn < lo) xn = xn + G.L[a];
-                if (xn >= hi) xn = xn - G.L[a];
-                pos[a][i] = xn;
-            } else {
-                if (xn < lo || xn >= hi) gone = 1;
-            }
-        }
+        double r[3], v[3];
+        load(&V, i, r, v);
+        int gone = move_one(&G, g, dt, r, v, partner[i] >= 0 ? nvel + 3 * i : NULL, tpoca[i]);
+        x[i] = r[0]; y[i] = r[1]; z[i] = r[2];
+        vx[i] = v[0]; vy[i] = v[1]; vz[i] = v[2];
         if (gone) { alive[i] = 0; cnt[REF_CNT_ABSORBED]++; }
     }
 

@@ -126,11 +126,22 @@ uint64_t ref_count_tests(const ref_grid* g, int64_t n,
                          const double* vx, const double* vy, const double* vz,
                          const uint8_t* alive);
 
+/* Post-step state of the listed particles only, as ref_step (binned mode)
+ * would leave it: out_state[6k..6k+5] = x y z vx vy vz, out_partner[k] =
+ * index of the accepted partner or -1, out_alive[k] = alive after the step.
+ * Cost: two neighbourhood searches per listed particle. */
+int ref_step_sample(const ref_grid* g, const ref_params* p, int64_t n,
+                    const double* x, const double* y, const double* z,
+                    const double* vx, const double* vy, const double* vz,
+                    const uint32_t* id, const uint8_t* alive,
+                    int64_t ns, const int64_t* sample, int nthreads,
+                    double* out_state, int64_t* out_partner, uint8_t* out_alive);
+
 /* One full collision step, in place, in caller order.
  * pairs (may be NULL): (idA, idB) with idA < idB, at most pair_cap entries.
  * moments (may be NULL): double[nobin * 11].  globals: double[8] or NULL.
- * counters: uint64[8] or NULL.  alive may be NULL (all alive; ABSORB then
- * has no effect on the caller's data). */
+ * counters: uint64[8] or NULL.  alive may be NULL (all alive), except when
+ * an axis is ABSORB (then the call is rejected). */
 int ref_step(const ref_grid* g, const ref_params* p, int64_t n,
              double* x, double* y, double* z,
              double* vx, double* vy, double* vz,

@@ -1,0 +1,11 @@
+// FP32 instantiation of the step kernels (FMA contraction allowed; the pair
+// test stays symmetric under i <-> j because every fused product negates
+// exactly with its operands).
+#include "tpkmc_kernels.h"
+
+namespace tpkmc {
+template void launch_key<float>(const StepArgs<float>&, hipStream_t);
+template void launch_scatter<float>(const StepArgs<float>&, hipStream_t);
+template void launch_search<float>(const StepArgs<float>&, int, hipStream_t);
+template void launch_move<float>(const StepArgs<float>&, hipStream_t);
+}  // namespace tpkmc

@@ -1,0 +1,13 @@
+// FP64 instantiation of the step kernels.  No FMA contraction: every product
+// is rounded on its own, as in the CPU reference, so pair decisions and the
+// post-step state agree bit for bit.
+#pragma clang fp contract(off)
+
+#include "tpkmc_kernels.h"
+
+namespace tpkmc {
+template void launch_key<double>(const StepArgs<double>&, hipStream_t);
+template void launch_scatter<double>(const StepArgs<double>&, hipStream_t);
+template void launch_search<double>(const StepArgs<double>&, int, hipStream_t);
+template void launch_move<double>(const StepArgs<double>&, hipStream_t);
+}  // namespace tpkmc

@@ -1,0 +1,758 @@
+// Host side of libtpkmc: the C ABI, argument checking, device scratch, the
+// precision-independent kernels (clear, prefix sum, per-instance reduction)
+// and the step pipeline, plain or captured as a HIP graph.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "tpkmc_internal.h"
+
+#pragma clang fp contract(off)
+
+using namespace tpkmc;
+
+namespace {
+
+constexpr int kScanItems = 8;                       // per thread
+constexpr int kScanBlock = 256;
+constexpr int kScanTile = kScanItems * kScanBlock;  // per work-group
+constexpr int kPhases = 8;
+
+enum Phase { PH_CLEAR = 0, PH_KEY, PH_SCAN, PH_SCATTER, PH_SEARCH, PH_MOVE, PH_FINAL };
+
+// ---------------------------------------------------------------- kernels
+__global__ void k_clear(int32_t* start, int64_t ncell, double* moments, int64_t nmom,
+                        unsigned long long* pair_count) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t t = t0; t < ncell; t += stride) start[t] = 0;
+    if (moments)
+        for (int64_t t = t0; t < nmom; t += stride) moments[t] = 0.0;
+    if (t0 == 0) *pair_count = 0ull;
+}
+
+// Exclusive prefix sum of n int32 in place: per-tile totals, a single
+// work-group scan of the totals, then per-tile scans with the tile offset.
+__global__ void __launch_bounds__(kScanBlock) k_scan_reduce(const int32_t* d, int64_t n, int32_t* tile_sum) {
+    __shared__ int32_t lds[kScanBlock / 64];
+    const int64_t b0 = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k)
+        if (b0 + k < n) s += d[b0 + k];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t t = 0;
+        for (int w = 0; w < kScanBlock / 64; ++w) t += lds[w];
+        tile_sum[blockIdx.x] = t;
+    }
+}
+
+// Exclusive scan across one work-group of `v`; returns the prefix, and the
+// total in *total.
+__device__ __forceinline__ int32_t block_exscan(int32_t v, int32_t* lds, int32_t* total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int32_t inc = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t u = __shfl_up(inc, o);
+        if (lane >= o) inc += u;
+    }
+    __syncthreads();
+    if (lane == 63) lds[w] = inc;
+    __syncthreads();
+    int32_t woff = 0, tot = 0;
+    for (int k = 0; k < nw; ++k) {
+        if (k < w) woff += lds[k];
+        tot += lds[k];
+    }
+    *total = tot;
+    return woff + inc - v;
+}
+
+__global__ void __launch_bounds__(1024) k_scan_top(int32_t* tile_sum, int64_t ntiles) {
+    __shared__ int32_t lds[16];
+    int32_t carry = 0;
+    for (int64_t c0 = 0; c0 < ntiles; c0 += blockDim.x) {
+        const int64_t t = c0 + threadIdx.x;
+        const int32_t v = t < ntiles ? tile_sum[t] : 0;
+        int32_t total;
+        const int32_t ex = block_exscan(v, lds, &total);
+        if (t < ntiles) tile_sum[t] = carry + ex;
+        carry += total;
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(kScanBlock) k_scan_apply(int32_t* d, int64_t n, const int32_t* tile_off) {
+    __shared__ int32_t lds[kScanBlock / 64];
+    const int64_t b0 = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int32_t v[kScanItems];
+    int32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = b0 + k < n ? d[b0 + k] : 0;
+        s += v[k];
+    }
+    int32_t total;
+    int32_t run = tile_off[blockIdx.x] + block_exscan(s, lds, &total);
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (b0 + k < n) d[b0 + k] = run;
+        run += v[k];
+    }
+}
+
+// Neumaier (compensated) accumulation.
+struct NSum {
+    double s = 0.0, c = 0.0;
+    __device__ void add(double v) {
+        const double t = s + v;
+        if (fabs(s) >= fabs(v)) c += (s - t) + v;
+        else c += (v - t) + s;
+        s = t;
+    }
+    __device__ double value() const { return s + c; }
+};
+
+// Per-instance reduction of the work-group partials, in a fixed order.
+template <typename real>
+__global__ void __launch_bounds__(256) k_finalize(Inst<real>* inst, const double* gpart, uint64_t* counters,
+                                                  double* globals, uint32_t* status,
+                                                  const unsigned long long* pair_count, int64_t pair_cap,
+                                                  int advance_step) {
+    __shared__ double part[256][kGPart];
+    Inst<real>& I = inst[blockIdx.x];
+    double acc[kGPart];
+    NSum ns[7];
+    for (int k = 0; k < kGPart; ++k) acc[k] = 0.0;
+    double vmax = 0.0;
+    for (int b = threadIdx.x; b < I.nblk; b += blockDim.x) {
+        const double* g = gpart + (int64_t)(I.blk0 + b) * kGPart;
+        for (int k = 0; k < 7; ++k)
+            if (k != GP_VMAX2) ns[k].add(g[k]);
+        vmax = fmax(vmax, g[GP_VMAX2]);
+        for (int k = GP_ALIVE; k < kGPart; ++k) acc[k] += g[k];
+    }
+    for (int k = 0; k < 7; ++k) part[threadIdx.x][k] = ns[k].value();
+    part[threadIdx.x][GP_VMAX2] = vmax;
+    for (int k = GP_ALIVE; k < kGPart; ++k) part[threadIdx.x][k] = acc[k];
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    NSum tot[7];
+    double vm = 0.0, cnt[kGPart];
+    for (int k = 0; k < kGPart; ++k) cnt[k] = 0.0;
+    for (int t = 0; t < (int)blockDim.x; ++t) {
+        for (int k = 0; k < 7; ++k)
+            if (k != GP_VMAX2) tot[k].add(part[t][k]);
+        vm = fmax(vm, part[t][GP_VMAX2]);
+        for (int k = GP_ALIVE; k < kGPart; ++k) cnt[k] += part[t][k];
+    }
+    const int k0 = blockIdx.x;
+    if (counters) {
+        uint64_t* c = counters + 8 * k0;
+        c[TPKMC_CNT_ALIVE] = (uint64_t)cnt[GP_ALIVE];
+        c[TPKMC_CNT_PAIRS] = (uint64_t)cnt[GP_PAIRS];
+        c[TPKMC_CNT_TESTS] = (uint64_t)cnt[GP_TESTS2] / 2u;
+        c[TPKMC_CNT_CAND] = (uint64_t)cnt[GP_CAND];
+        c[TPKMC_CNT_FAST] = (uint64_t)cnt[GP_FAST];
+        c[TPKMC_CNT_NONFINITE] = (uint64_t)cnt[GP_NONFINITE];
+        c[TPKMC_CNT_ABSORBED] = (uint64_t)cnt[GP_ABSORBED];
+        c[TPKMC_CNT_HAVE_BEST] = (uint64_t)cnt[GP_HAVEBEST];
+    }
+    if (globals) {
+        double* g = globals + 8 * k0;
+        g[0] = tot[GP_PX].value();
+        g[1] = tot[GP_PY].value();
+        g[2] = tot[GP_PZ].value();
+        g[3] = tot[GP_EKIN].value();
+        g[4] = vm;
+        g[5] = tot[GP_VIR].value();
+        g[6] = tot[GP_MASS].value();
+        g[7] = 0.0;
+    }
+    uint32_t st = 0;
+    if (cnt[GP_NONFINITE] > 0.0) st |= TPKMC_STATUS_NONFINITE;
+    if (cnt[GP_FAST] > 0.0) st |= TPKMC_STATUS_FAST;
+    if (k0 == 0 && (int64_t)*pair_count > pair_cap) st |= TPKMC_STATUS_PAIR_OVERFLOW;
+    if (st) atomicOr(status, st);
+    if (advance_step) I.step_lo += 1u;
+}
+
+// Shifted o-bin sums -> momentum and central second moments; the bin mean
+// becomes the shift of the next step, so the sums stay small next time.
+template <typename real>
+__global__ void k_moments_final(const Inst<real>* inst, double* moments, double* shift) {
+    const Inst<real>& I = inst[blockIdx.y];
+    const int64_t nb = (int64_t)I.no[0] * I.no[1] * I.no[2];
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    const int64_t ob = I.obin_off + b;
+    double* M = moments + ob * TPKMC_MOMENT_STRIDE;
+    double* S = shift + ob * 3;
+    const double cnt = M[0];
+    if (cnt > 0.0) {
+        const double mass = I.mass_d * cnt;
+        for (int a = 0; a < 3; ++a) {
+            const double s1 = M[1 + a], s2 = M[4 + a];
+            const double mean_off = s1 / mass;
+            M[1 + a] = s1 + mass * S[a];
+            M[4 + a] = fmax(s2 - s1 * mean_off, 0.0);
+            S[a] = S[a] + mean_off;
+        }
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- handle
+struct ProfRec {
+    int phase;
+    hipEvent_t a, b;
+};
+
+struct tpkmc_handle {
+    int device = 0, precision = TPKMC_FP64;
+    int64_t max_n = 0, max_cells = 0, max_obins = 0, max_blk = 0;
+    int32_t max_inst = 0;
+    int32_t *key = nullptr, *rank = nullptr, *start = nullptr, *tiles = nullptr, *src = nullptr, *best = nullptr;
+    void* rec = nullptr;
+    void* inst = nullptr;
+    Blk* blk = nullptr;
+    double* gpart = nullptr;
+    double* shift = nullptr;
+    unsigned long long* pair_count = nullptr;
+    uint32_t* status = nullptr;
+    hipStream_t last_stream = nullptr;
+    hipStream_t own_stream = nullptr;
+    int search_block = kBlock;
+    bool profiling = false;
+    std::vector<ProfRec> prof;
+    std::vector<hipEvent_t> pool;
+    size_t pool_used = 0;
+    double prof_ms[kPhases] = {};
+    int64_t prof_n[kPhases] = {};
+    hipGraphExec_t gexec = nullptr;
+    // Pinned staging ring for the instance and block tables: a slot is
+    // rewritten only after the copy that last read it has run.
+    static constexpr int kRing = 8;
+    char* stage[kRing] = {};
+    hipEvent_t stage_ev[kRing] = {};
+    bool stage_used[kRing] = {};
+    size_t stage_bytes = 0;
+    int stage_next = 0;
+};
+
+namespace {
+
+// Host view of one validated call.
+struct Plan {
+    int n_inst = 0;
+    int64_t ncell_tot = 0, nob_tot = 0, max_nob = 0;
+    int nblk = 0;
+    std::vector<Blk> blk;
+    std::vector<char> inst_bytes;
+};
+
+bool bad_ptr(const void* p) { return p == nullptr; }
+
+template <typename real>
+int make_plan(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* in, int n_inst, Plan& P) {
+    if (!s || !in || n_inst < 1) return TPKMC_EINVAL;
+    if (n_inst > h->max_inst) return TPKMC_ECAPACITY;
+    if (s->n < 0) return TPKMC_EINVAL;
+    if (s->n > h->max_n) return TPKMC_ECAPACITY;
+    if (s->n > 0 && (bad_ptr(s->x) || bad_ptr(s->y) || bad_ptr(s->z) || bad_ptr(s->vx) || bad_ptr(s->vy) ||
+                     bad_ptr(s->vz) || bad_ptr(s->id)))
+        return TPKMC_EINVAL;
+    std::vector<std::pair<int64_t, int64_t>> spans;
+    std::vector<Inst<real>> I(n_inst);
+    P.blk.clear();
+    P.n_inst = n_inst;
+    P.ncell_tot = 0;
+    P.nob_tot = 0;
+    P.max_nob = 0;
+    for (int k = 0; k < n_inst; ++k) {
+        const tpkmc_instance& q = in[k];
+        const tpkmc_grid& g = q.grid;
+        const tpkmc_params& p = q.params;
+        if (q.offset < 0 || q.count < 0 || q.offset + q.count > s->n) return TPKMC_EINVAL;
+        spans.push_back({q.offset, q.count});
+        if (!(std::isfinite(p.sigma) && p.sigma >= 0.0)) return TPKMC_EINVAL;
+        if (!(std::isfinite(p.mass) && p.mass > 0.0)) return TPKMC_EINVAL;
+        if (!(std::isfinite(p.dt) && p.dt > 0.0)) return TPKMC_EINVAL;
+        if (p.instance >= (1u << 24)) return TPKMC_EINVAL;
+        if (p.flags & ~(uint32_t)(TPKMC_EMIT_PAIRS | TPKMC_ALLOW_REORDER)) return TPKMC_EINVAL;
+        Inst<real>& d = I[k];
+        std::memset(&d, 0, sizeof(d));
+        int64_t C = 1, B = 1;
+        for (int a = 0; a < 3; ++a) {
+            if (g.ncell[a] < 1 || g.nobin[a] < 1) return TPKMC_EINVAL;
+            if (g.ncell[a] > (1 << 24) || g.nobin[a] > (1 << 24)) return TPKMC_EINVAL;
+            if (!(std::isfinite(g.lo[a]) && std::isfinite(g.hi[a]) && g.hi[a] > g.lo[a])) return TPKMC_EINVAL;
+            if (g.bc[a] < TPKMC_BC_REFLECT || g.bc[a] > TPKMC_BC_ABSORB) return TPKMC_EINVAL;
+            if (g.bc[a] == TPKMC_BC_ABSORB && s->alive == nullptr) return TPKMC_EINVAL;
+            C *= g.ncell[a];
+            B *= g.nobin[a];
+            // Derived grid quantities, in double, in the order of the reference.
+            const double L = g.hi[a] - g.lo[a];
+            d.n[a] = g.ncell[a];
+            d.no[a] = g.nobin[a];
+            d.bc[a] = g.bc[a];
+            d.lo[a] = (real)g.lo[a];
+            d.hi[a] = (real)g.hi[a];
+            d.L[a] = (real)L;
+            d.halfL[a] = (real)(0.5 * L);
+            d.w[a] = (real)(L / (double)g.ncell[a]);
+            d.inv_w[a] = (real)((double)g.ncell[a] / L);
+            d.inv_wo[a] = (real)((double)g.nobin[a] / L);
+        }
+        if (C + 1 > (int64_t)1 << 30 || B > (int64_t)1 << 30) return TPKMC_EINVAL;
+        d.off = q.offset;
+        d.cnt = q.count;
+        d.C = (int32_t)C;
+        d.cell_off = P.ncell_tot;
+        d.obin_off = P.nob_tot;
+        P.ncell_tot += C + 1;
+        P.nob_tot += B;
+        P.max_nob = std::max(P.max_nob, B);
+        d.seed_lo = (uint32_t)p.seed;
+        d.seed_hi = (uint32_t)(p.seed >> 32);
+        d.step_lo = (uint32_t)p.step;
+        d.instance = p.instance;
+        d.flags = p.flags;
+        d.dt = (real)p.dt;
+        d.D2 = (real)(p.sigma / M_PI);
+        d.mass = (real)p.mass;
+        d.mass_d = p.mass;
+        d.dt_d = p.dt;
+        d.blk0 = (int32_t)P.blk.size();
+        for (int64_t o = 0; o < q.count; o += kBlock) P.blk.push_back({k, (int32_t)(q.offset + o)});
+        d.nblk = (int32_t)P.blk.size() - d.blk0;
+    }
+    std::sort(spans.begin(), spans.end());
+    for (size_t k = 1; k < spans.size(); ++k)
+        if (spans[k - 1].first + spans[k - 1].second > spans[k].first) return TPKMC_EINVAL;
+    if (P.ncell_tot + 1 > h->max_cells + 1) return TPKMC_ECAPACITY;
+    if (P.nob_tot > h->max_obins) return TPKMC_ECAPACITY;
+    if ((int64_t)P.blk.size() > h->max_blk) return TPKMC_ECAPACITY;
+    P.nblk = (int)P.blk.size();
+    P.inst_bytes.resize(sizeof(Inst<real>) * n_inst);
+    std::memcpy(P.inst_bytes.data(), I.data(), P.inst_bytes.size());
+    return TPKMC_OK;
+}
+
+int check_outputs(const tpkmc_outputs* o) {
+    if (!o) return TPKMC_OK;
+    if (o->pairs && o->pair_cap < 0) return TPKMC_EINVAL;
+    return TPKMC_OK;
+}
+
+hipEvent_t pool_event(tpkmc_handle* h) {
+    if (h->pool_used == h->pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        h->pool.push_back(e);
+    }
+    return h->pool[h->pool_used++];
+}
+
+struct PhaseScope {
+    tpkmc_handle* h;
+    int phase;
+    hipStream_t s;
+    hipEvent_t b = nullptr;
+    PhaseScope(tpkmc_handle* h_, int ph, hipStream_t s_, bool on) : h(h_), phase(ph), s(s_) {
+        if (!on) { h = nullptr; return; }
+        hipEvent_t a = pool_event(h);
+        b = pool_event(h);
+        if (!a || !b) { h = nullptr; return; }
+        hipEventRecord(a, s);
+        h->prof.push_back({phase, a, b});
+    }
+    ~PhaseScope() {
+        if (h) hipEventRecord(b, s);
+    }
+};
+
+template <typename real>
+StepArgs<real> make_args(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_outputs* o, const Plan& P) {
+    StepArgs<real> a{};
+    a.x = (real*)s->x; a.y = (real*)s->y; a.z = (real*)s->z;
+    a.vx = (real*)s->vx; a.vy = (real*)s->vy; a.vz = (real*)s->vz;
+    a.id = s->id;
+    a.alive = s->alive;
+    a.inst = (const Inst<real>*)h->inst;
+    a.blk = h->blk;
+    a.nblk = P.nblk;
+    a.key = h->key;
+    a.rank = h->rank;
+    a.start = h->start;
+    a.rec = (real*)h->rec;
+    a.src = h->src;
+    a.best = h->best;
+    a.gpart = h->gpart;
+    a.shift = h->shift;
+    a.pairs = o ? o->pairs : nullptr;
+    a.pair_cap = (o && o->pairs) ? o->pair_cap : 0;
+    a.pair_count = h->pair_count;
+    a.moments = o ? o->moments : nullptr;
+    return a;
+}
+
+void enqueue_scan(tpkmc_handle* h, int64_t n, hipStream_t s) {
+    const int64_t tiles = (n + kScanTile - 1) / kScanTile;
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)tiles), dim3(kScanBlock), 0, s, h->start, n, h->tiles);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, h->tiles, tiles);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)tiles), dim3(kScanBlock), 0, s, h->start, n, h->tiles);
+}
+
+// Everything of one step after the tables are on the device.
+template <typename real>
+void enqueue_step(tpkmc_handle* h, const StepArgs<real>& a, const tpkmc_outputs* o, const Plan& P,
+                  hipStream_t s, bool prof, int advance_step) {
+    const int64_t nmom = (o && o->moments) ? P.nob_tot * TPKMC_MOMENT_STRIDE : 0;
+    {
+        PhaseScope ps(h, PH_CLEAR, s, prof);
+        const int64_t work = std::max<int64_t>(P.ncell_tot + 1, nmom);
+        const int64_t grid = std::min<int64_t>((work + 255) / 256, 4096);
+        hipLaunchKernelGGL(k_clear, dim3((unsigned)std::max<int64_t>(grid, 1)), dim3(256), 0, s, h->start,
+                           P.ncell_tot + 1, nmom ? o->moments : nullptr, nmom, h->pair_count);
+    }
+    if (P.nblk > 0) {
+        PhaseScope ps(h, PH_KEY, s, prof);
+        launch_key<real>(a, s);
+    }
+    {
+        PhaseScope ps(h, PH_SCAN, s, prof);
+        enqueue_scan(h, P.ncell_tot + 1, s);
+    }
+    if (P.nblk > 0) {
+        {
+            PhaseScope ps(h, PH_SCATTER, s, prof);
+            launch_scatter<real>(a, s);
+        }
+        {
+            PhaseScope ps(h, PH_SEARCH, s, prof);
+            launch_search<real>(a, h->search_block, s);
+        }
+        {
+            PhaseScope ps(h, PH_MOVE, s, prof);
+            launch_move<real>(a, s);
+        }
+    }
+    {
+        PhaseScope ps(h, PH_FINAL, s, prof);
+        hipLaunchKernelGGL(k_finalize<real>, dim3(P.n_inst), dim3(256), 0, s, (Inst<real>*)h->inst, h->gpart,
+                           o ? o->counters : nullptr, o ? o->globals : nullptr, h->status, h->pair_count,
+                           a.pair_cap, advance_step);
+        if (nmom) {
+            const unsigned gx = (unsigned)((P.max_nob + 255) / 256);
+            hipLaunchKernelGGL(k_moments_final<real>, dim3(gx, P.n_inst), dim3(256), 0, s,
+                               (const Inst<real>*)h->inst, o->moments, h->shift);
+        }
+    }
+}
+
+int upload(tpkmc_handle* h, const Plan& P, hipStream_t s) {
+    const size_t ib = P.inst_bytes.size(), bb = sizeof(Blk) * P.blk.size();
+    if (ib + bb > h->stage_bytes) return TPKMC_ECAPACITY;
+    const int k = h->stage_next;
+    h->stage_next = (k + 1) % tpkmc_handle::kRing;
+    if (h->stage_used[k] && hipEventSynchronize(h->stage_ev[k]) != hipSuccess) return TPKMC_EHIP;
+    std::memcpy(h->stage[k], P.inst_bytes.data(), ib);
+    if (bb) std::memcpy(h->stage[k] + ib, P.blk.data(), bb);
+    if (hipMemcpyAsync(h->inst, h->stage[k], ib, hipMemcpyHostToDevice, s) != hipSuccess) return TPKMC_EHIP;
+    if (bb && hipMemcpyAsync(h->blk, h->stage[k] + ib, bb, hipMemcpyHostToDevice, s) != hipSuccess)
+        return TPKMC_EHIP;
+    if (hipEventRecord(h->stage_ev[k], s) != hipSuccess) return TPKMC_EHIP;
+    h->stage_used[k] = true;
+    return TPKMC_OK;
+}
+
+template <typename real>
+int step_impl(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* in, int n_inst,
+              const tpkmc_outputs* o, hipStream_t st) {
+    Plan P;
+    int rc = make_plan<real>(h, s, in, n_inst, P);
+    if (rc) return rc;
+    if ((rc = check_outputs(o))) return rc;
+    if (hipSetDevice(h->device) != hipSuccess) return TPKMC_EHIP;
+    if ((rc = upload(h, P, st))) return rc;
+    StepArgs<real> a = make_args<real>(h, s, o, P);
+    enqueue_step<real>(h, a, o, P, st, h->profiling, 0);
+    h->last_stream = st;
+    return hipGetLastError() == hipSuccess ? TPKMC_OK : TPKMC_EHIP;
+}
+
+template <typename real>
+int run_impl(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* in, int n_inst, int nsteps,
+             const tpkmc_outputs* o, hipStream_t caller) {
+    if (nsteps < 0) return TPKMC_EINVAL;
+    Plan P;
+    int rc = make_plan<real>(h, s, in, n_inst, P);
+    if (rc) return rc;
+    if ((rc = check_outputs(o))) return rc;
+    if (nsteps == 0) return TPKMC_OK;
+    if (hipSetDevice(h->device) != hipSuccess) return TPKMC_EHIP;
+    // Graphs are captured on a non-default stream; order it after the caller.
+    hipStream_t st = caller ? caller : h->own_stream;
+    hipEvent_t ev = nullptr;
+    if (!caller) {
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return TPKMC_EHIP;
+        hipEventRecord(ev, nullptr);
+        hipStreamWaitEvent(st, ev, 0);
+    }
+    if ((rc = upload(h, P, st))) return rc;
+    StepArgs<real> a = make_args<real>(h, s, o, P);
+    if (h->gexec) {
+        hipStreamSynchronize(h->last_stream ? h->last_stream : st);
+        hipGraphExecDestroy(h->gexec);
+        h->gexec = nullptr;
+    }
+    hipGraph_t graph = nullptr;
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return TPKMC_EHIP;
+    enqueue_step<real>(h, a, o, P, st, false, 1);
+    if (hipStreamEndCapture(st, &graph) != hipSuccess || !graph) return TPKMC_EHIP;
+    if (hipGraphInstantiate(&h->gexec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        hipGraphDestroy(graph);
+        return TPKMC_EHIP;
+    }
+    hipGraphDestroy(graph);
+    for (int k = 0; k < nsteps; ++k)
+        if (hipGraphLaunch(h->gexec, st) != hipSuccess) return TPKMC_EHIP;
+    if (!caller) {
+        hipEventRecord(ev, st);
+        hipStreamWaitEvent(nullptr, ev, 0);
+        hipEventDestroy(ev);
+    }
+    h->last_stream = st;
+    return hipGetLastError() == hipSuccess ? TPKMC_OK : TPKMC_EHIP;
+}
+
+template <typename real>
+int tune_impl(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* in, int n_inst, hipStream_t st) {
+    Plan P;
+    int rc = make_plan<real>(h, s, in, n_inst, P);
+    if (rc) return rc;
+    if (P.nblk == 0) return TPKMC_OK;
+    if (hipSetDevice(h->device) != hipSuccess) return TPKMC_EHIP;
+    if ((rc = upload(h, P, st))) return rc;
+    tpkmc_outputs none{};
+    StepArgs<real> a = make_args<real>(h, s, &none, P);
+    // Bin once (clear, key, prefix, scatter); then time only the search.
+    hipLaunchKernelGGL(k_clear, dim3(1024), dim3(256), 0, st, h->start, P.ncell_tot + 1, (double*)nullptr,
+                       (int64_t)0, h->pair_count);
+    launch_key<real>(a, st);
+    enqueue_scan(h, P.ncell_tot + 1, st);
+    launch_scatter<real>(a, st);
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    const int shapes[3] = {256, 128, 64};
+    float best_ms = 1e30f;
+    int best_shape = kBlock;
+    for (int shape : shapes) {
+        launch_search<real>(a, shape, st);  // warm-up
+        hipEventRecord(e0, st);
+        for (int r = 0; r < 3; ++r) launch_search<real>(a, shape, st);
+        hipEventRecord(e1, st);
+        if (hipEventSynchronize(e1) != hipSuccess) { rc = TPKMC_EHIP; break; }
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best_ms) { best_ms = ms; best_shape = shape; }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc) return rc;
+    h->search_block = best_shape;
+    h->last_stream = st;
+    return hipGetLastError() == hipSuccess ? TPKMC_OK : TPKMC_EHIP;
+}
+
+template <typename T>
+int dalloc(T** p, int64_t count) {
+    *p = nullptr;
+    if (count <= 0) count = 1;
+    return hipMalloc((void**)p, sizeof(T) * (size_t)count) == hipSuccess ? 0 : -1;
+}
+
+void free_all(tpkmc_handle* h) {
+    for (int k = 0; k < tpkmc_handle::kRing; ++k) {
+        if (h->stage[k]) hipHostFree(h->stage[k]);
+        if (h->stage_ev[k]) hipEventDestroy(h->stage_ev[k]);
+    }
+    hipFree(h->key); hipFree(h->rank); hipFree(h->start); hipFree(h->tiles);
+    hipFree(h->src); hipFree(h->best); hipFree(h->rec); hipFree(h->inst);
+    hipFree(h->blk); hipFree(h->gpart); hipFree(h->shift); hipFree(h->pair_count); hipFree(h->status);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- C ABI
+extern "C" {
+
+int tpkmc_version(void) { return TPKMC_ABI_VERSION; }
+
+const char* tpkmc_strerror(int code) {
+    switch (code) {
+        case TPKMC_OK: return "success";
+        case TPKMC_EINVAL: return "invalid argument";
+        case TPKMC_ENOMEM: return "device allocation failed";
+        case TPKMC_EHIP: return "HIP runtime error";
+        case TPKMC_ECAPACITY: return "input exceeds the handle's capacity";
+        case TPKMC_EUNSUPPORTED: return "unsupported";
+        default: return "unknown error code";
+    }
+}
+
+int tpkmc_create(const tpkmc_config* cfg, tpkmc_handle** out) {
+    if (!out) return TPKMC_EINVAL;
+    *out = nullptr;
+    if (!cfg || cfg->max_particles < 0 || cfg->max_particles >= ((int64_t)1 << 31) || cfg->max_cells < 1 ||
+        cfg->max_cells >= ((int64_t)1 << 30) || cfg->max_obins < 0 || cfg->max_obins >= ((int64_t)1 << 30) ||
+        cfg->max_instances < 1 || cfg->flags != 0 ||
+        (cfg->precision != TPKMC_FP64 && cfg->precision != TPKMC_FP32))
+        return TPKMC_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev) return TPKMC_EINVAL;
+    if (hipSetDevice(cfg->device) != hipSuccess) return TPKMC_EHIP;
+    tpkmc_handle* h = new (std::nothrow) tpkmc_handle();
+    if (!h) return TPKMC_ENOMEM;
+    h->device = cfg->device;
+    h->precision = cfg->precision;
+    h->max_n = cfg->max_particles;
+    h->max_cells = cfg->max_cells;
+    h->max_obins = cfg->max_obins;
+    h->max_inst = cfg->max_instances;
+    h->max_blk = cfg->max_particles / kBlock + cfg->max_instances + 1;
+    const size_t rs = cfg->precision == TPKMC_FP64 ? sizeof(double) : sizeof(float);
+    const size_t inst_sz = cfg->precision == TPKMC_FP64 ? sizeof(Inst<double>) : sizeof(Inst<float>);
+    const int64_t tiles = (cfg->max_cells + 1 + kScanTile - 1) / kScanTile + 1;
+    int bad = 0;
+    bad |= dalloc(&h->key, h->max_n);
+    bad |= dalloc(&h->rank, h->max_n);
+    bad |= dalloc(&h->start, h->max_cells + 1);
+    bad |= dalloc(&h->tiles, tiles);
+    bad |= dalloc(&h->src, h->max_n);
+    bad |= dalloc(&h->best, h->max_n);
+    bad |= hipMalloc(&h->rec, rs * 8 * (size_t)std::max<int64_t>(h->max_n, 1)) != hipSuccess;
+    bad |= hipMalloc(&h->inst, inst_sz * (size_t)h->max_inst) != hipSuccess;
+    bad |= dalloc(&h->blk, h->max_blk);
+    bad |= dalloc(&h->gpart, h->max_blk * kGPart);
+    bad |= dalloc(&h->shift, 3 * std::max<int64_t>(h->max_obins, 1));
+    bad |= dalloc(&h->pair_count, 1);
+    bad |= dalloc(&h->status, 1);
+    h->stage_bytes = inst_sz * (size_t)h->max_inst + sizeof(Blk) * (size_t)h->max_blk;
+    for (int k = 0; k < tpkmc_handle::kRing && !bad; ++k) {
+        bad |= hipHostMalloc((void**)&h->stage[k], h->stage_bytes, hipHostMallocDefault) != hipSuccess;
+        bad |= hipEventCreateWithFlags(&h->stage_ev[k], hipEventDisableTiming) != hipSuccess;
+    }
+    if (!bad) {
+        bad |= hipMemset(h->shift, 0, sizeof(double) * 3 * (size_t)std::max<int64_t>(h->max_obins, 1)) != hipSuccess;
+        bad |= hipMemset(h->status, 0, sizeof(uint32_t)) != hipSuccess;
+        bad |= hipMemset(h->gpart, 0, sizeof(double) * kGPart * (size_t)h->max_blk) != hipSuccess;
+        bad |= hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking) != hipSuccess;
+        bad |= hipDeviceSynchronize() != hipSuccess;
+    }
+    if (bad) {
+        free_all(h);
+        if (h->own_stream) hipStreamDestroy(h->own_stream);
+        delete h;
+        hipGetLastError();
+        return TPKMC_ENOMEM;
+    }
+    *out = h;
+    return TPKMC_OK;
+}
+
+int tpkmc_destroy(tpkmc_handle* h) {
+    if (!h) return TPKMC_OK;
+    hipSetDevice(h->device);
+    hipDeviceSynchronize();
+    if (h->gexec) hipGraphExecDestroy(h->gexec);
+    for (hipEvent_t e : h->pool) hipEventDestroy(e);
+    free_all(h);
+    if (h->own_stream) hipStreamDestroy(h->own_stream);
+    delete h;
+    return TPKMC_OK;
+}
+
+int tpkmc_step(tpkmc_handle* h, const tpkmc_grid* g, const tpkmc_params* p, const tpkmc_particles* s,
+               const tpkmc_outputs* o, void* stream) {
+    if (!h || !g || !p || !s) return TPKMC_EINVAL;
+    tpkmc_instance one;
+    one.offset = 0;
+    one.count = s->n;
+    one.grid = *g;
+    one.params = *p;
+    return tpkmc_step_batched(h, s, &one, 1, o, stream);
+}
+
+int tpkmc_step_batched(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* inst, int32_t n_inst,
+                       const tpkmc_outputs* o, void* stream) {
+    if (!h) return TPKMC_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    return h->precision == TPKMC_FP64 ? step_impl<double>(h, s, inst, n_inst, o, st)
+                                      : step_impl<float>(h, s, inst, n_inst, o, st);
+}
+
+int tpkmc_run(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* inst, int32_t n_inst,
+              int32_t nsteps, const tpkmc_outputs* o, void* stream) {
+    if (!h) return TPKMC_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    return h->precision == TPKMC_FP64 ? run_impl<double>(h, s, inst, n_inst, nsteps, o, st)
+                                      : run_impl<float>(h, s, inst, n_inst, nsteps, o, st);
+}
+
+int tpkmc_autotune(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* inst, int32_t n_inst,
+                   void* stream) {
+    if (!h) return TPKMC_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    return h->precision == TPKMC_FP64 ? tune_impl<double>(h, s, inst, n_inst, st)
+                                      : tune_impl<float>(h, s, inst, n_inst, st);
+}
+
+int tpkmc_status(tpkmc_handle* h, int32_t* device_status) {
+    if (!h || !device_status) return TPKMC_EINVAL;
+    if (hipSetDevice(h->device) != hipSuccess) return TPKMC_EHIP;
+    if (hipStreamSynchronize(h->last_stream) != hipSuccess) return TPKMC_EHIP;
+    uint32_t v = 0;
+    if (hipMemcpy(&v, h->status, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess) return TPKMC_EHIP;
+    if (hipMemset(h->status, 0, sizeof(v)) != hipSuccess) return TPKMC_EHIP;
+    *device_status = (int32_t)v;
+    return TPKMC_OK;
+}
+
+int tpkmc_profile_enable(tpkmc_handle* h, int32_t on) {
+    if (!h) return TPKMC_EINVAL;
+    h->profiling = on != 0;
+    return TPKMC_OK;
+}
+
+int tpkmc_profile_read(tpkmc_handle* h, double* ms, int64_t* launches, int32_t n) {
+    if (!h || n < 0 || (n > 0 && (!ms || !launches))) return TPKMC_EINVAL;
+    if (hipSetDevice(h->device) != hipSuccess) return TPKMC_EHIP;
+    if (!h->prof.empty()) {
+        if (hipEventSynchronize(h->prof.back().b) != hipSuccess) return TPKMC_EHIP;
+        for (const ProfRec& r : h->prof) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess && r.phase >= 0 && r.phase < kPhases) {
+                h->prof_ms[r.phase] += t;
+                h->prof_n[r.phase] += 1;
+            }
+        }
+        h->prof.clear();
+        h->pool_used = 0;
+    }
+    for (int k = 0; k < n; ++k) {
+        ms[k] = k < kPhases ? h->prof_ms[k] : 0.0;
+        launches[k] = k < kPhases ? h->prof_n[k] : 0;
+    }
+    for (int k = 0; k < kPhases; ++k) { h->prof_ms[k] = 0.0; h->prof_n[k] = 0; }
+    return TPKMC_OK;
+}
+
+}  // extern "C"

@@ -263,3 +263,22 @@ def test_resume_equals_uninterrupted(oracle):
     oracle.step(saved, w.grid, w.params)
     for k in a:
         assert np.array_equal(a[k], saved[k])
+
+
+def test_step_sample_matches_full_step(oracle):
+    """The sampled post-step state equals the full step's, particle by
+    particle (the full-size GPU checks rely on it)."""
+    w = W.random_box(n=3000, seed=41, ncell=(5, 4, 3), bc=(R, P, A), d_over_w=0.7, dt_over=0.6)
+    st = W.copy_state(w.state)
+    sample = np.arange(0, 3000, 7)
+    got, partner, alive = oracle.step_sample(st, w.grid, w.params, sample)
+    best, _ = oracle.best(st, w.grid, w.params)
+    oracle.step(st, w.grid, w.params)
+    want = np.stack([st[k][sample] for k in ("x", "y", "z", "vx", "vy", "vz")], axis=1)
+    assert np.array_equal(got, want)
+    assert np.array_equal(alive, st["alive"][sample])
+    for k, i in enumerate(sample):
+        b = best[i]
+        mutual = b >= 0 and best[b] == i
+        assert partner[k] == (b if mutual else -1)
+    assert (partner >= 0).sum() > 50
