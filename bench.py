@@ -127,6 +127,8 @@ def main():
     ap.add_argument("--precision", choices=("fp32", "fp64"), default="fp32")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay timing")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="after the run, copy a 1 GiB device buffer 3 times (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the collision step is not sharded across GPUs in this "
@@ -250,6 +252,13 @@ def main():
     }
     print(json.dumps(line), flush=True)
     eng.close()
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dstb = torch.empty_like(src)
+        for _ in range(3):
+            dstb.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration_copy_bytes_each_way": src.numel() * 4, "copies": 3}), flush=True)
 
 
 if __name__ == "__main__":

@@ -6,6 +6,6 @@
 namespace tpkmc {
 template void launch_key<float>(const StepArgs<float>&, hipStream_t);
 template void launch_scatter<float>(const StepArgs<float>&, hipStream_t);
-template void launch_search<float>(const StepArgs<float>&, int, hipStream_t);
+template void launch_search<float>(const StepArgs<float>&, int, int, hipStream_t);
 template void launch_move<float>(const StepArgs<float>&, hipStream_t);
 }  // namespace tpkmc

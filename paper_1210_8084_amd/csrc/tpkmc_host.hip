@@ -117,65 +117,94 @@ struct NSum {
     __device__ double value() const { return s + c; }
 };
 
-// Per-instance reduction of the work-group partials, in a fixed order.
-template <typename real>
-__global__ void __launch_bounds__(256) k_finalize(Inst<real>* inst, const double* gpart, uint64_t* counters,
-                                                  double* globals, uint32_t* status,
-                                                  const unsigned long long* pair_count, int64_t pair_cap,
-                                                  int advance_step) {
-    __shared__ double part[256][kGPart];
-    Inst<real>& I = inst[blockIdx.x];
-    double acc[kGPart];
-    NSum ns[7];
-    for (int k = 0; k < kGPart; ++k) acc[k] = 0.0;
-    double vmax = 0.0;
-    for (int b = threadIdx.x; b < I.nblk; b += blockDim.x) {
-        const double* g = gpart + (int64_t)(I.blk0 + b) * kGPart;
-        for (int k = 0; k < 7; ++k)
-            if (k != GP_VMAX2) ns[k].add(g[k]);
-        vmax = fmax(vmax, g[GP_VMAX2]);
-        for (int k = GP_ALIVE; k < kGPart; ++k) acc[k] += g[k];
+// Per-instance reduction of the work-group partials, in a fixed order:
+// first each chunk of <= kChunk work-groups, then each instance's chunks.
+// Thread k < kGPart owns slot k; Neumaier sums for the FP slots, max for
+// max|v|^2, plain sums for the (integer-valued) counts.
+__device__ __forceinline__ void reduce_slots(const double* rows, int nrows, double* out) {
+    const int k = threadIdx.x;
+    if (k >= kGPart) return;
+    if (k == GP_VMAX2) {
+        double m = 0.0;
+        for (int r = 0; r < nrows; ++r) m = fmax(m, rows[(int64_t)r * kGPart + k]);
+        out[k] = m;
+    } else if (k < GP_ALIVE) {
+        NSum s;
+        for (int r = 0; r < nrows; ++r) s.add(rows[(int64_t)r * kGPart + k]);
+        out[k] = s.value();
+    } else {
+        double t = 0.0;
+        for (int r = 0; r < nrows; ++r) t += rows[(int64_t)r * kGPart + k];
+        out[k] = t;
     }
-    for (int k = 0; k < 7; ++k) part[threadIdx.x][k] = ns[k].value();
-    part[threadIdx.x][GP_VMAX2] = vmax;
-    for (int k = GP_ALIVE; k < kGPart; ++k) part[threadIdx.x][k] = acc[k];
+}
+
+__global__ void __launch_bounds__(256) k_reduce_chunks(const Chunk* chunks, const double* gpart, double* cpart) {
+    __shared__ double rows[kChunk * kGPart];
+    const Chunk c = chunks[blockIdx.x];
+    for (int t = threadIdx.x; t < c.count * kGPart; t += blockDim.x)
+        rows[t] = gpart[(int64_t)c.first * kGPart + t];
+    __syncthreads();
+    reduce_slots(rows, c.count, cpart + (int64_t)blockIdx.x * kGPart);
+}
+
+template <typename real>
+__global__ void __launch_bounds__(256) k_finalize(Inst<real>* inst, const double* cpart, uint64_t* counters,
+                                                 double* globals, uint32_t* status,
+                                                 const unsigned long long* pair_count, int64_t pair_cap,
+                                                 int advance_step) {
+    __shared__ double tot[kGPart];
+    __shared__ double rows[kChunk * kGPart];
+    Inst<real>& I = inst[blockIdx.x];
+    // Chunk partials of this instance, staged in LDS kChunk rows at a time
+    // (folded in order, so the result does not depend on the launch shape).
+    double acc = 0.0;
+    NSum ns;
+    for (int c0 = 0; c0 < I.nchunk; c0 += kChunk) {
+        const int nr = min(kChunk, I.nchunk - c0);
+        __syncthreads();
+        for (int t = threadIdx.x; t < nr * kGPart; t += blockDim.x)
+            rows[t] = cpart[(int64_t)(I.chunk0 + c0) * kGPart + t];
+        __syncthreads();
+        reduce_slots(rows, nr, tot);
+        __syncthreads();
+        if (threadIdx.x < kGPart) {
+            const int k = threadIdx.x;
+            if (k == GP_VMAX2) acc = fmax(acc, tot[k]);
+            else if (k < GP_ALIVE) ns.add(tot[k]);
+            else acc += tot[k];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < kGPart) tot[threadIdx.x] = threadIdx.x < GP_ALIVE && threadIdx.x != GP_VMAX2 ? ns.value() : acc;
     __syncthreads();
     if (threadIdx.x != 0) return;
-    NSum tot[7];
-    double vm = 0.0, cnt[kGPart];
-    for (int k = 0; k < kGPart; ++k) cnt[k] = 0.0;
-    for (int t = 0; t < (int)blockDim.x; ++t) {
-        for (int k = 0; k < 7; ++k)
-            if (k != GP_VMAX2) tot[k].add(part[t][k]);
-        vm = fmax(vm, part[t][GP_VMAX2]);
-        for (int k = GP_ALIVE; k < kGPart; ++k) cnt[k] += part[t][k];
-    }
     const int k0 = blockIdx.x;
     if (counters) {
         uint64_t* c = counters + 8 * k0;
-        c[TPKMC_CNT_ALIVE] = (uint64_t)cnt[GP_ALIVE];
-        c[TPKMC_CNT_PAIRS] = (uint64_t)cnt[GP_PAIRS];
-        c[TPKMC_CNT_TESTS] = (uint64_t)cnt[GP_TESTS2] / 2u;
-        c[TPKMC_CNT_CAND] = (uint64_t)cnt[GP_CAND];
-        c[TPKMC_CNT_FAST] = (uint64_t)cnt[GP_FAST];
-        c[TPKMC_CNT_NONFINITE] = (uint64_t)cnt[GP_NONFINITE];
-        c[TPKMC_CNT_ABSORBED] = (uint64_t)cnt[GP_ABSORBED];
-        c[TPKMC_CNT_HAVE_BEST] = (uint64_t)cnt[GP_HAVEBEST];
+        c[TPKMC_CNT_ALIVE] = (uint64_t)tot[GP_ALIVE];
+        c[TPKMC_CNT_PAIRS] = (uint64_t)tot[GP_PAIRS];
+        c[TPKMC_CNT_TESTS] = (uint64_t)tot[GP_TESTS2] / 2u;
+        c[TPKMC_CNT_CAND] = (uint64_t)tot[GP_CAND];
+        c[TPKMC_CNT_FAST] = (uint64_t)tot[GP_FAST];
+        c[TPKMC_CNT_NONFINITE] = (uint64_t)tot[GP_NONFINITE];
+        c[TPKMC_CNT_ABSORBED] = (uint64_t)tot[GP_ABSORBED];
+        c[TPKMC_CNT_HAVE_BEST] = (uint64_t)tot[GP_HAVEBEST];
     }
     if (globals) {
         double* g = globals + 8 * k0;
-        g[0] = tot[GP_PX].value();
-        g[1] = tot[GP_PY].value();
-        g[2] = tot[GP_PZ].value();
-        g[3] = tot[GP_EKIN].value();
-        g[4] = vm;
-        g[5] = tot[GP_VIR].value();
-        g[6] = tot[GP_MASS].value();
+        g[0] = tot[GP_PX];
+        g[1] = tot[GP_PY];
+        g[2] = tot[GP_PZ];
+        g[3] = tot[GP_EKIN];
+        g[4] = tot[GP_VMAX2];
+        g[5] = tot[GP_VIR];
+        g[6] = tot[GP_MASS];
         g[7] = 0.0;
     }
     uint32_t st = 0;
-    if (cnt[GP_NONFINITE] > 0.0) st |= TPKMC_STATUS_NONFINITE;
-    if (cnt[GP_FAST] > 0.0) st |= TPKMC_STATUS_FAST;
+    if (tot[GP_NONFINITE] > 0.0) st |= TPKMC_STATUS_NONFINITE;
+    if (tot[GP_FAST] > 0.0) st |= TPKMC_STATUS_FAST;
     if (k0 == 0 && (int64_t)*pair_count > pair_cap) st |= TPKMC_STATUS_PAIR_OVERFLOW;
     if (st) atomicOr(status, st);
     if (advance_step) I.step_lo += 1u;
@@ -221,13 +250,18 @@ struct tpkmc_handle {
     void* rec = nullptr;
     void* inst = nullptr;
     Blk* blk = nullptr;
+    Chunk* chunks = nullptr;
+    unsigned long long* bkey = nullptr;
     double* gpart = nullptr;
+    double* cpart = nullptr;
+    int64_t max_chunks = 0;
     double* shift = nullptr;
     unsigned long long* pair_count = nullptr;
     uint32_t* status = nullptr;
     hipStream_t last_stream = nullptr;
     hipStream_t own_stream = nullptr;
     int search_block = kBlock;
+    int search_group = 2;
     bool profiling = false;
     std::vector<ProfRec> prof;
     std::vector<hipEvent_t> pool;
@@ -253,6 +287,7 @@ struct Plan {
     int64_t ncell_tot = 0, nob_tot = 0, max_nob = 0;
     int nblk = 0;
     std::vector<Blk> blk;
+    std::vector<Chunk> chunks;
     std::vector<char> inst_bytes;
 };
 
@@ -270,6 +305,7 @@ int make_plan(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* i
     std::vector<std::pair<int64_t, int64_t>> spans;
     std::vector<Inst<real>> I(n_inst);
     P.blk.clear();
+    P.chunks.clear();
     P.n_inst = n_inst;
     P.ncell_tot = 0;
     P.nob_tot = 0;
@@ -331,6 +367,10 @@ int make_plan(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* i
         d.blk0 = (int32_t)P.blk.size();
         for (int64_t o = 0; o < q.count; o += kBlock) P.blk.push_back({k, (int32_t)(q.offset + o)});
         d.nblk = (int32_t)P.blk.size() - d.blk0;
+        d.chunk0 = (int32_t)P.chunks.size();
+        for (int32_t b = 0; b < d.nblk; b += kChunk)
+            P.chunks.push_back({d.blk0 + b, std::min<int32_t>(kChunk, d.nblk - b)});
+        d.nchunk = (int32_t)P.chunks.size() - d.chunk0;
     }
     std::sort(spans.begin(), spans.end());
     for (size_t k = 1; k < spans.size(); ++k)
@@ -338,6 +378,7 @@ int make_plan(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* i
     if (P.ncell_tot + 1 > h->max_cells + 1) return TPKMC_ECAPACITY;
     if (P.nob_tot > h->max_obins) return TPKMC_ECAPACITY;
     if ((int64_t)P.blk.size() > h->max_blk) return TPKMC_ECAPACITY;
+    if ((int64_t)P.chunks.size() > h->max_chunks) return TPKMC_ECAPACITY;
     P.nblk = (int)P.blk.size();
     P.inst_bytes.resize(sizeof(Inst<real>) * n_inst);
     std::memcpy(P.inst_bytes.data(), I.data(), P.inst_bytes.size());
@@ -393,6 +434,7 @@ StepArgs<real> make_args(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_
     a.rec = (real*)h->rec;
     a.src = h->src;
     a.best = h->best;
+    a.bkey = h->bkey;
     a.gpart = h->gpart;
     a.shift = h->shift;
     a.pairs = o ? o->pairs : nullptr;
@@ -436,7 +478,7 @@ void enqueue_step(tpkmc_handle* h, const StepArgs<real>& a, const tpkmc_outputs*
         }
         {
             PhaseScope ps(h, PH_SEARCH, s, prof);
-            launch_search<real>(a, h->search_block, s);
+            launch_search<real>(a, h->search_block, h->search_group, s);
         }
         {
             PhaseScope ps(h, PH_MOVE, s, prof);
@@ -445,7 +487,10 @@ void enqueue_step(tpkmc_handle* h, const StepArgs<real>& a, const tpkmc_outputs*
     }
     {
         PhaseScope ps(h, PH_FINAL, s, prof);
-        hipLaunchKernelGGL(k_finalize<real>, dim3(P.n_inst), dim3(256), 0, s, (Inst<real>*)h->inst, h->gpart,
+        if (!P.chunks.empty())
+            hipLaunchKernelGGL(k_reduce_chunks, dim3((unsigned)P.chunks.size()), dim3(256), 0, s,
+                               (const Chunk*)h->chunks, (const double*)h->gpart, h->cpart);
+        hipLaunchKernelGGL(k_finalize<real>, dim3(P.n_inst), dim3(256), 0, s, (Inst<real>*)h->inst, h->cpart,
                            o ? o->counters : nullptr, o ? o->globals : nullptr, h->status, h->pair_count,
                            a.pair_cap, advance_step);
         if (nmom) {
@@ -457,15 +502,18 @@ void enqueue_step(tpkmc_handle* h, const StepArgs<real>& a, const tpkmc_outputs*
 }
 
 int upload(tpkmc_handle* h, const Plan& P, hipStream_t s) {
-    const size_t ib = P.inst_bytes.size(), bb = sizeof(Blk) * P.blk.size();
-    if (ib + bb > h->stage_bytes) return TPKMC_ECAPACITY;
+    const size_t ib = P.inst_bytes.size(), bb = sizeof(Blk) * P.blk.size(), cb = sizeof(Chunk) * P.chunks.size();
+    if (ib + bb + cb > h->stage_bytes) return TPKMC_ECAPACITY;
     const int k = h->stage_next;
     h->stage_next = (k + 1) % tpkmc_handle::kRing;
     if (h->stage_used[k] && hipEventSynchronize(h->stage_ev[k]) != hipSuccess) return TPKMC_EHIP;
     std::memcpy(h->stage[k], P.inst_bytes.data(), ib);
     if (bb) std::memcpy(h->stage[k] + ib, P.blk.data(), bb);
+    if (cb) std::memcpy(h->stage[k] + ib + bb, P.chunks.data(), cb);
     if (hipMemcpyAsync(h->inst, h->stage[k], ib, hipMemcpyHostToDevice, s) != hipSuccess) return TPKMC_EHIP;
     if (bb && hipMemcpyAsync(h->blk, h->stage[k] + ib, bb, hipMemcpyHostToDevice, s) != hipSuccess)
+        return TPKMC_EHIP;
+    if (cb && hipMemcpyAsync(h->chunks, h->stage[k] + ib + bb, cb, hipMemcpyHostToDevice, s) != hipSuccess)
         return TPKMC_EHIP;
     if (hipEventRecord(h->stage_ev[k], s) != hipSuccess) return TPKMC_EHIP;
     h->stage_used[k] = true;
@@ -551,23 +599,31 @@ int tune_impl(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* i
     hipEvent_t e0, e1;
     hipEventCreate(&e0);
     hipEventCreate(&e1);
+    // Results-neutral launch shapes: records per lane (1, 2, 4) and lanes per
+    // work-group (64, 128, 256).
+    const int groups[3] = {1, 2, 4};
     const int shapes[3] = {256, 128, 64};
     float best_ms = 1e30f;
-    int best_shape = kBlock;
-    for (int shape : shapes) {
-        launch_search<real>(a, shape, st);  // warm-up
-        hipEventRecord(e0, st);
-        for (int r = 0; r < 3; ++r) launch_search<real>(a, shape, st);
-        hipEventRecord(e1, st);
-        if (hipEventSynchronize(e1) != hipSuccess) { rc = TPKMC_EHIP; break; }
-        float ms = 0.f;
-        hipEventElapsedTime(&ms, e0, e1);
-        if (ms < best_ms) { best_ms = ms; best_shape = shape; }
+    int best_shape = kBlock, best_group = 2;
+    for (int grp : groups) {
+        for (int shape : shapes) {
+            if (shape > kBlock / grp) continue;
+            launch_search<real>(a, shape, grp, st);  // warm-up
+            hipEventRecord(e0, st);
+            for (int r = 0; r < 3; ++r) launch_search<real>(a, shape, grp, st);
+            hipEventRecord(e1, st);
+            if (hipEventSynchronize(e1) != hipSuccess) { rc = TPKMC_EHIP; break; }
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best_ms) { best_ms = ms; best_shape = shape; best_group = grp; }
+        }
+        if (rc) break;
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     if (rc) return rc;
     h->search_block = best_shape;
+    h->search_group = best_group;
     h->last_stream = st;
     return hipGetLastError() == hipSuccess ? TPKMC_OK : TPKMC_EHIP;
 }
@@ -586,7 +642,7 @@ void free_all(tpkmc_handle* h) {
     }
     hipFree(h->key); hipFree(h->rank); hipFree(h->start); hipFree(h->tiles);
     hipFree(h->src); hipFree(h->best); hipFree(h->rec); hipFree(h->inst);
-    hipFree(h->blk); hipFree(h->gpart); hipFree(h->shift); hipFree(h->pair_count); hipFree(h->status);
+    hipFree(h->blk); hipFree(h->chunks); hipFree(h->bkey); hipFree(h->cpart); hipFree(h->gpart); hipFree(h->shift); hipFree(h->pair_count); hipFree(h->status);
 }
 
 }  // namespace
@@ -628,6 +684,7 @@ int tpkmc_create(const tpkmc_config* cfg, tpkmc_handle** out) {
     h->max_obins = cfg->max_obins;
     h->max_inst = cfg->max_instances;
     h->max_blk = cfg->max_particles / kBlock + cfg->max_instances + 1;
+    h->max_chunks = h->max_blk / kChunk + cfg->max_instances + 1;
     const size_t rs = cfg->precision == TPKMC_FP64 ? sizeof(double) : sizeof(float);
     const size_t inst_sz = cfg->precision == TPKMC_FP64 ? sizeof(Inst<double>) : sizeof(Inst<float>);
     const int64_t tiles = (cfg->max_cells + 1 + kScanTile - 1) / kScanTile + 1;
@@ -642,10 +699,14 @@ int tpkmc_create(const tpkmc_config* cfg, tpkmc_handle** out) {
     bad |= hipMalloc(&h->inst, inst_sz * (size_t)h->max_inst) != hipSuccess;
     bad |= dalloc(&h->blk, h->max_blk);
     bad |= dalloc(&h->gpart, h->max_blk * kGPart);
+    bad |= dalloc(&h->chunks, h->max_chunks);
+    bad |= dalloc(&h->cpart, h->max_chunks * kGPart);
+    if (cfg->precision == TPKMC_FP32) bad |= dalloc(&h->bkey, h->max_n);
     bad |= dalloc(&h->shift, 3 * std::max<int64_t>(h->max_obins, 1));
     bad |= dalloc(&h->pair_count, 1);
     bad |= dalloc(&h->status, 1);
-    h->stage_bytes = inst_sz * (size_t)h->max_inst + sizeof(Blk) * (size_t)h->max_blk;
+    h->stage_bytes = inst_sz * (size_t)h->max_inst + sizeof(Blk) * (size_t)h->max_blk +
+                     sizeof(Chunk) * (size_t)h->max_chunks;
     for (int k = 0; k < tpkmc_handle::kRing && !bad; ++k) {
         bad |= hipHostMalloc((void**)&h->stage[k], h->stage_bytes, hipHostMallocDefault) != hipSuccess;
         bad |= hipEventCreateWithFlags(&h->stage_ev[k], hipEventDisableTiming) != hipSuccess;

@@ -32,6 +32,7 @@ struct Inst {
     int32_t n[3], bc[3];      // c-bins and boundary per axis
     int32_t no[3];            // o-bins per axis
     int32_t blk0, nblk;       // range in the block table
+    int32_t chunk0, nchunk;   // range in the chunk table (partials reduction)
     uint32_t seed_lo, seed_hi, step_lo, instance;
     uint32_t flags;           // TPKMC_EMIT_PAIRS | TPKMC_ALLOW_REORDER
     int32_t pad;
@@ -44,6 +45,14 @@ struct Inst {
 struct Blk {
     int32_t inst;
     int32_t first;
+};
+
+// Chunk of at most kChunk consecutive block-table entries of one instance,
+// the unit of the first level of the per-instance reduction.
+constexpr int kChunk = 256;
+struct Chunk {
+    int32_t first;
+    int32_t count;
 };
 
 // Arguments of one step, shared by all kernels of a precision.
@@ -62,7 +71,8 @@ struct StepArgs {
     int32_t* start;           // counts, then exclusive prefix (ncells + 1)
     real* rec;                // c-bin ordered records, 8 reals per particle
     int32_t* src;             // record -> caller index
-    int32_t* best;            // record -> partner record or -1
+    int32_t* best;            // record -> partner record or -1 (FP64 search)
+    unsigned long long* bkey; // record -> (d_min^2 bits, partner record) (FP32 search)
     double* gpart;            // [nblk][kGPart]
     double* shift;            // per-o-bin velocity shift (3 per o-bin)
     // outputs
@@ -70,13 +80,12 @@ struct StepArgs {
     int64_t pair_cap;
     unsigned long long* pair_count;
     double* moments;
-    int32_t pair_chunk;       // particles per work-item of the search kernel
 };
 
 // Launchers implemented per precision (tpkmc_f32.hip / tpkmc_f64.hip).
 template <typename real> void launch_key(const StepArgs<real>& a, hipStream_t s);
 template <typename real> void launch_scatter(const StepArgs<real>& a, hipStream_t s);
-template <typename real> void launch_search(const StepArgs<real>& a, int block, hipStream_t s);
+template <typename real> void launch_search(const StepArgs<real>& a, int block, int group, hipStream_t s);
 template <typename real> void launch_move(const StepArgs<real>& a, hipStream_t s);
 
 }  // namespace tpkmc

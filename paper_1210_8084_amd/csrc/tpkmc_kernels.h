@@ -13,6 +13,8 @@
 // x-seam) contiguous record ranges.
 #pragma once
 
+#include <type_traits>
+
 #include "tpkmc_internal.h"
 
 namespace tpkmc {
@@ -99,6 +101,27 @@ __device__ __forceinline__ double block_max(double v, double* lds) {
     double t = lds[0];
     for (int k = 1; k < nw; ++k) t = fmax(t, lds[k]);
     return t;
+}
+
+// Sums (max for index kmax) of N values over the work-group in one LDS pass;
+// the totals land in v[] of thread 0.  lds holds 16 * N doubles.
+template <int N>
+__device__ __forceinline__ void block_reduce(double v[N], int kmax, double* lds) {
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+        for (int o = 32; o > 0; o >>= 1) {
+            const double u = __shfl_xor(v[k], o);
+            v[k] = k == kmax ? fmax(v[k], u) : v[k] + u;
+        }
+    const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int k = 0; k < N; ++k) lds[w * N + k] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int q = 1; q < nw; ++q)
+#pragma unroll
+            for (int k = 0; k < N; ++k) v[k] = k == kmax ? fmax(v[k], lds[q * N + k]) : v[k] + lds[q * N + k];
 }
 
 // Work-groups are dispatched round-robin over the 8 XCDs; remap so that each
@@ -201,7 +224,6 @@ __global__ void __launch_bounds__(kBlock) k_key(StepArgs<real> a) {
         // The search kernel may accumulate into these with atomics.
         gp[GP_TESTS2] = 0.0;
         gp[GP_CAND] = 0.0;
-        gp[GP_HAVEBEST] = 0.0;
     }
 }
 
@@ -219,161 +241,460 @@ __global__ void __launch_bounds__(kBlock) k_scatter(StepArgs<real> a) {
     const uint32_t fl = a.alive ? (a.alive[p] != 0) : 1u;
     Rec<real>::store(a.rec, dst, a.x[p], a.y[p], a.z[p], a.id[p], a.vx[p], a.vy[p], a.vz[p], fl);
     a.src[dst] = (int32_t)p;
+    if (a.bkey) a.bkey[dst] = ~0ull;
 }
 
 // ---------------------------------------------------------------- 4. search
-// Neighbourhood of c-bin (cx, cy, cz) as contiguous record ranges.
-struct Ranges {
-    int ny, nz, nxr;
-    int ys[3], zs[3];
-    int xlo[2], xhi[2];
+// Per-instance constants of the pair test, held in registers.
+template <typename real>
+struct Geo {
+    real L[3], halfL[3], invL[3];
+    real dt, D2;
+    bool per[3];
+    __device__ __forceinline__ explicit Geo(const Inst<real>& I) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            L[a] = I.L[a];
+            halfL[a] = I.halfL[a];
+            invL[a] = real(1) / I.L[a];
+            per[a] = I.bc[a] == TPKMC_BC_PERIODIC;
+        }
+        dt = I.dt;
+        D2 = I.D2;
+    }
 };
 
-__device__ __forceinline__ void axis_set(int c, int n, int bc, int out[3], int& cnt) {
-    if (bc == TPKMC_BC_PERIODIC) {
-        if (n <= 3) {
-            cnt = n;
-            for (int k = 0; k < n; ++k) out[k] = k;
+// Minimum image on a periodic axis, written as selects (same value as the
+// reference's if / else-if).
+template <typename real>
+__device__ __forceinline__ real min_image(real r, real L, real halfL) {
+    const real up = r - L, dn = r + L;
+    return r > halfL ? up : (r < -halfL ? dn : r);
+}
+
+// The three criteria for the ordered pair (i, j): chi < 0 within the step
+// (s0 = r.u < 0 < s1 = r.u + |u|^2 dt), then d_min^2 <= D^2.  Returns d_min^2,
+// or -1 when j is not a candidate.  j == i (or an exact twin) has r.u = 0 and
+// is rejected by the first criterion.
+//
+// Most pairs fail, and a branch taken by any lane of a wave costs the whole
+// wave, so the rejection is decided without branches and without a division:
+// d_min^2 |u|^2 = |r x u|^2, hence d_min^2 <= D^2  <=>  |r x u|^2 <= D^2 |u|^2.
+//  - FP32: that form decides; d_min^2 = |r x u|^2 / |u|^2 only for candidates.
+//  - FP64: that form, with FMAs and a margin far above the rounding of either
+//    form, only discards pairs that are certainly not candidates; the rest go
+//    through the reference's own expressions (t_poca = -s0/|u|^2, PoCA
+//    separation r + t_poca u), so decisions and d_min^2 are bit-identical.
+template <typename real, bool PER>
+__device__ __forceinline__ void rel_vectors(const Geo<real>& G, real xi, real yi, real zi, real vxi, real vyi,
+                                            real vzi, real xj, real yj, real zj, real vxj, real vyj, real vzj,
+                                            real& rx, real& ry, real& rz, real& ux, real& uy, real& uz) {
+    rx = xi - xj; ry = yi - yj; rz = zi - zj;
+    if (PER) {
+        if (G.per[0]) rx = min_image(rx, G.L[0], G.halfL[0]);
+        if (G.per[1]) ry = min_image(ry, G.L[1], G.halfL[1]);
+        if (G.per[2]) rz = min_image(rz, G.L[2], G.halfL[2]);
+    }
+    ux = vxi - vxj; uy = vyi - vyj; uz = vzi - vzj;
+}
+
+// Two-stage screening, both stages without divergent branches:
+//  stage 1, criterion 1 (s0 < 0 < s1), on every pair;
+//  stage 2, |r x u|^2 <= D^2 |u|^2, only when some lane of the wave passed
+//  stage 1 (a wave-uniform branch, so cold regions where no pair of the wave
+//  meets within the step skip it).
+template <typename real> struct Screen {
+    real rx, ry, rz, ux, uy, uz, s0, vv;
+};
+
+template <typename real, bool PER> struct PairTest;
+
+template <bool PER> struct PairTest<float, PER> {
+    static __device__ __forceinline__ bool stage1(const Geo<float>& G, float xi, float yi, float zi, float vxi,
+                                                  float vyi, float vzi, float xj, float yj, float zj, float vxj,
+                                                  float vyj, float vzj, Screen<float>& S) {
+        float rx = xi - xj, ry = yi - yj, rz = zi - zj;
+        if (PER) {
+            // Nearest image: r - L rint(r / L) (ties at exactly L/2 keep r).
+            if (G.per[0]) rx = fmaf(-G.L[0], rintf(rx * G.invL[0]), rx);
+            if (G.per[1]) ry = fmaf(-G.L[1], rintf(ry * G.invL[1]), ry);
+            if (G.per[2]) rz = fmaf(-G.L[2], rintf(rz * G.invL[2]), rz);
+        }
+        const float ux = vxi - vxj, uy = vyi - vyj, uz = vzi - vzj;
+        const float s0 = fmaf(rz, uz, fmaf(ry, uy, rx * ux));
+        const float vv = fmaf(uz, uz, fmaf(uy, uy, ux * ux));
+        const float s1 = fmaf(vv, G.dt, s0);
+        S.rx = rx; S.ry = ry; S.rz = rz; S.ux = ux; S.uy = uy; S.uz = uz; S.s0 = s0; S.vv = vv;
+        return (s0 < 0.0f) & (s1 > 0.0f);
+    }
+    static __device__ __forceinline__ bool stage2(const Geo<float>& G, const Screen<float>& S) {
+        const float cx = fmaf(S.ry, S.uz, -S.rz * S.uy);
+        const float cy = fmaf(S.rz, S.ux, -S.rx * S.uz);
+        const float cz = fmaf(S.rx, S.uy, -S.ry * S.ux);
+        const float c2 = fmaf(cz, cz, fmaf(cy, cy, cx * cx));
+        return c2 <= G.D2 * S.vv;
+    }
+    // d_min^2 of a pair that passed both stages (always a candidate in FP32).
+    static __device__ __forceinline__ float finish(const Geo<float>&, const Screen<float>& S) {
+        const float cx = fmaf(S.ry, S.uz, -S.rz * S.uy);
+        const float cy = fmaf(S.rz, S.ux, -S.rx * S.uz);
+        const float cz = fmaf(S.rx, S.uy, -S.ry * S.ux);
+        return fmaf(cz, cz, fmaf(cy, cy, cx * cx)) / S.vv;
+    }
+};
+
+template <bool PER> struct PairTest<double, PER> {
+    static __device__ __forceinline__ bool stage1(const Geo<double>& G, double xi, double yi, double zi, double vxi,
+                                                  double vyi, double vzi, double xj, double yj, double zj, double vxj,
+                                                  double vyj, double vzj, Screen<double>& S) {
+        double rx, ry, rz, ux, uy, uz;
+        rel_vectors<double, PER>(G, xi, yi, zi, vxi, vyi, vzi, xj, yj, zj, vxj, vyj, vzj, rx, ry, rz, ux, uy, uz);
+        // Exactly the reference's s0 and s1 (no contraction in this unit).
+        const double s0 = (rx * ux + ry * uy) + rz * uz;
+        const double vv = (ux * ux + uy * uy) + uz * uz;
+        const double s1 = s0 + vv * G.dt;
+        S.rx = rx; S.ry = ry; S.rz = rz; S.ux = ux; S.uy = uy; S.uz = uz; S.s0 = s0; S.vv = vv;
+        return (s0 < 0.0) & (s1 > 0.0);
+    }
+    // Conservative: |r x u|^2 <= D^2 |u|^2 with a margin far above the
+    // rounding of either form, so no pair the reference accepts is lost.
+    static __device__ __forceinline__ bool stage2(const Geo<double>& G, const Screen<double>& S) {
+        const double cx = fma(S.ry, S.uz, -S.rz * S.uy);
+        const double cy = fma(S.rz, S.ux, -S.rx * S.uz);
+        const double cz = fma(S.rx, S.uy, -S.ry * S.ux);
+        const double c2 = fma(cz, cz, fma(cy, cy, cx * cx));
+        const double rr = fma(S.rz, S.rz, fma(S.ry, S.ry, S.rx * S.rx));
+        return c2 <= fma(G.D2 * S.vv, 1.0 + 1e-6, 1e-12 * rr * S.vv);
+    }
+    // The reference's expressions; -1 when the exact d_min^2 exceeds D^2.
+    static __device__ __forceinline__ double finish(const Geo<double>& G, const Screen<double>& S) {
+        const double tp = -S.s0 / S.vv;
+        const double px = S.rx + tp * S.ux, py = S.ry + tp * S.uy, pz = S.rz + tp * S.uz;
+        const double d2 = (px * px + py * py) + pz * pz;
+        return d2 <= G.D2 ? d2 : -1.0;
+    }
+};
+
+// Neighbour index along one axis (offset d in -1..1): whether it exists and
+// is not a repeat of another offset (periodic axes with 1 or 2 bins), and the
+// wrapped index.
+__device__ __forceinline__ bool axis_nb(int c, int d, int n, bool periodic, int& out) {
+    int v = c + d;
+    if (periodic) {
+        if (n == 1 && d != 0) return false;
+        if (n == 2 && d == 1) return false;
+        v = v < 0 ? v + n : (v >= n ? v - n : v);
+    } else if (v < 0 || v >= n) {
+        return false;
+    }
+    out = v;
+    return true;
+}
+
+// x-extent of the neighbourhood as at most two contiguous bin ranges; the
+// first always contains cx.
+__device__ __forceinline__ int x_ranges(int cx, int n, bool periodic, int xa[2], int xb[2]) {
+    if (periodic && n > 3 && cx == 0) { xa[0] = 0; xb[0] = 1; xa[1] = n - 1; xb[1] = n - 1; return 2; }
+    if (periodic && n > 3 && cx == n - 1) { xa[0] = n - 2; xb[0] = n - 1; xa[1] = 0; xb[1] = 0; return 2; }
+    if (periodic && n <= 3) { xa[0] = 0; xb[0] = n - 1; return 1; }
+    xa[0] = cx > 0 ? cx - 1 : 0;
+    xb[0] = cx < n - 1 ? cx + 1 : n - 1;
+    return 1;
+}
+
+template <typename real>
+__device__ __forceinline__ int cy_of(real y, const Inst<real>& I) { return axis_bin(y, I.lo[1], I.inv_w[1], I.n[1]); }
+template <typename real>
+__device__ __forceinline__ int cz_of(real z, const Inst<real>& I) { return axis_bin(z, I.lo[2], I.inv_w[2], I.n[2]); }
+
+// Visits the record ranges of the neighbourhood of record i (bin cx, cy, cz).
+// HALF: only pairs (i, j) not visited from j's side -- bins of larger index
+// and, in i's own bin, records after i -- so every unordered pair is met once.
+template <bool HALF, typename F>
+__device__ __forceinline__ void for_neighbourhood(const int32_t* start, int64_t cell_off, int64_t base,
+                                                  const int n[3], const bool per[3], int cx, int cy, int cz,
+                                                  int32_t i, F&& visit) {
+    int xa[2], xb[2];
+    const int nxr = x_ranges(cx, n[0], per[0], xa, xb);
+    const int own_row = cy + n[1] * cz;
+    for (int k = 0; k < 9; ++k) {
+        int y, z;
+        if (!axis_nb(cz, k / 3 - 1, n[2], per[2], z)) continue;
+        if (!axis_nb(cy, k % 3 - 1, n[1], per[1], y)) continue;
+        const int row_idx = y + n[1] * z;
+        if (HALF && row_idx < own_row) continue;
+        const bool own = row_idx == own_row;
+        const int64_t row = cell_off + (int64_t)n[0] * row_idx;
+        for (int r = 0; r < nxr; ++r) {
+            int32_t j0 = (int32_t)(base + start[row + xa[r]]);
+            const int32_t j1 = (int32_t)(base + start[row + xb[r] + 1]);
+            if (HALF && own) {
+                if (r == 0) j0 = i + 1;           // range holding cx: after i
+                else if (xa[r] < cx) continue;    // wrapped bins below cx
+            }
+            visit(j0, j1);
+        }
+    }
+}
+
+// Closest-candidate search with register blocking: one lane owns up to G
+// consecutive records and tests every neighbour record it loads against all
+// of them, so a load serves up to G pair tests.  The lane walks the union of
+// its records' neighbourhoods row by row; record k only takes the records in
+// its own range of that row.
+//
+// HALF (FP32): every unordered pair is tested once -- bins of larger index
+// and, in a record's own bin, the records after it -- and a candidate lowers
+// both particles' 64-bit keys (d_min^2 bits, partner record) with atomicMin,
+// which is order independent; exact ties of d_min^2 go to the lower record.
+// Ordered (FP64): each record scans its whole neighbourhood and keeps the
+// smallest d_min^2, ties to the lower id, with the reference's arithmetic, so
+// the choice does not depend on the order of records inside a bin.
+template <typename real, bool HALF, bool PER, int G>
+__device__ __forceinline__ void search_group(const StepArgs<real>& a, const Inst<real>& I, int64_t base,
+                                             int32_t i0, int nrec, double& tests, double& cand) {
+    const Geo<real> G_(I);
+    const int n[3] = {I.n[0], I.n[1], I.n[2]};
+    real xi[G], yi[G], zi[G], vxi[G], vyi[G], vzi[G];
+    int cxk[G];
+    int cy = 0, cz = 0;
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+        uint32_t idk, flk;
+        const int32_t ik = k < nrec ? i0 + k : i0;
+        Rec<real>::load(a.rec, ik, xi[k], yi[k], zi[k], idk, vxi[k], vyi[k], vzi[k], flk);
+        cxk[k] = axis_bin(xi[k], I.lo[0], I.inv_w[0], I.n[0]);
+        if (k == 0) {
+            cy = axis_bin(yi[0], I.lo[1], I.inv_w[1], I.n[1]);
+            cz = axis_bin(zi[0], I.lo[2], I.inv_w[2], I.n[2]);
+        }
+    }
+    // The records share a row (y, z bins) and single x-ranges?  Otherwise
+    // search them one at a time.
+    bool joint = true;
+    int xa[G], xb[G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+        int ta[2], tb[2];
+        const int nr = x_ranges(cxk[k], n[0], G_.per[0], ta, tb);
+        xa[k] = ta[0];
+        xb[k] = tb[0];
+        if (k < nrec) {
+            joint &= nr == 1;
+            if (k > 0) {
+                joint &= axis_bin(yi[k], I.lo[1], I.inv_w[1], I.n[1]) == cy;
+                joint &= axis_bin(zi[k], I.lo[2], I.inv_w[2], I.n[2]) == cz;
+            }
+        }
+    }
+    unsigned long long mine[G];
+    int32_t bj[G];
+    real bd2[G];
+    uint32_t bid[G];
+    int32_t seen = 0, nc = 0;
+#pragma unroll
+    for (int k = 0; k < G; ++k) { mine[k] = ~0ull; bj[k] = -1; bd2[k] = real(0); bid[k] = 0; }
+
+    // Bookkeeping of a pair that passed both screening stages (rare).
+    auto hit = [&](int k, int32_t j, uint32_t idj, const Screen<real>& S) {
+        const real d2 = PairTest<real, PER>::finish(G_, S);
+        if (d2 >= real(0)) {
+            ++nc;
+            if constexpr (HALF) {
+                const unsigned long long hi = (unsigned long long)__float_as_uint((float)d2) << 32;
+                atomicMin(a.bkey + j, hi | (uint32_t)(i0 + k));
+                const unsigned long long key = hi | (uint32_t)j;
+                mine[k] = key < mine[k] ? key : mine[k];
+            } else {
+                if (bj[k] < 0 || d2 < bd2[k] || (d2 == bd2[k] && idj < bid[k])) {
+                    bj[k] = j; bd2[k] = d2; bid[k] = idj;
+                }
+            }
+        }
+    };
+    // Tests record j against the lane's records k with take[k] set.
+    auto visit = [&](int32_t j, const bool take[G]) {
+        real xj, yj, zj, vxj, vyj, vzj;
+        uint32_t idj, flj;
+        Rec<real>::load(a.rec, j, xj, yj, zj, idj, vxj, vyj, vzj, flj);
+        Screen<real> S[G];
+        bool p1[G];
+        bool any1 = false;
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            p1[k] = take[k] && PairTest<real, PER>::stage1(G_, xi[k], yi[k], zi[k], vxi[k], vyi[k], vzi[k], xj, yj,
+                                                            zj, vxj, vyj, vzj, S[k]);
+            any1 |= p1[k];
+        }
+        if (!__any(any1)) return;
+        bool p2[G];
+        bool any2 = false;
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            p2[k] = p1[k] && PairTest<real, PER>::stage2(G_, S[k]);
+            any2 |= p2[k];
+        }
+        if (!any2) return;
+#pragma unroll
+        for (int k = 0; k < G; ++k)
+            if (p2[k]) hit(k, j, idj, S[k]);
+    };
+
+    if (joint) {
+        const int own_row = cy + n[1] * cz;
+        const int ua = xa[0];
+        int ub = xb[0];
+#pragma unroll
+        for (int k = 1; k < G; ++k)
+            if (k < nrec) ub = xb[k];
+        for (int rr = 0; rr < 9; ++rr) {
+            int y, z;
+            if (!axis_nb(cz, rr / 3 - 1, n[2], G_.per[2], z)) continue;
+            if (!axis_nb(cy, rr % 3 - 1, n[1], G_.per[1], y)) continue;
+            const int row_idx = y + n[1] * z;
+            if (HALF && row_idx < own_row) continue;
+            const bool own = HALF && row_idx == own_row;
+            const int64_t row = I.cell_off + (int64_t)n[0] * row_idx;
+            int32_t lo[G], hi[G];
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                lo[k] = own ? i0 + k + 1 : (int32_t)(base + a.start[row + xa[k]]);
+                hi[k] = (int32_t)(base + a.start[row + xb[k] + 1]);
+                if (k >= nrec || hi[k] < lo[k]) { lo[k] = 0; hi[k] = 0; }
+                seen += hi[k] > lo[k] ? hi[k] - lo[k] : 0;
+            }
+            const int32_t u0 = own ? i0 + 1 : (int32_t)(base + a.start[row + ua]);
+            const int32_t u1 = (int32_t)(base + a.start[row + ub + 1]);
+            for (int32_t j = u0; j < u1; ++j) {
+                bool take[G];
+#pragma unroll
+                for (int k = 0; k < G; ++k) take[k] = (uint32_t)(j - lo[k]) < (uint32_t)(hi[k] - lo[k]);
+                visit(j, take);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            if (k >= nrec) continue;
+            const int32_t ik = i0 + k;
+            for_neighbourhood<HALF>(a.start, I.cell_off, base, n, G_.per, cxk[k], cy_of(yi[k], I), cz_of(zi[k], I),
+                                    ik, [&](int32_t j0, int32_t j1) {
+                seen += j1 > j0 ? j1 - j0 : 0;
+                for (int32_t j = j0; j < j1; ++j) {
+                    bool take[G];
+#pragma unroll
+                    for (int kk = 0; kk < G; ++kk) take[kk] = kk == k;
+                    visit(j, take);
+                }
+            });
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+        if (k >= nrec) continue;
+        if constexpr (HALF) {
+            if (mine[k] != ~0ull) atomicMin(a.bkey + i0 + k, mine[k]);
         } else {
-            cnt = 3;
-            out[0] = c == 0 ? n - 1 : c - 1;
-            out[1] = c;
-            out[2] = c == n - 1 ? 0 : c + 1;
-        }
-    } else {
-        cnt = 0;
-        for (int d = -1; d <= 1; ++d) {
-            const int v = c + d;
-            if (v >= 0 && v < n) out[cnt++] = v;
+            a.best[i0 + k] = bj[k];
         }
     }
+    // Ordered scans see every pair twice and count the record itself once.
+    tests = HALF ? (double)seen : 0.5 * (double)(seen - nrec);
+    cand = HALF ? 2.0 * (double)nc : (double)nc;
 }
 
-__device__ __forceinline__ void x_ranges(int c, int n, int bc, Ranges& R) {
-    if (bc == TPKMC_BC_PERIODIC && n > 3 && (c == 0 || c == n - 1)) {
-        R.nxr = 2;
-        if (c == 0) { R.xlo[0] = 0; R.xhi[0] = 1; R.xlo[1] = n - 1; R.xhi[1] = n - 1; }
-        else { R.xlo[0] = 0; R.xhi[0] = 0; R.xlo[1] = n - 2; R.xhi[1] = n - 1; }
-    } else if (bc == TPKMC_BC_PERIODIC && n <= 3) {
-        R.nxr = 1; R.xlo[0] = 0; R.xhi[0] = n - 1;
-    } else {
-        R.nxr = 1;
-        R.xlo[0] = c > 0 ? c - 1 : 0;
-        R.xhi[0] = c < n - 1 ? c + 1 : n - 1;
-    }
-}
-
-// The three criteria for the ordered pair (i, j), in the operation order of
-// the reference: chi < 0 within the step, d_min^2 <= D^2.  Returns d_min^2 or
-// a negative value when j is not a candidate.
-template <typename real>
-__device__ __forceinline__ real pair_d2(const Inst<real>& I, real xi, real yi, real zi, real vxi, real vyi,
-                                        real vzi, real xj, real yj, real zj, real vxj, real vyj, real vzj) {
-    real rx = xi - xj, ry = yi - yj, rz = zi - zj;
-    if (I.bc[0] == TPKMC_BC_PERIODIC) { if (rx > I.halfL[0]) rx = rx - I.L[0]; else if (rx < -I.halfL[0]) rx = rx + I.L[0]; }
-    if (I.bc[1] == TPKMC_BC_PERIODIC) { if (ry > I.halfL[1]) ry = ry - I.L[1]; else if (ry < -I.halfL[1]) ry = ry + I.L[1]; }
-    if (I.bc[2] == TPKMC_BC_PERIODIC) { if (rz > I.halfL[2]) rz = rz - I.L[2]; else if (rz < -I.halfL[2]) rz = rz + I.L[2]; }
-    const real ux = vxi - vxj, uy = vyi - vyj, uz = vzi - vzj;
-    const real s0 = (rx * ux + ry * uy) + rz * uz;
-    if (!(s0 < real(0))) return real(-1);
-    const real vv = (ux * ux + uy * uy) + uz * uz;
-    const real s1 = s0 + vv * I.dt;
-    if (!(s1 > real(0))) return real(-1);
-    const real tp = -s0 / vv;
-    const real px = rx + tp * ux, py = ry + tp * uy, pz = rz + tp * uz;
-    const real d2 = (px * px + py * py) + pz * pz;
-    if (!(d2 <= I.D2)) return real(-1);
-    return d2;
-}
-
-// Closest candidate of every live record (one lane per record, ordered
-// pairs: each lane scans the whole neighbourhood, so no atomics and the
-// choice does not depend on the order of records inside a c-bin).
-template <typename real>
+// One table entry (kBlock records) is covered by kBlock / G lanes, split
+// into work-groups of blockDim.x lanes.
+template <typename real, bool HALF, int G>
 __global__ void __launch_bounds__(256) k_search(StepArgs<real> a) {
     __shared__ double lds[16];
-    const int sub = kBlock / blockDim.x;
+    const int lanes = kBlock / G;
+    const int sub = lanes / blockDim.x;
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
     const int entry = lb / sub;
     const Blk bt = a.blk[entry];
     const Inst<real>& I = a.inst[bt.inst];
-    const int64_t i = (int64_t)bt.first + (int64_t)(lb % sub) * blockDim.x + threadIdx.x;
+    const int64_t i0 = (int64_t)bt.first + ((int64_t)(lb % sub) * blockDim.x + threadIdx.x) * G;
     const int64_t base = I.off - a.start[I.cell_off];
     const int64_t live_end = base + a.start[I.cell_off + I.C];
-    double tests = 0.0, cand = 0.0, have = 0.0;
-    if (i < live_end && i < I.off + I.cnt) {
-        real xi, yi, zi, vxi, vyi, vzi;
-        uint32_t idi, fl;
-        Rec<real>::load(a.rec, i, xi, yi, zi, idi, vxi, vyi, vzi, fl);
-        const int cx = axis_bin(xi, I.lo[0], I.inv_w[0], I.n[0]);
-        const int cy = axis_bin(yi, I.lo[1], I.inv_w[1], I.n[1]);
-        const int cz = axis_bin(zi, I.lo[2], I.inv_w[2], I.n[2]);
-        Ranges R;
-        axis_set(cy, I.n[1], I.bc[1], R.ys, R.ny);
-        axis_set(cz, I.n[2], I.bc[2], R.zs, R.nz);
-        x_ranges(cx, I.n[0], I.bc[0], R);
-        int64_t bj = -1;
-        real bd2 = real(0);
-        uint32_t bid = 0;
-        int64_t seen = 0;
-        int ncand = 0;
-        for (int iz = 0; iz < R.nz; ++iz) {
-            for (int iy = 0; iy < R.ny; ++iy) {
-                const int64_t row = I.cell_off + (int64_t)I.n[0] * (R.ys[iy] + (int64_t)I.n[1] * R.zs[iz]);
-                for (int ix = 0; ix < R.nxr; ++ix) {
-                    const int64_t j0 = base + a.start[row + R.xlo[ix]];
-                    const int64_t j1 = base + a.start[row + R.xhi[ix] + 1];
-                    seen += j1 - j0;
-                    for (int64_t j = j0; j < j1; ++j) {
-                        if (j == i) continue;
-                        real xj, yj, zj, vxj, vyj, vzj;
-                        uint32_t idj, flj;
-                        Rec<real>::load(a.rec, j, xj, yj, zj, idj, vxj, vyj, vzj, flj);
-                        const real d2 = pair_d2(I, xi, yi, zi, vxi, vyi, vzi, xj, yj, zj, vxj, vyj, vzj);
-                        if (d2 >= real(0)) {
-                            ++ncand;
-                            if (bj < 0 || d2 < bd2 || (d2 == bd2 && idj < bid)) {
-                                bj = j; bd2 = d2; bid = idj;
-                            }
-                        }
-                    }
-                }
-            }
-        }
-        a.best[i] = (int32_t)bj;
-        tests = (double)(seen - 1);
-        cand = (double)ncand;
-        have = bj >= 0 ? 1.0 : 0.0;
-    } else if (i < I.off + I.cnt) {
-        a.best[i] = -1;
+    const int64_t end = I.off + I.cnt;
+    const bool per = I.bc[0] == TPKMC_BC_PERIODIC || I.bc[1] == TPKMC_BC_PERIODIC || I.bc[2] == TPKMC_BC_PERIODIC;
+    double tests = 0.0, cand = 0.0;
+    const int64_t live_stop = live_end < end ? live_end : end;
+    const int nrec = i0 < live_stop ? (int)(live_stop - i0 < G ? live_stop - i0 : G) : 0;
+    if (nrec > 0) {
+        if (per) search_group<real, HALF, true, G>(a, I, base, (int32_t)i0, nrec, tests, cand);
+        else search_group<real, HALF, false, G>(a, I, base, (int32_t)i0, nrec, tests, cand);
+    }
+    if (!HALF) {
+        for (int k = nrec; k < G; ++k)
+            if (i0 + k < end) a.best[i0 + k] = -1;
     }
     const double t = block_sum(tests, lds);
     const double c = block_sum(cand, lds);
-    const double h = block_sum(have, lds);
     if (threadIdx.x == 0) {
         double* gp = a.gpart + (int64_t)entry * kGPart;
         if (sub == 1) {
-            gp[GP_TESTS2] = t; gp[GP_CAND] = c; gp[GP_HAVEBEST] = h;
+            gp[GP_TESTS2] = 2.0 * t;
+            gp[GP_CAND] = c;
         } else {
-            unsafeAtomicAdd(gp + GP_TESTS2, t);
+            unsafeAtomicAdd(gp + GP_TESTS2, 2.0 * t);
             unsafeAtomicAdd(gp + GP_CAND, c);
-            unsafeAtomicAdd(gp + GP_HAVEBEST, h);
         }
     }
 }
 
 // ---------------------------------------------------------------- 5. move
+// Partner record of record i after the search, or -1.
+template <typename real> __device__ __forceinline__ int32_t partner_of(const StepArgs<real>& a, int64_t i);
+template <> __device__ __forceinline__ int32_t partner_of<double>(const StepArgs<double>& a, int64_t i) {
+    return a.best[i];
+}
+template <> __device__ __forceinline__ int32_t partner_of<float>(const StepArgs<float>& a, int64_t i) {
+    const unsigned long long k = a.bkey[i];
+    return k == ~0ull ? -1 : (int32_t)(uint32_t)k;
+}
+
+// Work-group table of o-bin sums, flushed with one atomic per value per bin.
+constexpr int kSlots = 128;
+struct MomentTable {
+    int key[kSlots];
+    double val[kSlots][TPKMC_MOMENT_STRIDE];
+};
+
+__device__ __forceinline__ int table_slot(MomentTable& T, int ob) {
+    int h = (ob * 0x9E3779B1u) >> 25;  // 7 bits
+    for (int probe = 0; probe < kSlots; ++probe) {
+        const int s = (h + probe) & (kSlots - 1);
+        const int cur = T.key[s];
+        if (cur == ob) return s;
+        if (cur == -1) {
+            const int prev = atomicCAS(&T.key[s], -1, ob);
+            if (prev == -1 || prev == ob) return s;
+        }
+    }
+    return -1;
+}
+
 // Unambiguous pairs (each the other's closest candidate) scatter; every
 // particle moves and meets the walls; o-bin moments and global sums.
 template <typename real>
 __global__ void __launch_bounds__(kBlock) k_move(StepArgs<real> a) {
-    __shared__ double lds[16];
+    __shared__ double red[16 * 11];
+    __shared__ MomentTable tab;
     const Blk bt = a.blk[blockIdx.x];
     const Inst<real>& I = a.inst[bt.inst];
     const int64_t i = (int64_t)bt.first + threadIdx.x;
     const bool in = i < I.off + I.cnt;
     const bool reorder = (I.flags & TPKMC_ALLOW_REORDER) != 0;
-    double gpx = 0, gpy = 0, gpz = 0, gek = 0, gvm = 0, gvir = 0, gm = 0, galive = 0, gpairs = 0, gabs = 0;
+    if (a.moments) {
+        for (int t = threadIdx.x; t < kSlots; t += blockDim.x) {
+            tab.key[t] = -1;
+            for (int k = 0; k < TPKMC_MOMENT_STRIDE; ++k) tab.val[t][k] = 0.0;
+        }
+        __syncthreads();
+    }
+    double gpx = 0, gpy = 0, gpz = 0, gek = 0, gvm = 0, gvir = 0, gm = 0, galive = 0, gpairs = 0, gabs = 0, ghave = 0;
     bool emit = false;
     uint32_t emit_a = 0, emit_b = 0;
     if (in) {
@@ -391,8 +712,9 @@ __global__ void __launch_bounds__(kBlock) k_move(StepArgs<real> a) {
             }
         } else {
             const real dt = I.dt;
-            const int32_t j = a.best[i];
-            const bool mutual = j >= 0 && a.best[j] == (int32_t)i;
+            const int32_t j = partner_of<real>(a, i);
+            const bool mutual = j >= 0 && partner_of<real>(a, j) == (int32_t)i;
+            ghave = j >= 0 ? 1.0 : 0.0;
             real nx = x, ny = y, nz = z, nvx = vx, nvy = vy, nvz = vz;
             double virx = 0, viry = 0, virz = 0;
             if (mutual) {
@@ -406,9 +728,9 @@ __global__ void __launch_bounds__(kBlock) k_move(StepArgs<real> a) {
                 const real vxA = isA ? vx : vxj, vyA = isA ? vy : vyj, vzA = isA ? vz : vzj;
                 const real vxB = isA ? vxj : vx, vyB = isA ? vyj : vy, vzB = isA ? vzj : vz;
                 real rx = xA - xB, ry = yA - yB, rz = zA - zB;
-                if (I.bc[0] == TPKMC_BC_PERIODIC) { if (rx > I.halfL[0]) rx = rx - I.L[0]; else if (rx < -I.halfL[0]) rx = rx + I.L[0]; }
-                if (I.bc[1] == TPKMC_BC_PERIODIC) { if (ry > I.halfL[1]) ry = ry - I.L[1]; else if (ry < -I.halfL[1]) ry = ry + I.L[1]; }
-                if (I.bc[2] == TPKMC_BC_PERIODIC) { if (rz > I.halfL[2]) rz = rz - I.L[2]; else if (rz < -I.halfL[2]) rz = rz + I.L[2]; }
+                if (I.bc[0] == TPKMC_BC_PERIODIC) rx = min_image(rx, I.L[0], I.halfL[0]);
+                if (I.bc[1] == TPKMC_BC_PERIODIC) ry = min_image(ry, I.L[1], I.halfL[1]);
+                if (I.bc[2] == TPKMC_BC_PERIODIC) rz = min_image(rz, I.L[2], I.halfL[2]);
                 const real ux = vxA - vxB, uy = vyA - vyB, uz = vzA - vzB;
                 const real s0 = (rx * ux + ry * uy) + rz * uz;
                 const real vv = (ux * ux + uy * uy) + uz * uz;
@@ -485,21 +807,17 @@ __global__ void __launch_bounds__(kBlock) k_move(StepArgs<real> a) {
                     const int by = axis_bin(ny, I.lo[1], I.inv_wo[1], I.no[1]);
                     const int bz = axis_bin(nz, I.lo[2], I.inv_wo[2], I.no[2]);
                     const int64_t ob = I.obin_off + bx + (int64_t)I.no[0] * (by + (int64_t)I.no[1] * bz);
-                    double* M = a.moments + ob * TPKMC_MOMENT_STRIDE;
                     const double* S = a.shift + ob * 3;
                     const double ex = dvx - S[0], ey = dvy - S[1], ez = dvz - S[2];
-                    unsafeAtomicAdd(M + 0, 1.0);
-                    unsafeAtomicAdd(M + 1, m * ex);
-                    unsafeAtomicAdd(M + 2, m * ey);
-                    unsafeAtomicAdd(M + 3, m * ez);
-                    unsafeAtomicAdd(M + 4, m * ex * ex);
-                    unsafeAtomicAdd(M + 5, m * ey * ey);
-                    unsafeAtomicAdd(M + 6, m * ez * ez);
-                    if (mutual) {
-                        unsafeAtomicAdd(M + 7, virx);
-                        unsafeAtomicAdd(M + 8, viry);
-                        unsafeAtomicAdd(M + 9, virz);
-                        unsafeAtomicAdd(M + 10, 1.0);
+                    const double v[TPKMC_MOMENT_STRIDE] = {1.0, m * ex, m * ey, m * ez, m * ex * ex, m * ey * ey,
+                                                           m * ez * ez, virx, viry, virz, mutual ? 1.0 : 0.0};
+                    const int slot = table_slot(tab, (int)ob);
+                    const int nval = mutual ? TPKMC_MOMENT_STRIDE : 7;
+                    if (slot >= 0) {
+                        for (int k = 0; k < nval; ++k) unsafeAtomicAdd(&tab.val[slot][k], v[k]);
+                    } else {
+                        double* M = a.moments + ob * TPKMC_MOMENT_STRIDE;
+                        for (int k = 0; k < nval; ++k) unsafeAtomicAdd(M + k, v[k]);
                     }
                 }
             }
@@ -523,20 +841,23 @@ __global__ void __launch_bounds__(kBlock) k_move(StepArgs<real> a) {
             }
         }
     }
+    if (a.moments) {
+        __syncthreads();
+        for (int t = threadIdx.x; t < kSlots; t += blockDim.x) {
+            const int ob = tab.key[t];
+            if (ob < 0) continue;
+            double* M = a.moments + (int64_t)ob * TPKMC_MOMENT_STRIDE;
+            for (int k = 0; k < TPKMC_MOMENT_STRIDE; ++k)
+                if (k < 7 || tab.val[t][k] != 0.0) unsafeAtomicAdd(M + k, tab.val[t][k]);
+        }
+    }
     double* gp = a.gpart + (int64_t)blockIdx.x * kGPart;
-    const double r0 = block_sum(gpx, lds);
-    const double r1 = block_sum(gpy, lds);
-    const double r2 = block_sum(gpz, lds);
-    const double r3 = block_sum(gek, lds);
-    const double r4 = block_max(gvm, lds);
-    const double r5 = block_sum(gvir, lds);
-    const double r6 = block_sum(gm, lds);
-    const double r7 = block_sum(galive, lds);
-    const double r8 = block_sum(gpairs, lds);
-    const double r9 = block_sum(gabs, lds);
+    double v[11] = {gpx, gpy, gpz, gek, gvm, gvir, gm, galive, gpairs, gabs, ghave};
+    block_reduce<11>(v, 4, red);
     if (threadIdx.x == 0) {
-        gp[GP_PX] = r0; gp[GP_PY] = r1; gp[GP_PZ] = r2; gp[GP_EKIN] = r3; gp[GP_VMAX2] = r4;
-        gp[GP_VIR] = r5; gp[GP_MASS] = r6; gp[GP_ALIVE] = r7; gp[GP_PAIRS] = r8; gp[GP_ABSORBED] = r9;
+        gp[GP_PX] = v[0]; gp[GP_PY] = v[1]; gp[GP_PZ] = v[2]; gp[GP_EKIN] = v[3]; gp[GP_VMAX2] = v[4];
+        gp[GP_VIR] = v[5]; gp[GP_MASS] = v[6]; gp[GP_ALIVE] = v[7]; gp[GP_PAIRS] = v[8]; gp[GP_ABSORBED] = v[9];
+        gp[GP_HAVEBEST] = v[10];
     }
 }
 
@@ -550,9 +871,14 @@ void launch_scatter(const StepArgs<real>& a, hipStream_t s) {
     hipLaunchKernelGGL(k_scatter<real>, dim3(a.nblk), dim3(kBlock), 0, s, a);
 }
 template <typename real>
-void launch_search(const StepArgs<real>& a, int block, hipStream_t s) {
-    const int sub = kBlock / block;
-    hipLaunchKernelGGL(k_search<real>, dim3(a.nblk * sub), dim3(block), 0, s, a);
+void launch_search(const StepArgs<real>& a, int block, int group, hipStream_t s) {
+    constexpr bool half = std::is_same<real, float>::value;
+    const int lanes = kBlock / group;
+    const int bs = block < lanes ? block : lanes;
+    const unsigned grid = (unsigned)a.nblk * (unsigned)(lanes / bs);
+    if (group == 4) hipLaunchKernelGGL((k_search<real, half, 4>), dim3(grid), dim3(bs), 0, s, a);
+    else if (group == 2) hipLaunchKernelGGL((k_search<real, half, 2>), dim3(grid), dim3(bs), 0, s, a);
+    else hipLaunchKernelGGL((k_search<real, half, 1>), dim3(grid), dim3(bs), 0, s, a);
 }
 template <typename real>
 void launch_move(const StepArgs<real>& a, hipStream_t s) {
