@@ -61,6 +61,21 @@ template <> struct Rec<double> {
     }
 };
 
+// Loads of a record whose index is the same in every lane of the wave: through
+// the constant address space the compiler issues scalar loads (one per wave,
+// into SGPRs); the records are never written while the search runs.
+template <typename real> struct RecU;
+template <typename real> struct RecU {
+    typedef __attribute__((address_space(4))) const real cr;
+    static __device__ __forceinline__ void load(const real* r, int32_t i, real& x, real& y, real& z, uint32_t& id,
+                                                real& vx, real& vy, real& vz) {
+        const cr* p = (const cr*)(r) + 8 * (int64_t)i;
+        x = p[0]; y = p[1]; z = p[2];
+        id = Rec<real>::to_u32(p[3]);
+        vx = p[4]; vy = p[5]; vz = p[6];
+    }
+};
+
 // ---------------------------------------------------------------- helpers
 // Bin along one axis: floor((x - lo) * n / L) clamped into [0, n - 1].
 template <typename real>
@@ -403,6 +418,16 @@ __device__ __forceinline__ int x_ranges(int cx, int n, bool periodic, int xa[2],
 }
 
 template <typename real>
+__device__ __forceinline__ int x_lo_of(int32_t f, const StepArgs<real>& a, const Inst<real>& I, int n0, bool per0) {
+    real x, y, z, vx, vy, vz;
+    uint32_t id;
+    RecU<real>::load(a.rec, f, x, y, z, id, vx, vy, vz);
+    int xa[2], xb[2];
+    x_ranges(axis_bin(x, I.lo[0], I.inv_w[0], I.n[0]), n0, per0, xa, xb);
+    return xa[0];
+}
+
+template <typename real>
 __device__ __forceinline__ int cy_of(real y, const Inst<real>& I) { return axis_bin(y, I.lo[1], I.inv_w[1], I.n[1]); }
 template <typename real>
 __device__ __forceinline__ int cz_of(real z, const Inst<real>& I) { return axis_bin(z, I.lo[2], I.inv_w[2], I.n[2]); }
@@ -450,9 +475,10 @@ __device__ __forceinline__ void for_neighbourhood(const int32_t* start, int64_t 
 // Ordered (FP64): each record scans its whole neighbourhood and keeps the
 // smallest d_min^2, ties to the lower id, with the reference's arithmetic, so
 // the choice does not depend on the order of records inside a bin.
-template <typename real, bool HALF, bool PER, int G>
+template <typename real, bool HALF, bool PER, int G, bool UNIFORM>
 __device__ __forceinline__ void search_group(const StepArgs<real>& a, const Inst<real>& I, int64_t base,
-                                             int32_t i0, int nrec, double& tests, double& cand) {
+                                             int32_t i0, int nrec, int32_t wave_first, int wave_ub,
+                                             double& tests, double& cand) {
     const Geo<real> G_(I);
     const int n[3] = {I.n[0], I.n[1], I.n[2]};
     real xi[G], yi[G], zi[G], vxi[G], vyi[G], vzi[G];
@@ -468,6 +494,11 @@ __device__ __forceinline__ void search_group(const StepArgs<real>& a, const Inst
             cy = axis_bin(yi[0], I.lo[1], I.inv_w[1], I.n[1]);
             cz = axis_bin(zi[0], I.lo[2], I.inv_w[2], I.n[2]);
         }
+    }
+    if constexpr (UNIFORM) {
+        // Same row for the whole wave (checked by the caller).
+        cy = __builtin_amdgcn_readfirstlane(cy);
+        cz = __builtin_amdgcn_readfirstlane(cz);
     }
     // The records share a row (y, z bins) and single x-ranges?  Otherwise
     // search them one at a time.
@@ -515,8 +546,13 @@ __device__ __forceinline__ void search_group(const StepArgs<real>& a, const Inst
     // Tests record j against the lane's records k with take[k] set.
     auto visit = [&](int32_t j, const bool take[G]) {
         real xj, yj, zj, vxj, vyj, vzj;
-        uint32_t idj, flj;
-        Rec<real>::load(a.rec, j, xj, yj, zj, idj, vxj, vyj, vzj, flj);
+        uint32_t idj;
+        if constexpr (UNIFORM) {
+            RecU<real>::load(a.rec, j, xj, yj, zj, idj, vxj, vyj, vzj);
+        } else {
+            uint32_t flj;
+            Rec<real>::load(a.rec, j, xj, yj, zj, idj, vxj, vyj, vzj, flj);
+        }
         Screen<real> S[G];
         bool p1[G];
         bool any1 = false;
@@ -540,13 +576,17 @@ __device__ __forceinline__ void search_group(const StepArgs<real>& a, const Inst
             if (p2[k]) hit(k, j, idj, S[k]);
     };
 
-    if (joint) {
+    if (UNIFORM || joint) {
+        // UNIFORM: every lane of the wave shares the row and walks the union
+        // of the wave's ranges (first record's lower end, wave_ub upper end)
+        // in lock-step, so j is the same in all lanes.
         const int own_row = cy + n[1] * cz;
-        const int ua = xa[0];
+        const int ua = UNIFORM ? __builtin_amdgcn_readfirstlane(x_lo_of(wave_first, a, I, n[0], G_.per[0])) : xa[0];
         int ub = xb[0];
 #pragma unroll
         for (int k = 1; k < G; ++k)
             if (k < nrec) ub = xb[k];
+        if (UNIFORM) ub = wave_ub;
         for (int rr = 0; rr < 9; ++rr) {
             int y, z;
             if (!axis_nb(cz, rr / 3 - 1, n[2], G_.per[2], z)) continue;
@@ -563,8 +603,12 @@ __device__ __forceinline__ void search_group(const StepArgs<real>& a, const Inst
                 if (k >= nrec || hi[k] < lo[k]) { lo[k] = 0; hi[k] = 0; }
                 seen += hi[k] > lo[k] ? hi[k] - lo[k] : 0;
             }
-            const int32_t u0 = own ? i0 + 1 : (int32_t)(base + a.start[row + ua]);
-            const int32_t u1 = (int32_t)(base + a.start[row + ub + 1]);
+            int32_t u0 = own ? (UNIFORM ? wave_first : i0) + 1 : (int32_t)(base + a.start[row + ua]);
+            int32_t u1 = (int32_t)(base + a.start[row + ub + 1]);
+            if constexpr (UNIFORM) {
+                u0 = __builtin_amdgcn_readfirstlane(u0);
+                u1 = __builtin_amdgcn_readfirstlane(u1);
+            }
             for (int32_t j = u0; j < u1; ++j) {
                 bool take[G];
 #pragma unroll
@@ -622,9 +666,41 @@ __global__ void __launch_bounds__(256) k_search(StepArgs<real> a) {
     double tests = 0.0, cand = 0.0;
     const int64_t live_stop = live_end < end ? live_end : end;
     const int nrec = i0 < live_stop ? (int)(live_stop - i0 < G ? live_stop - i0 : G) : 0;
-    if (nrec > 0) {
-        if (per) search_group<real, HALF, true, G>(a, I, base, (int32_t)i0, nrec, tests, cand);
-        else search_group<real, HALF, false, G>(a, I, base, (int32_t)i0, nrec, tests, cand);
+    // Wave-uniform mode when the wave's live records lie in at most two
+    // neighbouring bins of one row (dense bins): decided on the first and
+    // last live record, so the branch is uniform.
+    const uint64_t live = __ballot(nrec > 0);
+    bool uni = false;
+    int32_t wfirst = 0;
+    int wub = 0;
+    if (live) {
+        const int fl = __ffsll((long long)live) - 1;
+        const int ll = 63 - __clzll((long long)live);
+        wfirst = __builtin_amdgcn_readlane((int32_t)i0, fl);
+        const int32_t wlast = __builtin_amdgcn_readlane((int32_t)(i0 + nrec - 1), ll);
+        real xf, yf, zf, vxf, vyf, vzf, xl, yl, zl, vxl, vyl, vzl;
+        uint32_t idf, idl;
+        RecU<real>::load(a.rec, wfirst, xf, yf, zf, idf, vxf, vyf, vzf);
+        RecU<real>::load(a.rec, wlast, xl, yl, zl, idl, vxl, vyl, vzl);
+        const int cxf = axis_bin(xf, I.lo[0], I.inv_w[0], I.n[0]);
+        const int cxl = axis_bin(xl, I.lo[0], I.inv_w[0], I.n[0]);
+        const bool per0 = I.bc[0] == TPKMC_BC_PERIODIC;
+        int xa[2], xb[2];
+        const int nrf = x_ranges(cxf, I.n[0], per0, xa, xb);
+        const int nrl = x_ranges(cxl, I.n[0], per0, xa, xb);
+        wub = xb[0];
+        uni = nrf == 1 && nrl == 1 && cxl - cxf <= 1 &&
+              axis_bin(yf, I.lo[1], I.inv_w[1], I.n[1]) == axis_bin(yl, I.lo[1], I.inv_w[1], I.n[1]) &&
+              axis_bin(zf, I.lo[2], I.inv_w[2], I.n[2]) == axis_bin(zl, I.lo[2], I.inv_w[2], I.n[2]);
+    }
+    if (uni) {
+        if (nrec > 0) {
+            if (per) search_group<real, HALF, true, G, true>(a, I, base, (int32_t)i0, nrec, wfirst, wub, tests, cand);
+            else search_group<real, HALF, false, G, true>(a, I, base, (int32_t)i0, nrec, wfirst, wub, tests, cand);
+        }
+    } else if (nrec > 0) {
+        if (per) search_group<real, HALF, true, G, false>(a, I, base, (int32_t)i0, nrec, 0, 0, tests, cand);
+        else search_group<real, HALF, false, G, false>(a, I, base, (int32_t)i0, nrec, 0, 0, tests, cand);
     }
     if (!HALF) {
         for (int k = nrec; k < G; ++k)
