@@ -26,10 +26,11 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic work of one unordered pair test: the six coordinate differences
-# and the dot product r.u (3 products, 2 sums) that every pair needs before it
-# can be rejected or accepted.
-FLOP_PER_TEST = 11
+# Algorithmic work of one unordered pair test: criterion 1 (closest approach
+# reached within the step) must be decided for every pair of the
+# neighbourhood -- six coordinate differences, the dot products r.u and |u|^2
+# (3 products + 2 sums each) and s1 = r.u + |u|^2 dt (2 FLOP).
+FLOP_PER_TEST = 18
 PEAK_FLOPS = {"fp32": 157.3e12, "fp64": 78.6e12}
 HBM_PEAK = 8.0e12
 
@@ -118,6 +119,103 @@ def cpu_baseline(w, nthreads):
     return w.n / t, sample
 
 
+def run_batched(args):
+    """64 independent Sod/Noh/Sedov instances (log-uniform sizes and Knudsen
+    numbers) stepped together: FP32 state, one captured HIP graph per run,
+    launch shape from the autotuner; compared with the same instances run one
+    after another as plain FP64 steps with the default launch shape."""
+    import ctypes
+    import torch
+    from paper_1210_8084_amd import tpkmc as T
+    from paper_1210_8084_amd import workloads as W
+    ws = W.batched(n_inst=64, seed=1, scale=args.batch_scale)
+    st = {k: np.concatenate([w.state[k] for w in ws]) for k in ("x", "y", "z", "vx", "vy", "vz", "alive")}
+    ids, specs, off = [], [], 0
+    for w in ws:
+        ids.append(w.state["id"].astype(np.int64) + off)
+        specs.append((off, w.n, w.grid, w.params))
+        off += w.n
+    st["id"] = np.concatenate(ids).astype(np.uint32)
+    ntot = off
+    ncell = sum(T.ncells(w.grid) + 1 for w in ws)
+    nob = sum(T.nobins(w.grid) for w in ws)
+    K, Wm = args.steps, args.warmup
+    stream = torch.cuda.Stream()
+    eng = T.Engine(max_particles=ntot, max_cells=ncell, max_obins=nob, precision=T.FP32, max_instances=len(ws))
+    with torch.cuda.stream(stream):
+        dst = T.to_device(st, T.FP32)
+        out = T.make_outputs(len(ws), nob)
+    torch.cuda.synchronize()
+    eng.autotune(dst, specs, stream=stream)
+    flags = T.ALLOW_REORDER
+    eng.run(dst, specs, Wm, out, flags=flags, stream=stream)
+    torch.cuda.synchronize()
+    # Per-kernel times from one plain batched step with event profiling.
+    eng.profile(True)
+    eng.profile_read()
+    eng.step_batched(dst, [(o, c, g, dict(p, step=p["step"] + Wm)) for o, c, g, p in specs], out, flags=flags,
+                     stream=stream)
+    torch.cuda.synchronize()
+    prof = eng.profile_read()
+    eng.profile(False)
+    tests_one = float(out.host()["counters"][:, T.CNT["tests"]].sum())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    eng.run(dst, [(o, c, g, dict(p, step=p["step"] + Wm + 1)) for o, c, g, p in specs], K, out, flags=flags,
+            stream=stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    c = out.host()["counters"]
+    alive_last = float(c[:, T.CNT["alive"]].sum())
+    value = alive_last * K / elapsed
+    eng.close()
+    del dst
+    torch.cuda.empty_cache()
+    # The same instances one after another, plain FP64 steps.
+    Kp = max(1, args.fp64_steps)
+    t64 = 0.0
+    ps64 = 0.0
+    for w in ws:
+        g, p = w.grid, w.params
+        e = T.Engine(max_particles=w.n, max_cells=T.ncells(g) + 1, max_obins=T.nobins(g), precision=T.FP64)
+        d = T.to_device(w.state, T.FP64)
+        o = T.make_outputs(1, T.nobins(g))
+        e.step(d, g, p, o, stream=stream)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        for k in range(Kp):
+            e.step(d, g, dict(p, step=1 + k), o, stream=stream)
+        torch.cuda.synchronize()
+        t64 += time.perf_counter() - ts
+        ps64 += w.n * Kp
+        e.close()
+        del d
+    torch.cuda.empty_cache()
+    v64 = ps64 / t64
+    search_ms, search_n = prof["search"]
+    achieved = tests_one * FLOP_PER_TEST / (search_ms / 1e3) if search_ms > 0 else 0.0
+    line = {
+        "metric": "particle-steps/s (batched ensemble: 64 Sod/Noh/Sedov instances, FP32 state, one HIP graph)",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1, "steps": K, "warmup": Wm, "ms_per_step": 1e3 * elapsed / K,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded initial states of the paper's test problems)",
+        "config": {"workload": "batched64", "instances": len(ws), "particles": ntot,
+                   "sizes": "log-uniform 5e4-2e6" if args.batch_scale == 1.0 else f"scaled x{args.batch_scale}",
+                   "kn": "log-uniform 1e-3-1e-1", "state_precision": "fp32", "moments": "fp64"},
+        "plain_fp64_sequential": {"value": v64, "unit": "particle-steps/s", "steps_per_instance": Kp},
+        "batched_fp32_over_plain_fp64": value / v64,
+        "roofline": {"kernel": "k_search (closest-partner search)", "bound": "alu",
+                     "achieved": achieved / 1e12, "peak": PEAK_FLOPS["fp32"] / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FLOPS["fp32"], "traffic": None,
+                     "avg_launch_ms": search_ms / max(search_n, 1), "flop_per_pair_test": FLOP_PER_TEST},
+        "phases": {ph: {"ms": round(ms / n, 5)} for ph, (ms, n) in prof.items() if n},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -127,6 +225,8 @@ def main():
     ap.add_argument("--precision", choices=("fp32", "fp64"), default="fp32")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay timing")
+    ap.add_argument("--batch-scale", type=float, default=1.0, help="batched64: scale every instance size")
+    ap.add_argument("--fp64-steps", type=int, default=5, help="batched64: plain FP64 steps per instance")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the run, copy a 1 GiB device buffer 3 times (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -134,6 +234,10 @@ def main():
         print("bench.py measures one GPU only: the collision step is not sharded across GPUs in this "
               "build (see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batched64":
+        run_batched(args)
+        return
 
     import torch
     from paper_1210_8084_amd import tpkmc as T
