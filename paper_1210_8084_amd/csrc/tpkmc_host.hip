@@ -667,7 +667,9 @@ const char* tpkmc_strerror(int code) {
 int tpkmc_create(const tpkmc_config* cfg, tpkmc_handle** out) {
     if (!out) return TPKMC_EINVAL;
     *out = nullptr;
-    if (!cfg || cfg->max_particles < 0 || cfg->max_particles >= ((int64_t)1 << 31) || cfg->max_cells < 1 ||
+    // Records are addressed with 32-bit byte offsets in the FP32 search.
+    const int64_t max_n = cfg && cfg->precision == TPKMC_FP32 ? ((int64_t)1 << 27) : ((int64_t)1 << 31);
+    if (!cfg || cfg->max_particles < 0 || cfg->max_particles >= max_n || cfg->max_cells < 1 ||
         cfg->max_cells >= ((int64_t)1 << 30) || cfg->max_obins < 0 || cfg->max_obins >= ((int64_t)1 << 30) ||
         cfg->max_instances < 1 || cfg->flags != 0 ||
         (cfg->precision != TPKMC_FP64 && cfg->precision != TPKMC_FP32))

@@ -24,6 +24,15 @@ namespace tpkmc {
 template <typename real> struct Rec;
 
 template <> struct Rec<float> {
+    // Position and velocity of record i through a 32-bit byte offset (the
+    // host keeps 32 * records below 2^32).
+    static __device__ __forceinline__ void load6(const float* r, uint32_t i, float& x, float& y, float& z,
+                                                 float& vx, float& vy, float& vz) {
+        const char* b = reinterpret_cast<const char*>(r) + i * 32u;
+        const float4 a = *reinterpret_cast<const float4*>(b);
+        const float4 c = *reinterpret_cast<const float4*>(b + 16);
+        x = a.x; y = a.y; z = a.z; vx = c.x; vy = c.y; vz = c.z;
+    }
     static __device__ __forceinline__ float from_u32(uint32_t v) { return __uint_as_float(v); }
     static __device__ __forceinline__ uint32_t to_u32(float v) { return __float_as_uint(v); }
     static __device__ __forceinline__ void store(float* r, int64_t i, float x, float y, float z, uint32_t id,
@@ -546,9 +555,12 @@ __device__ __forceinline__ void search_group(const StepArgs<real>& a, const Inst
     // Tests record j against the lane's records k with take[k] set.
     auto visit = [&](int32_t j, const bool take[G]) {
         real xj, yj, zj, vxj, vyj, vzj;
-        uint32_t idj;
+        uint32_t idj = 0;
         if constexpr (UNIFORM) {
             RecU<real>::load(a.rec, j, xj, yj, zj, idj, vxj, vyj, vzj);
+        } else if constexpr (HALF) {
+            // FP32 keys carry the record index, not the id: skip that word.
+            Rec<float>::load6(a.rec, (uint32_t)j, xj, yj, zj, vxj, vyj, vzj);
         } else {
             uint32_t flj;
             Rec<real>::load(a.rec, j, xj, yj, zj, idj, vxj, vyj, vzj, flj);
@@ -558,11 +570,12 @@ __device__ __forceinline__ void search_group(const StepArgs<real>& a, const Inst
         bool any1 = false;
 #pragma unroll
         for (int k = 0; k < G; ++k) {
-            p1[k] = take[k] && PairTest<real, PER>::stage1(G_, xi[k], yi[k], zi[k], vxi[k], vyi[k], vzi[k], xj, yj,
-                                                            zj, vxj, vyj, vzj, S[k]);
+            // Evaluated on every lane, masked afterwards: no branch.
+            p1[k] = PairTest<real, PER>::stage1(G_, xi[k], yi[k], zi[k], vxi[k], vyi[k], vzi[k], xj, yj, zj, vxj,
+                                                vyj, vzj, S[k]) & take[k];
             any1 |= p1[k];
         }
-        if (!__any(any1)) return;
+        if (__builtin_amdgcn_ballot_w64(any1) == 0) return;
         bool p2[G];
         bool any2 = false;
 #pragma unroll
