@@ -349,6 +349,7 @@ def main():
         "roofline": {"kernel": "k_search (closest-partner search)", "bound": "alu",
                      "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
+                     "algorithmic_bytes": bytes_per["search"],
                      "avg_launch_ms": search_ms / max(search_n, 1),
                      "flop_per_pair_test": FLOP_PER_TEST},
         "phases": phases,
