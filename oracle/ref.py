@@ -24,8 +24,9 @@ LIB = os.path.join(HERE, "libtpkmc_ref.so")
 
 MODE_BINNED, MODE_BRUTE, MODE_ALL = 0, 1, 2
 CNT = dict(alive=0, pairs=1, tests=2, cand=3, fast=4, nonfinite=5, absorbed=6, have_best=7)
-GLB = dict(px=0, py=1, pz=2, ekin=3, vmax2=4, virial=5, mass=6)
+GLB = dict(px=0, py=1, pz=2, ekin=3, vmax2=4, virial=5, mass=6, dt=7)
 M_STRIDE = 11
+ADAPTIVE_DT = 1  # ref_params.flags: step length from the rule of Sec. 3
 
 
 def build() -> str:
@@ -47,7 +48,7 @@ class Grid(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("sigma", ctypes.c_double), ("mass", ctypes.c_double), ("dt", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("step", ctypes.c_uint64),
-                ("instance", ctypes.c_uint32), ("pad", ctypes.c_uint32)]
+                ("instance", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
 
 
 _lib = None
@@ -79,6 +80,8 @@ def lib():
         L.ref_step_sample.argtypes = ([_P, _P, ctypes.c_int64] + [_P] * 8 +
                                       [ctypes.c_int64, _P, ctypes.c_int, _P, _P, _P])
         L.ref_step_sample.restype = ctypes.c_int
+        L.ref_step_dt.argtypes = [_P, _P, ctypes.c_int64] + [_P] * 7
+        L.ref_step_dt.restype = ctypes.c_double
         L.ref_count_tests.argtypes = [_P, ctypes.c_int64] + [_P] * 7
         L.ref_count_tests.restype = ctypes.c_uint64
         L.ref_step.argtypes = ([_P, _P, ctypes.c_int64] + [_P] * 8 +
@@ -107,6 +110,7 @@ def make_params(p) -> Params:
     P.seed = int(p.get("seed", 0))
     P.step = int(p.get("step", 0))
     P.instance = int(p.get("instance", 0))
+    P.flags = ADAPTIVE_DT if p.get("adaptive_dt") else 0
     return P
 
 
@@ -214,6 +218,18 @@ def step_sample(state, grid, params, sample, nthreads=0):
     if rc:
         raise ValueError(f"ref_step_sample failed ({rc})")
     return out, partner, alive
+
+
+def step_dt(state, grid, params):
+    """Time step a step of this state would use (the adaptive rule of Sec. 3
+    when ``params["adaptive_dt"]``, else ``params["dt"]``)."""
+    n = _check_state(state)
+    G, P = make_grid(grid), make_params(params)
+    ptrs = _state_ptrs(state)
+    dt = lib().ref_step_dt(ctypes.byref(G), ctypes.byref(P), n, *ptrs[:6], ptrs[7])
+    if dt < 0:
+        raise ValueError("ref_step_dt failed")
+    return float(dt)
 
 
 def count_tests(state, grid):

@@ -414,6 +414,46 @@ static int check_common(const derived* G, const ref_grid* g, const ref_params* p
     return 0;
 }
 
+/* Time step of Sec. 3: dt = dx / v_max, so that no particle crosses more
+ * than one c-bin per step; the caller's dt is the upper bound. */
+static double step_dt(const derived* G, const ref_params* p, const view* V)
+{
+    if (!(p->flags & REF_ADAPTIVE_DT)) return p->dt;
+    double dx = 0.0;
+    for (int a = 0; a < 3; ++a)
+        if (G->n[a] > 1 && (dx == 0.0 || G->w[a] < dx)) dx = G->w[a];
+    double vmax2 = 0.0;
+    for (int64_t i = 0; i < V->n; ++i) {
+        if (V->alive && !V->alive[i]) continue;
+        if (!finite6(V, i)) continue;
+        double v2 = (V->vx[i] * V->vx[i] + V->vy[i] * V->vy[i]) + V->vz[i] * V->vz[i];
+        if (v2 > vmax2) vmax2 = v2;
+    }
+    if (dx == 0.0 || vmax2 == 0.0) return p->dt;
+    double t = dx / sqrt(vmax2);
+    return t < p->dt ? t : p->dt;
+}
+
+/* Copy of the parameters with the step's dt filled in. */
+static void with_step_dt(const derived* G, const ref_params* p, const view* V, ref_params* q)
+{
+    *q = *p;
+    q->dt = step_dt(G, p, V);
+}
+
+double ref_step_dt(const ref_grid* g, const ref_params* p, int64_t n,
+                   const double* x, const double* y, const double* z,
+                   const double* vx, const double* vy, const double* vz,
+                   const uint8_t* alive)
+{
+    derived G;
+    if (derive(g, p, &G)) return -1.0;
+    if (n < 0 || (n > 0 && (!x || !y || !z || !vx || !vy || !vz))) return -1.0;
+    static const uint32_t no_id = 0;
+    view V = { n, x, y, z, vx, vy, vz, &no_id, alive };
+    return step_dt(&G, p, &V);
+}
+
 int ref_best(const ref_grid* g, const ref_params* p, int64_t n,
              const double* x, const double* y, const double* z,
              const double* vx, const double* vy, const double* vz,
@@ -425,9 +465,10 @@ int ref_best(const ref_grid* g, const ref_params* p, int64_t n,
     if (check_common(&G, g, p, n, x, y, z, vx, vy, vz, id)) return -1;
     if (mode < 0 || mode > 2 || (n > 0 && (!best || !best_d2))) return -1;
     view V = { n, x, y, z, vx, vy, vz, id, alive };
+    const double dt = step_dt(&G, p, &V);
     bins Bn;
     if (make_bins(&G, g, &V, &Bn)) { free_bins(&Bn); return -2; }
-    search_all(&G, p->dt, &V, &Bn, mode, nthreads, best, best_d2);
+    search_all(&G, dt, &V, &Bn, mode, nthreads, best, best_d2);
     free_bins(&Bn);
     return 0;
 }
@@ -446,6 +487,7 @@ int ref_best_sample(const ref_grid* g, const ref_params* p, int64_t n,
     for (int64_t k = 0; k < ns; ++k)
         if (sample[k] < 0 || sample[k] >= n) return -1;
     view V = { n, x, y, z, vx, vy, vz, id, alive };
+    const double dt = step_dt(&G, p, &V);
     bins Bn;
     if (make_bins(&G, g, &V, &Bn)) { free_bins(&Bn); return -2; }
     int nt = nthreads_or_default(nthreads);
@@ -453,7 +495,7 @@ int ref_best_sample(const ref_grid* g, const ref_params* p, int64_t n,
 #pragma omp parallel for schedule(dynamic, 16) num_threads(nt)
     for (int64_t k = 0; k < ns; ++k) {
         uint64_t nc = 0;
-        best_of(&G, p->dt, &V, &Bn, REF_MODE_BINNED, sample[k], &best[k], &best_d2[k], &nc);
+        best_of(&G, dt, &V, &Bn, REF_MODE_BINNED, sample[k], &best[k], &best_d2[k], &nc);
     }
     free_bins(&Bn);
     return 0;
@@ -573,6 +615,9 @@ int ref_step_sample(const ref_grid* g, const ref_params* p, int64_t n,
     for (int64_t k = 0; k < ns; ++k)
         if (sample[k] < 0 || sample[k] >= n) return -1;
     view V = { n, x, y, z, vx, vy, vz, id, alive };
+    ref_params q;
+    with_step_dt(&G, p, &V, &q);
+    p = &q;
     bins Bn;
     if (make_bins(&G, g, &V, &Bn)) { free_bins(&Bn); return -2; }
     int nt = nthreads_or_default(nthreads);
@@ -635,8 +680,11 @@ int ref_step(const ref_grid* g, const ref_params* p, int64_t n,
     if (mode < 0 || mode > 2 || pair_cap < 0) return -1;
     for (int a = 0; a < 3; ++a)
         if (G.bc[a] == REF_BC_ABSORB && !alive) return -1;
-    const double dt = p->dt, m = p->mass;
     view V = { n, x, y, z, vx, vy, vz, id, alive };
+    ref_params q;
+    with_step_dt(&G, p, &V, &q);
+    p = &q;
+    const double dt = p->dt, m = p->mass;
     uint64_t cnt[8] = { 0 };
 
     size_t nn = (size_t)(n > 0 ? n : 1);
@@ -764,7 +812,7 @@ int ref_step(const ref_grid* g, const ref_params* p, int64_t n,
         globals[REF_G_VMAX2] = vmax2;
         globals[REF_G_VIRIAL] = nval(&gv);
         globals[REF_G_MASS] = nval(&gm);
-        globals[REF_G_RESERVED] = 0.0;
+        globals[REF_G_DT] = dt;
     }
     if (counters) memcpy(counters, cnt, sizeof(cnt));
 

@@ -48,8 +48,17 @@ typedef struct {
     uint64_t seed;          /* Philox key                                     */
     uint64_t step;          /* step number (low 32 bits enter the counter)    */
     uint32_t instance;      /* instance number (< 2^24)                       */
-    uint32_t pad;
+    uint32_t flags;         /* REF_ADAPTIVE_DT or 0                           */
 } ref_params;
+
+/* ref_params.flags.  REF_ADAPTIVE_DT: the step length follows the rule of
+ * Sec. 3, dt = dx / v_max, with v_max the largest speed of the alive,
+ * finite particles at the start of the step and dx the smallest c-bin width
+ * over the axes that have more than one c-bin; params.dt is then an upper
+ * bound (it is also taken when v_max = 0 or no axis has two c-bins).  Full
+ * steps (ref_step, ref_step_sample) and the searches (ref_best,
+ * ref_best_sample) apply it; ref_pair_test uses params.dt as given. */
+enum { REF_ADAPTIVE_DT = 1 };
 
 /* Counters written by ref_step (uint64[8]). */
 enum {
@@ -70,7 +79,7 @@ enum {
     REF_G_VMAX2 = 4,                          /* max |v|^2                     */
     REF_G_VIRIAL = 5,                         /* sum of virial trace terms     */
     REF_G_MASS = 6,                           /* sum m                         */
-    REF_G_RESERVED = 7
+    REF_G_DT = 7                              /* time step the step used       */
 };
 
 /* Per-o-bin moments written by ref_step (double[nobin * 11]). */
@@ -136,6 +145,14 @@ int ref_step_sample(const ref_grid* g, const ref_params* p, int64_t n,
                     const uint32_t* id, const uint8_t* alive,
                     int64_t ns, const int64_t* sample, int nthreads,
                     double* out_state, int64_t* out_partner, uint8_t* out_alive);
+
+/* Time step a step of this state would use: params.dt, or the adaptive
+ * rule above when params.flags has REF_ADAPTIVE_DT.  Negative on bad
+ * arguments. */
+double ref_step_dt(const ref_grid* g, const ref_params* p, int64_t n,
+                   const double* x, const double* y, const double* z,
+                   const double* vx, const double* vy, const double* vz,
+                   const uint8_t* alive);
 
 /* One full collision step, in place, in caller order.
  * pairs (may be NULL): (idA, idB) with idA < idB, at most pair_cap entries.
