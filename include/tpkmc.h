@@ -41,6 +41,8 @@
  *   - Work is enqueued on the caller's HIP stream (hipStream_t passed as
  *     void*, NULL = default stream) and the calls return without waiting.
  *     One handle serves one stream at a time.
+ *   - The time step is the caller's dt, or with TPKMC_ADAPTIVE_DT the
+ *     rule of Sec. 3 (dt = c-bin width / v_max), evaluated on the device.
  *   - Precision is fixed per handle: TPKMC_FP64 takes double particle
  *     arrays and reproduces the CPU oracle's pair decisions bit for bit;
  *     TPKMC_FP32 takes float arrays.  Moments and global sums are FP64 in
@@ -77,9 +79,25 @@ enum { TPKMC_BC_REFLECT = 0, TPKMC_BC_PERIODIC = 1, TPKMC_BC_ABSORB = 2 };
 /* tpkmc_params.flags */
 enum {
     TPKMC_EMIT_PAIRS = 1u,     /* write accepted pairs to outputs.pairs       */
-    TPKMC_ALLOW_REORDER = 2u   /* leave all particle arrays (id and alive
+    TPKMC_ALLOW_REORDER = 2u,  /* leave all particle arrays (id and alive
                                   included) in c-bin order instead of the
                                   caller's order                            */
+    TPKMC_ADAPTIVE_DT = 4u,    /* time step of Sec. 3: dt = dx / v_max, with
+                                  v_max the largest speed of the alive finite
+                                  particles at the start of the step and dx
+                                  the smallest c-bin width over the axes with
+                                  more than one c-bin; params.dt is the upper
+                                  bound (also taken when v_max = 0).  Computed
+                                  on the device, so graph replays adapt too;
+                                  the dt used is globals slot 7.            */
+    TPKMC_PLANAR = 8u          /* two-dimensional gas in the x-y plane (the 2D
+                                  runs of Sec. 4, f = 2): the grid has one
+                                  c-bin along z and the caller gives every
+                                  particle the same z and vz = 0, which the
+                                  step keeps; sigma is then a length, the
+                                  width 2 D of the strip one disk sweeps
+                                  relative to another (D^2 = sigma^2 / 4),
+                                  and directions are isotropic in the plane */
 };
 
 /* Bits of the device status word (sticky until read). */
@@ -105,8 +123,9 @@ enum {
 
 /* Globals (double[8] per instance), over alive finite particles after the
  * step: 0..2 sum m v_a, 3 sum m|v|^2/2, 4 max |v|^2, 5 sum of virial trace
- * terms, 6 sum m, 7 zero. */
-enum { TPKMC_G_PX = 0, TPKMC_G_EKIN = 3, TPKMC_G_VMAX2 = 4, TPKMC_G_VIRIAL = 5, TPKMC_G_MASS = 6 };
+ * terms, 6 sum m, 7 the time step this step used. */
+enum { TPKMC_G_PX = 0, TPKMC_G_EKIN = 3, TPKMC_G_VMAX2 = 4, TPKMC_G_VIRIAL = 5, TPKMC_G_MASS = 6,
+       TPKMC_G_DT = 7 };
 
 /* Per-o-bin moments (double[nobin * 11] per instance, o-bin index
  * bx + nobin[0] * (by + nobin[1] * bz) of the post-step position):
@@ -142,13 +161,16 @@ typedef struct {
 } tpkmc_grid;
 
 typedef struct {
-    double sigma;           /* cross section; D^2 = sigma / pi               */
+    double sigma;           /* cross section; D^2 = sigma / pi (sigma^2 / 4
+                               with TPKMC_PLANAR)                            */
     double mass;            /* particle mass (> 0)                           */
-    double dt;              /* time step (> 0)                               */
+    double dt;              /* time step (> 0); its upper bound with
+                               TPKMC_ADAPTIVE_DT                             */
     uint64_t seed;          /* Philox key                                    */
     uint64_t step;          /* step number (low 32 bits enter the counter)   */
     uint32_t instance;      /* instance number (< 2^24)                      */
-    uint32_t flags;         /* TPKMC_EMIT_PAIRS | TPKMC_ALLOW_REORDER        */
+    uint32_t flags;         /* TPKMC_EMIT_PAIRS | TPKMC_ALLOW_REORDER |
+                               TPKMC_ADAPTIVE_DT | TPKMC_PLANAR              */
 } tpkmc_params;
 
 /* Structure-of-arrays particle state, device pointers, n entries each.
@@ -224,6 +246,21 @@ int tpkmc_run(tpkmc_handle* h, const tpkmc_particles* s,
  * particle state is not modified.  Synchronises the stream. */
 int tpkmc_autotune(tpkmc_handle* h, const tpkmc_particles* s,
                    const tpkmc_instance* inst, int32_t n_inst, void* hip_stream);
+
+/* Partner-search variants.  All give the same pairs, state and counters; they
+ * differ only in how the work is laid out on the GPU:
+ *   TPKMC_SEARCH_LANES: one lane per `group` consecutive c-bin-ordered
+ *     records (group 1, 2 or 4), `block` lanes per work-group (64, 128 or
+ *     256, at most 256 / group);
+ *   TPKMC_SEARCH_CELLS: FP32 handles only; one wave per `group` consecutive
+ *     c-bins (group must be 4), the candidates of a c-bin spread over the
+ *     lanes and its own records streamed through scalar registers; `block`
+ *     lanes per work-group (64, 128 or 256).  Suited to sparse c-bins.
+ * tpkmc_autotune picks among them; tpkmc_set_search fixes one (EINVAL for a
+ * shape outside these lists, EUNSUPPORTED for CELLS on an FP64 handle). */
+enum { TPKMC_SEARCH_LANES = 0, TPKMC_SEARCH_CELLS = 1 };
+int tpkmc_set_search(tpkmc_handle* h, int32_t kind, int32_t group, int32_t block);
+int tpkmc_get_search(tpkmc_handle* h, int32_t* kind, int32_t* group, int32_t* block);
 
 /* Synchronises the handle's last stream, returns the status word in
  * *device_status and clears it. */

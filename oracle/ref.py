@@ -27,6 +27,7 @@ CNT = dict(alive=0, pairs=1, tests=2, cand=3, fast=4, nonfinite=5, absorbed=6, h
 GLB = dict(px=0, py=1, pz=2, ekin=3, vmax2=4, virial=5, mass=6, dt=7)
 M_STRIDE = 11
 ADAPTIVE_DT = 1  # ref_params.flags: step length from the rule of Sec. 3
+PLANAR = 2       # ref_params.flags: two-dimensional gas (x-y plane)
 
 
 def build() -> str:
@@ -66,6 +67,8 @@ def lib():
         L.ref_direction.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32,
                                     ctypes.c_uint32, ctypes.c_uint32, _P]
         L.ref_direction.restype = ctypes.c_int
+        L.ref_direction_planar.argtypes = L.ref_direction.argtypes
+        L.ref_direction_planar.restype = ctypes.c_int
         L.ref_cell_of.argtypes = [_P, ctypes.c_double, ctypes.c_double, ctypes.c_double, _P]
         L.ref_cell_of.restype = ctypes.c_int32
         L.ref_stencil.argtypes = [_P, ctypes.c_int32, _P]
@@ -110,7 +113,7 @@ def make_params(p) -> Params:
     P.seed = int(p.get("seed", 0))
     P.step = int(p.get("step", 0))
     P.instance = int(p.get("instance", 0))
-    P.flags = ADAPTIVE_DT if p.get("adaptive_dt") else 0
+    P.flags = (ADAPTIVE_DT if p.get("adaptive_dt") else 0) | (PLANAR if p.get("planar") else 0)
     return P
 
 
@@ -143,9 +146,10 @@ def philox(ctr, key):
     return out
 
 
-def direction(seed, step, instance, idA, idB):
+def direction(seed, step, instance, idA, idB, planar=False):
     n = np.zeros(3)
-    used = lib().ref_direction(seed, step, instance, idA, idB, _ptr(n))
+    f = lib().ref_direction_planar if planar else lib().ref_direction
+    used = f(seed, step, instance, idA, idB, _ptr(n))
     return n, used
 
 

@@ -93,6 +93,30 @@ int ref_direction(uint64_t seed, uint64_t step, uint32_t instance,
     return 256;
 }
 
+int ref_direction_planar(uint64_t seed, uint64_t step, uint32_t instance,
+                         uint32_t idA, uint32_t idB, double n[3])
+{
+    uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
+    for (uint32_t attempt = 0; attempt < 256u; ++attempt) {
+        uint32_t ctr[4] = { (uint32_t)step, idA, idB, (instance << 8) | attempt };
+        uint32_t w[4];
+        ref_philox4x32_10(ctr, key, w);
+        double x1 = 2.0 * unit_double(w[0], w[1]) - 1.0;
+        double x2 = 2.0 * unit_double(w[2], w[3]) - 1.0;
+        double s = x1 * x1 + x2 * x2;
+        if (s < 1.0 && s > 0.0) {
+            /* The angle of (x1, x2) is uniform; doubling it keeps it uniform
+             * and needs no square root. */
+            n[0] = (x1 * x1 - x2 * x2) / s;
+            n[1] = (2.0 * x1 * x2) / s;
+            n[2] = 0.0;
+            return (int)attempt + 1;
+        }
+    }
+    n[0] = 1.0; n[1] = 0.0; n[2] = 0.0;
+    return 256;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Grid                                                                      */
 /* ------------------------------------------------------------------------ */
@@ -126,8 +150,15 @@ static int derive(const ref_grid* g, const ref_params* p, derived* G)
         if (!(p->sigma >= 0.0) || !(p->dt > 0.0) || !(p->mass > 0.0)) return -1;
         if (p->instance >= (1u << 24)) return -1;
         /* sigma = 4 pi r_eff^2 and d_min <= r_eff,A + r_eff,B = 2 r_eff
-         * (Sec. 2.4), so the largest accepted d_min^2 is sigma / pi. */
-        G->D2 = p->sigma / M_PI;
+         * (Sec. 2.4), so the largest accepted d_min^2 is sigma / pi.  In
+         * the plane the cross section is the length 2 D. */
+        if (p->flags & REF_PLANAR) {
+            if (g->ncell[2] != 1) return -1;
+            double D = 0.5 * p->sigma;
+            G->D2 = D * D;
+        } else {
+            G->D2 = p->sigma / M_PI;
+        }
     } else {
         G->D2 = 0.0;
     }
@@ -545,7 +576,10 @@ static void scatter_pair(const derived* G, const ref_params* p, const view* V, i
     double s0 = (r[0] * u[0] + r[1] * u[1]) + r[2] * u[2];
     double vv = (u[0] * u[0] + u[1] * u[1]) + u[2] * u[2];
     double tp = -s0 / vv;
-    ref_direction(p->seed, p->step, p->instance, V->id[A], V->id[B], nhat);
+    if (p->flags & REF_PLANAR)
+        ref_direction_planar(p->seed, p->step, p->instance, V->id[A], V->id[B], nhat);
+    else
+        ref_direction(p->seed, p->step, p->instance, V->id[A], V->id[B], nhat);
     /* Centre-of-mass frame, equal masses: the relative speed g is kept and
      * the outgoing velocities are opposite along nhat. */
     double gr = sqrt(vv);

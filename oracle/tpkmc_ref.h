@@ -48,7 +48,7 @@ typedef struct {
     uint64_t seed;          /* Philox key                                     */
     uint64_t step;          /* step number (low 32 bits enter the counter)    */
     uint32_t instance;      /* instance number (< 2^24)                       */
-    uint32_t flags;         /* REF_ADAPTIVE_DT or 0                           */
+    uint32_t flags;         /* REF_ADAPTIVE_DT | REF_PLANAR                   */
 } ref_params;
 
 /* ref_params.flags.  REF_ADAPTIVE_DT: the step length follows the rule of
@@ -59,6 +59,16 @@ typedef struct {
  * steps (ref_step, ref_step_sample) and the searches (ref_best,
  * ref_best_sample) apply it; ref_pair_test uses params.dt as given. */
 enum { REF_ADAPTIVE_DT = 1 };
+
+/* ref_params.flags.  REF_PLANAR: a two-dimensional gas (Sec. 4: every test
+ * is also run in 2D, with f = 2 velocity degrees of freedom).  Particles
+ * move in the x-y plane: the grid must have one c-bin along z, and the
+ * caller gives every particle the same z and vz = 0, which the step then
+ * keeps.  The cross section is a length, sigma = 2 D (the width of the strip
+ * a disk of diameter D sweeps relative to another), so D^2 = sigma^2 / 4 in
+ * place of sigma / pi, and the scattering direction is isotropic in the
+ * plane. */
+enum { REF_PLANAR = 2 };
 
 /* Counters written by ref_step (uint64[8]). */
 enum {
@@ -99,6 +109,13 @@ void ref_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
  * returns the number of Philox draws used (1..256). */
 int ref_direction(uint64_t seed, uint64_t step, uint32_t instance,
                   uint32_t idA, uint32_t idB, double n[3]);
+
+/* In-plane isotropic unit vector (n[2] = 0) for the pair, from the same
+ * Philox draws: an accepted point (x1, x2) of the unit disk, 0 < s < 1,
+ * gives the doubled angle n = ((x1^2 - x2^2) / s, 2 x1 x2 / s).  Returns the
+ * number of draws used. */
+int ref_direction_planar(uint64_t seed, uint64_t step, uint32_t instance,
+                         uint32_t idA, uint32_t idB, double n[3]);
 
 /* c-bin of a point (bin indices per axis and flattened index). */
 int32_t ref_cell_of(const ref_grid* g, double x, double y, double z, int32_t c[3]);

@@ -24,7 +24,7 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}", f"-I{INCLUDE}"
 UNITS = {
     "tpkmc_host.hip": ["-ffp-contract=off"],
     "tpkmc_f64.hip": ["-ffp-contract=off"],
-    "tpkmc_f32.hip": ["-ffp-contract=fast"],
+    "tpkmc_f32.hip": ["-ffp-contract=fast-honor-pragmas"],
 }
 
 

@@ -200,7 +200,7 @@ __global__ void __launch_bounds__(256) k_finalize(Inst<real>* inst, const double
         g[4] = tot[GP_VMAX2];
         g[5] = tot[GP_VIR];
         g[6] = tot[GP_MASS];
-        g[7] = 0.0;
+        g[7] = I.dt_d;
     }
     uint32_t st = 0;
     if (tot[GP_NONFINITE] > 0.0) st |= TPKMC_STATUS_NONFINITE;
@@ -260,6 +260,7 @@ struct tpkmc_handle {
     uint32_t* status = nullptr;
     hipStream_t last_stream = nullptr;
     hipStream_t own_stream = nullptr;
+    int search_kind = SEARCH_LANES;
     int search_block = kBlock;
     int search_group = 2;
     bool profiling = false;
@@ -286,6 +287,9 @@ struct Plan {
     int n_inst = 0;
     int64_t ncell_tot = 0, nob_tot = 0, max_nob = 0;
     int nblk = 0;
+    bool adaptive = false;    // some instance takes the adaptive time step
+    bool any_periodic = false;
+    int64_t ncw = 0;          // waves of the c-bin-centric search
     std::vector<Blk> blk;
     std::vector<Chunk> chunks;
     std::vector<char> inst_bytes;
@@ -307,6 +311,9 @@ int make_plan(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* i
     P.blk.clear();
     P.chunks.clear();
     P.n_inst = n_inst;
+    P.adaptive = false;
+    P.any_periodic = false;
+    P.ncw = 0;
     P.ncell_tot = 0;
     P.nob_tot = 0;
     P.max_nob = 0;
@@ -320,16 +327,21 @@ int make_plan(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* i
         if (!(std::isfinite(p.mass) && p.mass > 0.0)) return TPKMC_EINVAL;
         if (!(std::isfinite(p.dt) && p.dt > 0.0)) return TPKMC_EINVAL;
         if (p.instance >= (1u << 24)) return TPKMC_EINVAL;
-        if (p.flags & ~(uint32_t)(TPKMC_EMIT_PAIRS | TPKMC_ALLOW_REORDER)) return TPKMC_EINVAL;
+        if (p.flags & ~(uint32_t)(TPKMC_EMIT_PAIRS | TPKMC_ALLOW_REORDER | TPKMC_ADAPTIVE_DT | TPKMC_PLANAR))
+            return TPKMC_EINVAL;
+        const bool planar = (p.flags & TPKMC_PLANAR) != 0;
+        if (planar && g.ncell[2] != 1) return TPKMC_EINVAL;
         Inst<real>& d = I[k];
         std::memset(&d, 0, sizeof(d));
         int64_t C = 1, B = 1;
+        double dx = 0.0;
         for (int a = 0; a < 3; ++a) {
             if (g.ncell[a] < 1 || g.nobin[a] < 1) return TPKMC_EINVAL;
             if (g.ncell[a] > (1 << 24) || g.nobin[a] > (1 << 24)) return TPKMC_EINVAL;
             if (!(std::isfinite(g.lo[a]) && std::isfinite(g.hi[a]) && g.hi[a] > g.lo[a])) return TPKMC_EINVAL;
             if (g.bc[a] < TPKMC_BC_REFLECT || g.bc[a] > TPKMC_BC_ABSORB) return TPKMC_EINVAL;
             if (g.bc[a] == TPKMC_BC_ABSORB && s->alive == nullptr) return TPKMC_EINVAL;
+            if (g.bc[a] == TPKMC_BC_PERIODIC) P.any_periodic = true;
             C *= g.ncell[a];
             B *= g.nobin[a];
             // Derived grid quantities, in double, in the order of the reference.
@@ -342,6 +354,7 @@ int make_plan(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* i
             d.L[a] = (real)L;
             d.halfL[a] = (real)(0.5 * L);
             d.w[a] = (real)(L / (double)g.ncell[a]);
+            if (g.ncell[a] > 1 && (dx == 0.0 || L / (double)g.ncell[a] < dx)) dx = L / (double)g.ncell[a];
             d.inv_w[a] = (real)((double)g.ncell[a] / L);
             d.inv_wo[a] = (real)((double)g.nobin[a] / L);
         }
@@ -360,10 +373,18 @@ int make_plan(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* i
         d.instance = p.instance;
         d.flags = p.flags;
         d.dt = (real)p.dt;
-        d.D2 = (real)(p.sigma / M_PI);
+        // Largest accepted d_min^2: sigma = pi D^2 in space, sigma = 2 D in
+        // the plane (same expressions as the reference).
+        const double Dp = 0.5 * p.sigma;
+        d.D2 = planar ? (real)(Dp * Dp) : (real)(p.sigma / M_PI);
         d.mass = (real)p.mass;
         d.mass_d = p.mass;
         d.dt_d = p.dt;
+        d.dt_cap = p.dt;
+        d.dx_d = dx;
+        if (p.flags & TPKMC_ADAPTIVE_DT) P.adaptive = true;
+        d.cw0 = P.ncw;
+        if (q.count > 0) P.ncw += (C + kCellsPerWave - 1) / kCellsPerWave;
         d.blk0 = (int32_t)P.blk.size();
         for (int64_t o = 0; o < q.count; o += kBlock) P.blk.push_back({k, (int32_t)(q.offset + o)});
         d.nblk = (int32_t)P.blk.size() - d.blk0;
@@ -437,6 +458,9 @@ StepArgs<real> make_args(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_
     a.bkey = h->bkey;
     a.gpart = h->gpart;
     a.shift = h->shift;
+    a.n_inst = P.n_inst;
+    a.any_periodic = P.any_periodic ? 1 : 0;
+    a.ncw = P.ncw;
     a.pairs = o ? o->pairs : nullptr;
     a.pair_cap = (o && o->pairs) ? o->pair_cap : 0;
     a.pair_count = h->pair_count;
@@ -466,6 +490,7 @@ void enqueue_step(tpkmc_handle* h, const StepArgs<real>& a, const tpkmc_outputs*
     if (P.nblk > 0) {
         PhaseScope ps(h, PH_KEY, s, prof);
         launch_key<real>(a, s);
+        if (P.adaptive) launch_adapt_dt<real>((Inst<real>*)h->inst, h->gpart, P.n_inst, s);
     }
     {
         PhaseScope ps(h, PH_SCAN, s, prof);
@@ -478,7 +503,7 @@ void enqueue_step(tpkmc_handle* h, const StepArgs<real>& a, const tpkmc_outputs*
         }
         {
             PhaseScope ps(h, PH_SEARCH, s, prof);
-            launch_search<real>(a, h->search_block, h->search_group, s);
+            launch_search<real>(a, h->search_kind, h->search_block, h->search_group, s);
         }
         {
             PhaseScope ps(h, PH_MOVE, s, prof);
@@ -594,36 +619,39 @@ int tune_impl(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* i
     hipLaunchKernelGGL(k_clear, dim3(1024), dim3(256), 0, st, h->start, P.ncell_tot + 1, (double*)nullptr,
                        (int64_t)0, h->pair_count);
     launch_key<real>(a, st);
+    if (P.adaptive) launch_adapt_dt<real>((Inst<real>*)h->inst, h->gpart, P.n_inst, st);
     enqueue_scan(h, P.ncell_tot + 1, st);
     launch_scatter<real>(a, st);
     hipEvent_t e0, e1;
     hipEventCreate(&e0);
     hipEventCreate(&e1);
     // Results-neutral launch shapes: records per lane (1, 2, 4) and lanes per
-    // work-group (64, 128, 256).
-    const int groups[3] = {1, 2, 4};
-    const int shapes[3] = {256, 128, 64};
+    // work-group (64, 128, 256); in FP32 also the c-bin-centric search.
+    struct Shape { int kind, group, block; };
+    std::vector<Shape> shapes;
+    for (int grp : {1, 2, 4})
+        for (int bs : {256, 128, 64})
+            if (bs <= kBlock / grp) shapes.push_back({SEARCH_LANES, grp, bs});
+    if (std::is_same<real, float>::value)
+        for (int bs : {256, 128, 64}) shapes.push_back({SEARCH_CELLS, kCellsPerWave, bs});
     float best_ms = 1e30f;
-    int best_shape = kBlock, best_group = 2;
-    for (int grp : groups) {
-        for (int shape : shapes) {
-            if (shape > kBlock / grp) continue;
-            launch_search<real>(a, shape, grp, st);  // warm-up
-            hipEventRecord(e0, st);
-            for (int r = 0; r < 3; ++r) launch_search<real>(a, shape, grp, st);
-            hipEventRecord(e1, st);
-            if (hipEventSynchronize(e1) != hipSuccess) { rc = TPKMC_EHIP; break; }
-            float ms = 0.f;
-            hipEventElapsedTime(&ms, e0, e1);
-            if (ms < best_ms) { best_ms = ms; best_shape = shape; best_group = grp; }
-        }
-        if (rc) break;
+    Shape best{SEARCH_LANES, 2, kBlock};
+    for (const Shape& sh : shapes) {
+        launch_search<real>(a, sh.kind, sh.block, sh.group, st);  // warm-up
+        hipEventRecord(e0, st);
+        for (int r = 0; r < 3; ++r) launch_search<real>(a, sh.kind, sh.block, sh.group, st);
+        hipEventRecord(e1, st);
+        if (hipEventSynchronize(e1) != hipSuccess) { rc = TPKMC_EHIP; break; }
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best_ms) { best_ms = ms; best = sh; }
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     if (rc) return rc;
-    h->search_block = best_shape;
-    h->search_group = best_group;
+    h->search_kind = best.kind;
+    h->search_block = best.block;
+    h->search_group = best.group;
     h->last_stream = st;
     return hipGetLastError() == hipSuccess ? TPKMC_OK : TPKMC_EHIP;
 }
@@ -776,6 +804,32 @@ int tpkmc_autotune(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instan
     hipStream_t st = (hipStream_t)stream;
     return h->precision == TPKMC_FP64 ? tune_impl<double>(h, s, inst, n_inst, st)
                                       : tune_impl<float>(h, s, inst, n_inst, st);
+}
+
+int tpkmc_set_search(tpkmc_handle* h, int32_t kind, int32_t group, int32_t block) {
+    if (!h) return TPKMC_EINVAL;
+    if (block != 64 && block != 128 && block != 256) return TPKMC_EINVAL;
+    if (kind == TPKMC_SEARCH_LANES) {
+        if (group != 1 && group != 2 && group != 4) return TPKMC_EINVAL;
+        if (block > kBlock / group) return TPKMC_EINVAL;
+    } else if (kind == TPKMC_SEARCH_CELLS) {
+        if (group != kCellsPerWave) return TPKMC_EINVAL;
+        if (h->precision != TPKMC_FP32) return TPKMC_EUNSUPPORTED;
+    } else {
+        return TPKMC_EINVAL;
+    }
+    h->search_kind = kind;
+    h->search_group = group;
+    h->search_block = block;
+    return TPKMC_OK;
+}
+
+int tpkmc_get_search(tpkmc_handle* h, int32_t* kind, int32_t* group, int32_t* block) {
+    if (!h || !kind || !group || !block) return TPKMC_EINVAL;
+    *kind = h->search_kind;
+    *group = h->search_group;
+    *block = h->search_block;
+    return TPKMC_OK;
 }
 
 int tpkmc_status(tpkmc_handle* h, int32_t* device_status) {

@@ -18,7 +18,7 @@ constexpr int kWave = 64;
 enum GPart {
     GP_PX = 0, GP_PY, GP_PZ, GP_EKIN, GP_VMAX2, GP_VIR, GP_MASS,
     GP_ALIVE, GP_PAIRS, GP_ABSORBED, GP_TESTS2, GP_CAND, GP_HAVEBEST,
-    GP_FAST, GP_NONFINITE, GP_SPARE, kGPart
+    GP_FAST, GP_NONFINITE, GP_VMAX0, kGPart
 };
 
 // Instance descriptor on the device.  Derived grid quantities are computed
@@ -38,8 +38,16 @@ struct Inst {
     int32_t pad;
     real lo[3], hi[3], L[3], halfL[3], inv_w[3], inv_wo[3], w[3];
     real dt, D2, mass;
-    double mass_d, dt_d;
+    double mass_d, dt_d;      // dt_d: this step's time step (set on the device with ADAPTIVE_DT)
+    double dt_cap, dx_d;      // caller's dt; smallest c-bin width over axes with > 1 c-bin (0: none)
+    int64_t cw0;              // first wave of this instance in the c-bin-centric search
 };
+
+// c-bins per wave of the c-bin-centric search.
+constexpr int kCellsPerWave = 4;
+
+// Search variants (results-neutral; chosen by the autotuner or the caller).
+enum SearchKind { SEARCH_LANES = 0, SEARCH_CELLS = 1 };
 
 // Block table entry: instance index and first particle of the work-group.
 struct Blk {
@@ -75,6 +83,9 @@ struct StepArgs {
     unsigned long long* bkey; // record -> (d_min^2 bits, partner record) (FP32 search)
     double* gpart;            // [nblk][kGPart]
     double* shift;            // per-o-bin velocity shift (3 per o-bin)
+    int32_t n_inst;           // instances of this step
+    int32_t any_periodic;     // some instance has a periodic axis
+    int64_t ncw;              // waves of the c-bin-centric search
     // outputs
     uint32_t* pairs;
     int64_t pair_cap;
@@ -85,7 +96,8 @@ struct StepArgs {
 // Launchers implemented per precision (tpkmc_f32.hip / tpkmc_f64.hip).
 template <typename real> void launch_key(const StepArgs<real>& a, hipStream_t s);
 template <typename real> void launch_scatter(const StepArgs<real>& a, hipStream_t s);
-template <typename real> void launch_search(const StepArgs<real>& a, int block, int group, hipStream_t s);
+template <typename real> void launch_adapt_dt(Inst<real>* inst, const double* gpart, int n_inst, hipStream_t s);
+template <typename real> void launch_search(const StepArgs<real>& a, int kind, int block, int group, hipStream_t s);
 template <typename real> void launch_move(const StepArgs<real>& a, hipStream_t s);
 
 }  // namespace tpkmc

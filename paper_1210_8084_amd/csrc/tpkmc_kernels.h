@@ -172,10 +172,13 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32
     }
 }
 
-// Isotropic unit vector of the pair (idA < idB): Marsaglia's rejection method
-// on two 53-bit uniforms per Philox draw; computed in double in both modes.
+// Isotropic unit vector of the pair (idA < idB) from a point (x1, x2) drawn
+// uniformly in the unit disk by rejection, two 53-bit uniforms per Philox
+// draw; computed in double in both precisions.  In space: Marsaglia's map
+// (2 x1 q, 2 x2 q, 1 - 2 s), q = sqrt(1 - s).  In the plane: the doubled
+// angle ((x1^2 - x2^2) / s, 2 x1 x2 / s, 0), which needs s > 0.
 __device__ __forceinline__ void pair_direction(uint32_t k0, uint32_t k1, uint32_t step, uint32_t instance,
-                                               uint32_t idA, uint32_t idB, double n[3]) {
+                                               uint32_t idA, uint32_t idB, bool planar, double n[3]) {
     for (uint32_t attempt = 0; attempt < 256u; ++attempt) {
         uint32_t c[4] = {step, idA, idB, (instance << 8) | attempt};
         philox4x32_10(c, k0, k1);
@@ -184,7 +187,14 @@ __device__ __forceinline__ void pair_direction(uint32_t k0, uint32_t k1, uint32_
         const double x1 = 2.0 * u1 - 1.0;
         const double x2 = 2.0 * u2 - 1.0;
         const double s = x1 * x1 + x2 * x2;
-        if (s < 1.0) {
+        if (planar) {
+            if (s < 1.0 && s > 0.0) {
+                n[0] = (x1 * x1 - x2 * x2) / s;
+                n[1] = (2.0 * x1 * x2) / s;
+                n[2] = 0.0;
+                return;
+            }
+        } else if (s < 1.0) {
             const double q = sqrt(1.0 - s);
             n[0] = (2.0 * x1) * q;
             n[1] = (2.0 * x2) * q;
@@ -192,7 +202,14 @@ __device__ __forceinline__ void pair_direction(uint32_t k0, uint32_t k1, uint32_
             return;
         }
     }
-    n[0] = 0.0; n[1] = 0.0; n[2] = 1.0;
+    n[0] = planar ? 1.0 : 0.0; n[1] = 0.0; n[2] = planar ? 0.0 : 1.0;
+}
+
+// |v|^2 in double, summed in axis order with every product rounded (the
+// order the time-step rule and the global maximum are defined in).
+__device__ __forceinline__ double speed2(double vx, double vy, double vz) {
+#pragma clang fp contract(off)
+    return (vx * vx + vy * vy) + vz * vz;
 }
 
 // ---------------------------------------------------------------- 1. key
@@ -206,7 +223,9 @@ __global__ void __launch_bounds__(kBlock) k_key(StepArgs<real> a) {
     const Inst<real>& I = a.inst[bt.inst];
     const int64_t p = (int64_t)bt.first + threadIdx.x;
     const bool in = p < I.off + I.cnt;
-    int key = 0, fast = 0, nonfin = 0;
+    const bool adaptive = (I.flags & TPKMC_ADAPTIVE_DT) != 0;
+    int key = 0, nonfin = 0;
+    double v2 = 0.0;
     if (in) {
         const bool alive = a.alive ? a.alive[p] != 0 : true;
         const real x = a.x[p], y = a.y[p], z = a.z[p];
@@ -217,7 +236,7 @@ __global__ void __launch_bounds__(kBlock) k_key(StepArgs<real> a) {
             const int cy = axis_bin(y, I.lo[1], I.inv_w[1], I.n[1]);
             const int cz = axis_bin(z, I.lo[2], I.inv_w[2], I.n[2]);
             key = (int)I.cell_off + cx + I.n[0] * (cy + I.n[1] * cz);
-            fast = (fabs(vx) * I.dt > I.w[0]) || (fabs(vy) * I.dt > I.w[1]) || (fabs(vz) * I.dt > I.w[2]);
+            if (adaptive) v2 = speed2((double)vx, (double)vy, (double)vz);
         } else {
             key = (int)(I.cell_off + I.C);
             nonfin = alive && !fin;
@@ -239,12 +258,13 @@ __global__ void __launch_bounds__(kBlock) k_key(StepArgs<real> a) {
         a.key[p] = key;
         a.rank[p] = base + (lane - seg0);
     }
-    const double nf = block_sum((double)fast, lds);
     const double nn = block_sum((double)nonfin, lds);
+    const double vm = adaptive ? block_max(v2, lds) : 0.0;
     if (threadIdx.x == 0) {
         double* gp = a.gpart + (int64_t)blockIdx.x * kGPart;
-        gp[GP_FAST] = nf;
         gp[GP_NONFINITE] = nn;
+        gp[GP_VMAX0] = vm;
+        gp[GP_FAST] = 0.0;  // counted by the scatter kernel, once dt is known
         // The search kernel may accumulate into these with atomics.
         gp[GP_TESTS2] = 0.0;
         gp[GP_CAND] = 0.0;
@@ -258,14 +278,24 @@ __global__ void __launch_bounds__(kBlock) k_scatter(StepArgs<real> a) {
     const Blk bt = a.blk[blockIdx.x];
     const Inst<real>& I = a.inst[bt.inst];
     const int64_t p = (int64_t)bt.first + threadIdx.x;
-    if (p >= I.off + I.cnt) return;
-    const int64_t base = I.off - a.start[I.cell_off];
-    const int k = a.key[p];
-    const int64_t dst = base + a.start[k] + a.rank[p];
-    const uint32_t fl = a.alive ? (a.alive[p] != 0) : 1u;
-    Rec<real>::store(a.rec, dst, a.x[p], a.y[p], a.z[p], a.id[p], a.vx[p], a.vy[p], a.vz[p], fl);
-    a.src[dst] = (int32_t)p;
-    if (a.bkey) a.bkey[dst] = ~0ull;
+    bool fast = false;
+    if (p < I.off + I.cnt) {
+        const int64_t base = I.off - a.start[I.cell_off];
+        const int k = a.key[p];
+        const int64_t dst = base + a.start[k] + a.rank[p];
+        const uint32_t fl = a.alive ? (a.alive[p] != 0) : 1u;
+        const real x = a.x[p], y = a.y[p], z = a.z[p], vx = a.vx[p], vy = a.vy[p], vz = a.vz[p];
+        Rec<real>::store(a.rec, dst, x, y, z, a.id[p], vx, vy, vz, fl);
+        a.src[dst] = (int32_t)p;
+        if (a.bkey) a.bkey[dst] = ~0ull;
+        // Diagnostic: a particle faster than one c-bin per step on some axis.
+        const real dt = I.dt;
+        fast = fl && finite3(x, y, z) && finite3(vx, vy, vz) &&
+               (fabs(vx) * dt > I.w[0] || fabs(vy) * dt > I.w[1] || fabs(vz) * dt > I.w[2]);
+    }
+    const uint64_t fm = __ballot(fast);
+    if (fm && (threadIdx.x & 63) == __ffsll((long long)fm) - 1)
+        atomicAdd(a.gpart + (int64_t)blockIdx.x * kGPart + GP_FAST, (double)__popcll(fm));
 }
 
 // ---------------------------------------------------------------- 4. search
@@ -733,6 +763,134 @@ __global__ void __launch_bounds__(256) k_search(StepArgs<real> a) {
     }
 }
 
+// c-bin-centric half search (FP32).  One wave takes kCellsPerWave
+// consecutive c-bins.  For a c-bin c, the candidates are the records of the
+// neighbour c-bins of index >= c: up to two x-ranges in each of up to nine
+// rows.  They are flattened into one list and dealt to the 64 lanes, one
+// chunk of 64 at a time, and each lane keeps its candidate in registers.  The
+// c-bin's own records then stream through scalar registers, one at a time.
+// Every pair (i, j) with j > i in that list is tested once, the own c-bin
+// included, which is exactly the pair set, orientation and arithmetic of the
+// lane-per-record search.  Keys and counts therefore come out identical.
+// Compared with that search, this one has no per-pair address arithmetic, no
+// per-lane loop bounds (the loop is over the uniform i), and each candidate
+// record is loaded once per c-bin instead of once per record.
+template <bool PER>
+__device__ __forceinline__ void search_cell(const StepArgs<float>& a, const Inst<float>& I, const Geo<float>& G_,
+                                            int64_t base, int c, int lane, int32_t* rpre, int32_t* rdel,
+                                            uint64_t& tests, uint32_t& ncand) {
+    typedef __attribute__((address_space(4))) const int32_t cint;
+    const cint* st = (const cint*)a.start;
+    const int nx = I.n[0], ny = I.n[1], nz = I.n[2];
+    const int cx = c % nx, rest = c / nx;
+    const int cy = rest % ny, cz = rest / ny;
+    const int64_t co = I.cell_off;
+    const int32_t i_lo = (int32_t)(base + st[co + c]);
+    const int32_t i_hi = (int32_t)(base + st[co + c + 1]);
+    if (i_hi <= i_lo) return;
+    int xa[2], xb[2];
+    const int nxr = x_ranges(cx, nx, G_.per[0], xa, xb);
+    const int own_row = cy + ny * cz;
+    // Candidate list: range r holds list positions [rpre[r], rpre[r+1]) and
+    // record index = list position + rdel[r] (kept in this wave's LDS).
+    int nr = 0;
+    int32_t tot = 0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        int y = 0, z = 0;
+        bool ok = axis_nb(cz, k / 3 - 1, nz, G_.per[2], z);
+        ok = ok && axis_nb(cy, k % 3 - 1, ny, G_.per[1], y);
+        const int row_idx = y + ny * z;
+        ok = ok && row_idx >= own_row;
+        const bool own = row_idx == own_row;
+        const int64_t row = co + (int64_t)nx * row_idx;
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            bool use = ok && r < nxr;
+            int x0 = xa[r];
+            if (own) {
+                if (r == 0) x0 = cx;               // the own c-bin and those after it
+                else use = use && xa[r] > cx;      // a wrapped range above cx
+            }
+            if (use) {
+                const int32_t j0 = (int32_t)(base + st[row + x0]);
+                const int32_t j1 = (int32_t)(base + st[row + xb[r] + 1]);
+                if (j1 > j0) {
+                    if (lane == 0) { rpre[nr] = tot; rdel[nr] = j0 - tot; }
+                    ++nr;
+                    tot += j1 - j0;
+                }
+            }
+        }
+    }
+    // Pairs met: every own record i with every listed j > i.
+    const uint64_t m = (uint64_t)(i_hi - i_lo);
+    tests += m * (uint64_t)tot - m * (m + 1u) / 2u;
+    __builtin_amdgcn_wave_barrier();
+    for (int32_t q = 0; q < tot; q += 64) {
+        const int32_t f = q + lane;
+        const bool valid = f < tot;
+        int32_t j = i_lo;
+        for (int r = 0; r < nr; ++r)
+            if (f >= rpre[r]) j = f + rdel[r];
+        if (!valid) j = i_lo;
+        float xj, yj, zj, vxj, vyj, vzj;
+        Rec<float>::load6(a.rec, (uint32_t)j, xj, yj, zj, vxj, vyj, vzj);
+        for (int32_t i = i_lo; i < i_hi; ++i) {
+            float xi, yi, zi, vxi, vyi, vzi;
+            uint32_t idi;
+            RecU<float>::load(a.rec, i, xi, yi, zi, idi, vxi, vyi, vzi);
+            Screen<float> S;
+            const bool s1 = PairTest<float, PER>::stage1(G_, xi, yi, zi, vxi, vyi, vzi, xj, yj, zj, vxj, vyj, vzj, S);
+            const bool p1 = s1 && valid && j > i;
+            if (__builtin_amdgcn_ballot_w64(p1) == 0) continue;
+            const bool p2 = p1 && PairTest<float, PER>::stage2(G_, S);
+            bool hit = false;
+            if (p2) {
+                const float d2 = PairTest<float, PER>::finish(G_, S);
+                if (d2 >= 0.0f) {
+                    hit = true;
+                    const unsigned long long hk = (unsigned long long)__float_as_uint(d2) << 32;
+                    atomicMin(a.bkey + j, hk | (uint32_t)i);
+                    atomicMin(a.bkey + i, hk | (uint32_t)j);
+                }
+            }
+            ncand += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(hit));
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <bool PER>
+__global__ void __launch_bounds__(256) k_search_cells(StepArgs<float> a) {
+    const int wpb = (int)(blockDim.x >> 6);
+    const int wib = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int64_t w = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * wpb + wib;
+    if (w >= a.ncw) return;
+    int lo = 0, hi = a.n_inst - 1;  // the last instance with cw0 <= w
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.inst[mid].cw0 <= w) lo = mid; else hi = mid - 1;
+    }
+    const Inst<float>& I = a.inst[lo];
+    const Geo<float> G_(I);
+    const int64_t base = I.off - a.start[I.cell_off];
+    const int c0 = (int)(w - I.cw0) * kCellsPerWave;
+    const int c1 = c0 + kCellsPerWave < I.C ? c0 + kCellsPerWave : I.C;
+    __shared__ int32_t rpre[4][18], rdel[4][18];
+    uint64_t tests = 0;
+    uint32_t ncand = 0;
+    for (int c = c0; c < c1; ++c)
+        search_cell<PER>(a, I, G_, base, c, lane, rpre[wib], rdel[wib], tests, ncand);
+    if (lane == 0 && (tests | ncand)) {
+        // Spread over the instance's partial slots (summed per instance).
+        double* gp = a.gpart + (int64_t)(I.blk0 + (int)(w % I.nblk)) * kGPart;
+        unsafeAtomicAdd(gp + GP_TESTS2, 2.0 * (double)tests);
+        unsafeAtomicAdd(gp + GP_CAND, 2.0 * (double)ncand);
+    }
+}
+
 // ---------------------------------------------------------------- 5. move
 // Partner record of record i after the search, or -1.
 template <typename real> __device__ __forceinline__ int32_t partner_of(const StepArgs<real>& a, int64_t i);
@@ -825,7 +983,8 @@ __global__ void __launch_bounds__(kBlock) k_move(StepArgs<real> a) {
                 const real vv = (ux * ux + uy * uy) + uz * uz;
                 const real tp = -s0 / vv;
                 double nh[3];
-                pair_direction(I.seed_lo, I.seed_hi, I.step_lo, I.instance, isA ? idi : idj, isA ? idj : idi, nh);
+                pair_direction(I.seed_lo, I.seed_hi, I.step_lo, I.instance, isA ? idi : idj, isA ? idj : idi,
+                               (I.flags & TPKMC_PLANAR) != 0, nh);
                 // Equal masses: centre-of-mass velocity kept, relative speed g
                 // kept, outgoing directions opposite along nhat.
                 const real g = sqrt(vv);
@@ -950,6 +1109,28 @@ __global__ void __launch_bounds__(kBlock) k_move(StepArgs<real> a) {
     }
 }
 
+// Time step of Sec. 3 per instance, dt = dx / v_max, from the work-group
+// maxima of |v|^2 left by the key kernel; the caller's dt is the cap.  One
+// work-group per instance; writes the instance's dt for the later kernels.
+template <typename real>
+__global__ void __launch_bounds__(256) k_adapt_dt(Inst<real>* inst, const double* gpart) {
+    __shared__ double lds[16];
+    Inst<real>& I = inst[blockIdx.x];
+    if (!(I.flags & TPKMC_ADAPTIVE_DT)) return;
+    double v = 0.0;
+    for (int b = threadIdx.x; b < I.nblk; b += blockDim.x)
+        v = fmax(v, gpart[(int64_t)(I.blk0 + b) * kGPart + GP_VMAX0]);
+    const double vmax2 = block_max(v, lds);
+    if (threadIdx.x != 0) return;
+    double dt = I.dt_cap;
+    if (I.dx_d > 0.0 && vmax2 > 0.0) {
+        const double t = I.dx_d / sqrt(vmax2);
+        if (t < dt) dt = t;
+    }
+    I.dt_d = dt;
+    I.dt = (real)dt;
+}
+
 // ---------------------------------------------------------------- launchers
 template <typename real>
 void launch_key(const StepArgs<real>& a, hipStream_t s) {
@@ -960,8 +1141,23 @@ void launch_scatter(const StepArgs<real>& a, hipStream_t s) {
     hipLaunchKernelGGL(k_scatter<real>, dim3(a.nblk), dim3(kBlock), 0, s, a);
 }
 template <typename real>
-void launch_search(const StepArgs<real>& a, int block, int group, hipStream_t s) {
+void launch_adapt_dt(Inst<real>* inst, const double* gpart, int n_inst, hipStream_t s) {
+    hipLaunchKernelGGL(k_adapt_dt<real>, dim3(n_inst), dim3(256), 0, s, inst, gpart);
+}
+template <typename real>
+void launch_search(const StepArgs<real>& a, int kind, int block, int group, hipStream_t s) {
     constexpr bool half = std::is_same<real, float>::value;
+    if constexpr (half) {
+        if (kind == SEARCH_CELLS) {
+            if (a.ncw <= 0) return;
+            const int wpb = block / kWave;
+            const unsigned grid = (unsigned)((a.ncw + wpb - 1) / wpb);
+            // Any periodic axis in the batch selects the minimum-image variant.
+            if (a.any_periodic) hipLaunchKernelGGL(k_search_cells<true>, dim3(grid), dim3(block), 0, s, a);
+            else hipLaunchKernelGGL(k_search_cells<false>, dim3(grid), dim3(block), 0, s, a);
+            return;
+        }
+    }
     const int lanes = kBlock / group;
     const int bs = block < lanes ? block : lanes;
     const unsigned grid = (unsigned)a.nblk * (unsigned)(lanes / bs);

@@ -1,10 +1,12 @@
 """Physics validation of the GPU collision step on the paper's shock problems.
 
 Runs the Sod tube (Sec. 4.2), the cylindrical Noh implosion (Sec. 4.3) and
-the Sedov blast (Sec. 4.4) on the GPU library, in FP32 and FP64, and reports
-L1 errors of the number density and pressure profiles against the analytic
-solutions, the FP32-FP64 difference of those errors, and the conservation of
-particles, momentum and energy over the run.
+the Sedov blast (Sec. 4.4) on the GPU library, in FP32 and FP64, as
+three-dimensional gases (f = 3, gamma = 5/3) and as two-dimensional ones
+(f = 2, gamma = 2, the paper's 2D runs), and reports L1 errors of the number
+density and pressure profiles against the analytic solutions, the FP32-FP64
+difference of those errors, and the conservation of particles, momentum and
+energy over the run.
 
 The analytic solutions and the CPU reference live in ``oracle/`` (test
 infrastructure); this script only reads them to score the GPU results.
@@ -64,6 +66,8 @@ def _conservation(w, r):
     gl = r["globals"][-1]
     m = w.params["mass"]
     e0 = 0.5 * m * sum(float(np.sum(w.state[k] ** 2)) for k in ("vx", "vy", "vz"))
+    if w.params.get("planar"):
+        assert np.all(r["state"]["vz"] == 0.0), "a 2D run left the plane"
     alive = r["counters"][:, 0]
     return dict(energy_rel_drift=float(abs(gl[3] - e0) / e0),
                 energy_first_step_rel=float(abs(g0[3] - e0) / e0),
@@ -72,36 +76,43 @@ def _conservation(w, r):
                 collided_fraction=float(2 * r["counters"][:, 1].mean() / w.n))
 
 
-def sod(precision, n=4_000_000, steps=500, kn=1e-3):
+def sod(precision, n=4_000_000, steps=500, kn=1e-3, planar=False):
     from oracle import analytic as A
     from paper_1210_8084_amd import workloads as W
-    w = W.sod(n=n, ncell=1000, nobin=200, dt=1.134e-4, kn=kn)
+    if planar:
+        w = W.sod2d(n=n, ncell=1000, nobin=200, dt=1.134e-4, kn=kn)
+    else:
+        w = W.sod(n=n, ncell=1000, nobin=200, dt=1.134e-4, kn=kn)
+    f = 2 if planar else 3
     r = _run(w, precision, steps, progress=100)
     t = steps * w.params["dt"]
     M = r["moments"]
     nob = w.grid["nobin"][0]
-    vol = (1.0 / nob) * 0.05 * 0.05
+    # o-bin volume: length x cross-section (an area in space, a width in the plane)
+    vol = (1.0 / nob) * (w.info["side"] if planar else 0.05 * 0.05)
     n_ = M[:, 0] / vol
-    # p = n T + virial / (3 V), T = m sum (v - vbar)^2 / (3 count)
-    kin = (M[:, 4] + M[:, 5] + M[:, 6]) / 3.0
-    vir = (M[:, 7] + M[:, 8] + M[:, 9]) / 3.0
+    # p = n T + virial / (f V), T = m sum (v - vbar)^2 / (f count)
+    kin = M[:, 4:4 + f].sum(axis=1) / f
+    vir = M[:, 7:7 + f].sum(axis=1) / f
     p_kin = kin / vol
     p_tot = (kin + vir) / vol
     xc = (np.arange(nob) + 0.5) / nob
     nl, nr = w.info["n_left"], w.info["n_right"]
-    rho, u, p = A.sod_profile(xc, t, (nl, 0.0, nl * 1.25), (nr, 0.0, nr * 1.0))
-    return dict(workload=f"sod n={n} kn={kn}", steps=steps, t=t, wall_s=r["wall"],
+    tl, tr = w.info["t_left"], w.info["t_right"]
+    rho, u, p = A.sod_profile(xc, t, (nl, 0.0, nl * tl), (nr, 0.0, nr * tr), gamma=w.info["gamma"])
+    return dict(workload=f"{w.name} n={n} kn={kn}", steps=steps, t=t, wall_s=r["wall"],
                 l1_density=float(np.mean(np.abs(n_ - rho)) / nl),
-                l1_pressure_kinetic=float(np.mean(np.abs(p_kin - p)) / (nl * 1.25)),
-                l1_pressure_with_virial=float(np.mean(np.abs(p_tot - p)) / (nl * 1.25)),
+                l1_pressure_kinetic=float(np.mean(np.abs(p_kin - p)) / (nl * tl)),
+                l1_pressure_with_virial=float(np.mean(np.abs(p_tot - p)) / (nl * tl)),
                 profile_density=(n_ / nl).round(4).tolist(), analytic_density=(rho / nl).round(4).tolist(),
                 **_conservation(w, r))
 
 
-def noh(precision, n=8_000_000, steps=800):
+def noh(precision, n=8_000_000, steps=800, planar=False):
     from oracle import analytic as A
     from paper_1210_8084_amd import workloads as W
-    w = W.noh(n=n, steps=steps)
+    w = (W.noh2d if planar else W.noh)(n=n, steps=steps)
+    f = 2 if planar else 3
     r = _run(w, precision, steps, progress=200)
     t = steps * w.params["dt"]
     st = r["state"]
@@ -109,34 +120,46 @@ def noh(precision, n=8_000_000, steps=800):
     edges = np.arange(0.0, 0.4 + 1e-12, 0.01)
     cnt, _ = np.histogram(rad, bins=edges)
     area = math.pi * (edges[1:] ** 2 - edges[:-1] ** 2)
-    n_ = cnt / (area * w.info["h"])
+    n_ = cnt / (area * (1.0 if planar else w.info["h"]))
     rc = 0.5 * (edges[1:] + edges[:-1])
-    na, _, _, rs = A.noh_profile(rc, t, n0=w.info["n0"], v0=1.0, gamma=5 / 3, d=2)
+    gamma = w.info["gamma"]
+    na, _, _, rs = A.noh_profile(rc, t, n0=w.info["n0"], v0=1.0, gamma=gamma, d=2)
     inside = rc < rs * 0.8
-    return dict(workload=f"noh n={n}", steps=steps, t=t, wall_s=r["wall"], r_shock=rs,
+    # Shocked gas at rest with internal energy v0^2 / 2 per mass: T = m v0^2 / f.
+    core = rad < 0.8 * rs
+    t_core = None
+    if core.sum() > 100:
+        dv2 = sum((st[k][core] - st[k][core].mean()) ** 2 for k in ("vx", "vy", "vz")[:f])
+        t_core = float(w.params["mass"] * dv2.mean() / f)
+    return dict(workload=f"{w.name} n={n}", steps=steps, t=t, wall_s=r["wall"], r_shock=rs,
                 l1_density=float(np.mean(np.abs(n_ - na)) / w.info["n0"]),
                 shocked_density_over_n0=float(np.mean(n_[inside]) / w.info["n0"]) if inside.any() else None,
-                analytic_shocked=16.0,
+                analytic_shocked=((gamma + 1.0) / (gamma - 1.0)) ** 2,
+                shocked_temperature=t_core, analytic_shocked_temperature=w.params["mass"] * 1.0 / f,
                 profile_density=(n_ / w.info["n0"]).round(3).tolist(), analytic_density=(na / w.info["n0"]).round(3).tolist(),
                 **_conservation(w, r))
 
 
-def sedov(precision, n=16_000_000, steps=600):
+def sedov(precision, n=16_000_000, steps=600, planar=False):
     from oracle import analytic as A
     from paper_1210_8084_amd import workloads as W
-    w = W.sedov(n=n, steps=steps)
+    w = (W.sedov2d if planar else W.sedov)(n=n, steps=steps)
     r = _run(w, precision, steps, progress=200)
     t = steps * w.params["dt"]
     st = r["state"]
-    rad = np.sqrt((st["x"] - 0.5) ** 2 + (st["y"] - 0.5) ** 2 + (st["z"] - 0.5) ** 2)
+    j = 2 if planar else 3
+    rad = np.sqrt(sum((st[k] - 0.5) ** 2 for k in ("x", "y", "z")[:j]))
     edges = np.arange(0.0, 0.5 + 1e-12, 0.01)
     cnt, _ = np.histogram(rad, bins=edges)
-    vol = 4.0 / 3.0 * math.pi * (edges[1:] ** 3 - edges[:-1] ** 3)
+    if planar:
+        vol = math.pi * (edges[1:] ** 2 - edges[:-1] ** 2)
+    else:
+        vol = 4.0 / 3.0 * math.pi * (edges[1:] ** 3 - edges[:-1] ** 3)
     rho = cnt * w.params["mass"] / vol
     rc = 0.5 * (edges[1:] + edges[:-1])
-    ra, _, _, R = A.sedov_profile(rc, t, energy=w.info["energy"], rho0=1.0)
+    ra, _, _, R = A.sedov_profile(rc, t, energy=w.info["energy"], rho0=1.0, gamma=w.info["gamma"], j=j)
     peak = int(np.argmax(rho))
-    return dict(workload=f"sedov n={n}", steps=steps, t=t, wall_s=r["wall"], r_shock_analytic=R,
+    return dict(workload=f"{w.name} n={n}", steps=steps, t=t, wall_s=r["wall"], r_shock_analytic=R,
                 r_density_peak=float(rc[peak]), peak_density=float(rho[peak]),
                 l1_density=float(np.mean(np.abs(rho - ra))),
                 profile_density=rho.round(3).tolist(), analytic_density=ra.round(3).tolist(),
@@ -147,19 +170,25 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=None)
     ap.add_argument("--quick", action="store_true", help="smaller sizes and fewer steps")
-    ap.add_argument("--only", default="sod,noh,sedov")
+    ap.add_argument("--only", default="sod,noh,sedov,sod2d,noh2d,sedov2d")
     args = ap.parse_args()
     from paper_1210_8084_amd import tpkmc as T
     report = {}
     for name in args.only.split(","):
+        planar = name.endswith("2d")
+        base = name[:-2] if planar else name
         for prec, label in ((T.FP32, "fp32"), (T.FP64, "fp64")):
             print(f"== {name} {label}", flush=True)
-            if name == "sod":
-                res = sod(prec, n=400_000 if args.quick else 4_000_000, steps=100 if args.quick else 500)
-            elif name == "noh":
-                res = noh(prec, n=800_000 if args.quick else 8_000_000, steps=200 if args.quick else 800)
+            if base == "sod":
+                res = sod(prec, n=400_000 if args.quick else 4_000_000, steps=100 if args.quick else 500,
+                          planar=planar)
+            elif base == "noh":
+                res = noh(prec, n=800_000 if args.quick else 8_000_000, steps=200 if args.quick else 800,
+                          planar=planar)
             else:
-                res = sedov(prec, n=2_000_000 if args.quick else 16_000_000, steps=150 if args.quick else 600)
+                n_full = 4_000_000 if planar else 16_000_000
+                res = sedov(prec, n=n_full // 8 if args.quick else n_full, steps=150 if args.quick else 600,
+                            planar=planar)
             report[f"{name}_{label}"] = res
             brief = {k: v for k, v in res.items() if not k.startswith(("profile", "analytic_density"))}
             print(json.dumps(brief), flush=True)

@@ -195,6 +195,117 @@ def equilibration(n=200_000, seed=1, lam_over_dx=1e-3, ncell=(32, 32, 32), box=4
     return Workload("equilibration", st, g, params(sigma, dt, seed=seed), steps, info)
 
 
+def mean_speed_2d(temperature: float, mass: float = 1.0) -> float:
+    """Mean speed of a 2D Maxwellian, sqrt(pi T / (2 m))."""
+    return math.sqrt(math.pi * temperature / (2.0 * mass))
+
+
+def _in_plane(n, z=0.0):
+    return np.full(n, float(z)), np.zeros(n)
+
+
+def sod2d(n=100_000, seed=1, kn=1e-3, ncell=200, nobin=200, dt=None, steps=100,
+          t_left=1.25, t_right=1.0, density_ratio=8.0, side=0.05):
+    """Sod shock tube of a two-dimensional gas (Sec. 4.2, the 2D run; f = 2,
+    gamma = 2) in the strip [0,1] x [0,side] of the plane z = 0: reflecting
+    ends, periodic along y.  sigma is a length, 1 / (n lambda) with n the
+    number per area."""
+    rng = np.random.default_rng(seed)
+    n_left = int(round(n * density_ratio / (density_ratio + 1.0)))
+    n_right = n - n_left
+    x = np.concatenate([rng.uniform(0.0, 0.5, n_left), rng.uniform(0.5, 1.0, n_right)])
+    y = rng.uniform(0.0, side, n)
+    vl = rng.normal(0.0, math.sqrt(t_left), size=(2, n_left))
+    vr = rng.normal(0.0, math.sqrt(t_right), size=(2, n_right))
+    vl -= vl.mean(axis=1, keepdims=True)
+    vr -= vr.mean(axis=1, keepdims=True)
+    v = np.concatenate([vl, vr], axis=1)
+    area = 1.0 * side
+    n_mean = n / area
+    lam = kn * 1.0
+    sigma = sigma_from_kn(kn, 1.0, n_mean)
+    t_mean = (n_left * t_left + n_right * t_right) / n
+    tau = lam / mean_speed_2d(t_mean)
+    if dt is None:
+        dt = 0.2 * tau
+    g = grid((0, 0, -0.5), (1.0, side, 0.5), (ncell, 1, 1), (REFLECT, PERIODIC, PERIODIC), (nobin, 1, 1))
+    z, vz = _in_plane(n)
+    st = make_state(x, y, z, v[0], v[1], vz)
+    info = dict(kn=kn, lam=lam, n_mean=n_mean, n_left=n_left / (0.5 * area),
+                n_right=n_right / (0.5 * area), t_left=t_left, t_right=t_right, tau=tau,
+                gamma=2.0, f=2, side=side)
+    return Workload("sod2d", st, g, dict(params(sigma, dt, seed=seed), planar=True), steps, info)
+
+
+def noh2d(n=8_000_000, seed=1, kn=1e-3, ncell=256, nobin=None, dt=7.5e-4, steps=800,
+          thermal=1e-3, v0=1.0):
+    """Cylindrical Noh implosion of a two-dimensional gas (Sec. 4.3, the 2D
+    run; f = 2, gamma = 2, density jump 9): uniform disk of radius 1 in the
+    plane z = 0, radial inflow speed v0 plus a cold 2D Maxwellian."""
+    rng = np.random.default_rng(seed)
+    rad = np.sqrt(rng.uniform(0.0, 1.0, n))
+    th = rng.uniform(0.0, 2.0 * math.pi, n)
+    x, y = rad * np.cos(th), rad * np.sin(th)
+    vt = rng.normal(0.0, thermal, size=(2, n))
+    vx = -v0 * np.cos(th) + vt[0]
+    vy = -v0 * np.sin(th) + vt[1]
+    n0 = n / math.pi
+    sigma = sigma_from_kn(kn, 1.0, n0)
+    nb = ncell if nobin is None else nobin
+    g = grid((-1, -1, -0.5), (1, 1, 0.5), (ncell, ncell, 1), (REFLECT, REFLECT, PERIODIC), (nb, nb, 1))
+    z, vz = _in_plane(n)
+    st = make_state(x, y, z, vx, vy, vz)
+    info = dict(kn=kn, lam=kn, n0=n0, v0=v0, gamma=2.0, f=2, geometry=2)
+    return Workload("noh2d", st, g, dict(params(sigma, dt, seed=seed), planar=True), steps, info)
+
+
+def sedov2d(n=4_000_000, seed=1, kn=1e-3, ncell=800, nobin=200, steps=600, blast_fraction=1e-3,
+            energy=1.0, cold_ratio=1e-3):
+    """Point blast in a two-dimensional gas (Sec. 4.4, the 2D run; f = 2,
+    gamma = 2, cylindrical similarity solution) in the unit square with
+    reflecting walls, mass 1/N (areal density 1).  dt moves the fastest
+    particle half a c-bin."""
+    rng = np.random.default_rng(seed)
+    pos = rng.uniform(0.0, 1.0, size=(2, n))
+    m = 1.0 / n
+    nb = max(1, int(round(blast_fraction * n)))
+    r2 = ((pos - 0.5) ** 2).sum(axis=0)
+    blast = np.argpartition(r2, nb - 1)[:nb]
+    vb = math.sqrt(2.0 * energy / (nb * m))
+    speed = np.full(n, cold_ratio * vb)
+    speed[blast] = vb
+    th = rng.uniform(0.0, 2.0 * math.pi, n)
+    w = 1.0 / ncell
+    dt = 0.5 * w / vb
+    sigma = sigma_from_kn(kn, 1.0, float(n))
+    g = grid((0, 0, -0.5), (1, 1, 0.5), (ncell, ncell, 1), (REFLECT, REFLECT, PERIODIC), (nobin, nobin, 1))
+    z, vz = _in_plane(n)
+    st = make_state(pos[0], pos[1], z, speed * np.cos(th), speed * np.sin(th), vz)
+    info = dict(kn=kn, lam=kn, n0=float(n), rho0=1.0, energy=energy, v_blast=vb, n_blast=nb,
+                gamma=2.0, f=2, geometry=2)
+    return Workload("sedov2d", st, g, dict(params(sigma, dt, mass=m, seed=seed), planar=True), steps, info)
+
+
+def random_plane(n=2000, seed=1, ncell=(6, 5), bc=(REFLECT, PERIODIC), hi=(1.0, 0.8), speed=1.0,
+                 d_over_w=0.6, dt_over=0.4, nobin=None):
+    """Small two-dimensional box for parity tests: uniform positions in the
+    plane z = 0, Gaussian in-plane velocities; D = d_over_w * (smallest
+    c-bin width), sigma = 2 D."""
+    rng = np.random.default_rng(seed)
+    x = rng.uniform(0.0, hi[0], n)
+    y = rng.uniform(0.0, hi[1], n)
+    v = rng.normal(0.0, speed, size=(2, n))
+    wmin = min(hi[0] / ncell[0], hi[1] / ncell[1])
+    sigma = 2.0 * d_over_w * wmin
+    dt = dt_over * wmin / speed
+    nb = (ncell[0], ncell[1]) if nobin is None else nobin
+    g = grid((0, 0, -0.5), (hi[0], hi[1], 0.5), (ncell[0], ncell[1], 1), (bc[0], bc[1], PERIODIC),
+             (nb[0], nb[1], 1))
+    z, vz = _in_plane(n)
+    st = make_state(x, y, z, v[0], v[1], vz)
+    return Workload("random_plane", st, g, dict(params(sigma, dt, seed=seed), planar=True), 1, {})
+
+
 def random_box(n=2000, seed=1, ncell=(6, 5, 4), bc=(REFLECT, PERIODIC, PERIODIC), lo=(0, 0, 0),
                hi=(1.0, 0.8, 0.6), speed=1.0, d_over_w=0.6, dt_over=0.4, nobin=None):
     """Small generic box for parity tests: uniform positions, Gaussian

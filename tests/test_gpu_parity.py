@@ -88,6 +88,7 @@ def assert_outputs_match(go, ro, mass):
     for k in (3, 6):
         assert gg[k] == pytest.approx(rg[k], rel=1e-13)
     assert gg[4] == rg[4]
+    assert gg[7] == rg[7]  # the time step used
     assert gg[5] == pytest.approx(rg[5], rel=1e-9, abs=1e-12 * scale)
     gm, rm = go["moments"], ro["moments"]
     assert np.array_equal(gm[:, 0], rm[:, 0])
@@ -345,3 +346,265 @@ def test_fp64_sqrt_and_division_are_correctly_rounded(T, oracle):
     want, routs = oracle_steps(oracle, w)
     assert routs[0]["counters"][1] > 1000
     assert_state_equal(got, want)
+
+
+# ------------------------------------------------------------ adaptive dt
+def _adaptive(w, cap=1.0):
+    w.params = dict(w.params, dt=float(cap), adaptive_dt=True)
+    return w
+
+
+@pytest.mark.parametrize("case", CASES[:5], ids=lambda c: f"s{c['seed']}-{c['ncell']}-{c['bc']}")
+def test_fp64_adaptive_step_bit_exact(T, oracle, case):
+    """The adaptive time step of Sec. 3 is taken on the device: the same
+    dt, pairs and state as the oracle, bit for bit."""
+    w = _adaptive(W.random_box(n=2500, seed=case["seed"], ncell=case["ncell"], bc=case["bc"], d_over_w=0.7,
+                               dt_over=0.6, nobin=(3, 2, 1)))
+    w.state["vx"][7] *= 3.0  # a clear fastest particle
+    _say(f"adaptive case {case}")
+    got, gouts, status = gpu_steps(T, w, T.FP64)
+    want, routs = oracle_steps(oracle, w)
+    dt = oracle.step_dt(w.state, w.grid, w.params)
+    assert routs[0]["globals"][7] == dt
+    assert (dt < 1.0) if max(case["ncell"]) > 1 else (dt == 1.0)  # one c-bin per axis: the cap
+    assert_state_equal(got, want)
+    assert_outputs_match(gouts[0], routs[0], w.params["mass"])
+    if min(case["ncell"]) > 1:  # every axis bounds the step
+        assert routs[0]["counters"][oracle.CNT["fast"]] <= 1
+
+
+def test_fp64_adaptive_trajectory_and_cap(T, oracle):
+    """Eight adaptive steps: dt changes from step to step with v_max and
+    the state stays bit-identical; a small cap wins over the rule."""
+    w = _adaptive(W.random_box(n=4000, seed=12, ncell=(8, 4, 4), bc=(R, P, P), d_over_w=0.7, dt_over=0.4))
+    got, gouts, _ = gpu_steps(T, w, T.FP64, steps=8)
+    want, routs = oracle_steps(oracle, w, steps=8)
+    assert_state_equal(got, want)
+    dts = [o["globals"][0][7] for o in gouts]
+    assert dts == [o["globals"][7] for o in routs]
+    assert len(set(dts)) > 1
+    cap = 0.5 * min(dts)
+    w2 = _adaptive(W.random_box(n=4000, seed=12, ncell=(8, 4, 4), bc=(R, P, P), d_over_w=0.7, dt_over=0.4), cap)
+    _, gouts2, _ = gpu_steps(T, w2, T.FP64, steps=2)
+    assert [o["globals"][0][7] for o in gouts2] == [cap, cap]
+
+
+def test_graph_run_adapts_dt_on_the_device(T, oracle):
+    """tpkmc_run with adaptive instances: each replay takes its own dt from
+    the current state; instance 1 keeps its fixed dt."""
+    ws = _batch()[:3]
+    _adaptive(ws[0], cap=1.0)
+    _adaptive(ws[2], cap=1.0)
+    st, specs = _concat(ws)
+    n = len(st["x"])
+    kw = dict(max_particles=n, max_cells=sum(T.ncells(w.grid) + 1 for w in ws),
+              max_obins=sum(T.nobins(w.grid) for w in ws), precision=T.FP64, max_instances=len(ws))
+    K = 5
+    eng = T.Engine(**kw)
+    d1 = T.to_device(st, T.FP64)
+    out = T.make_outputs(len(ws), kw["max_obins"])
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        eng.run(d1, specs, K, out, stream=stream)
+    stream.synchronize()
+    h1 = T.to_host(d1)
+    go = out.host()
+    eng.close()
+    for k, w in enumerate(ws):
+        ref_state = W.copy_state(w.state)
+        ref_state["id"] = st["id"][specs[k][0]:specs[k][0] + w.n].copy()
+        dts = []
+        for s in range(K):
+            ro = oracle.step(ref_state, w.grid, dict(w.params, step=w.params["step"] + s))
+            dts.append(ro["globals"][7])
+        sl = slice(specs[k][0], specs[k][0] + w.n)
+        assert_state_equal({kk: v[sl] for kk, v in h1.items()}, ref_state)
+        assert go["globals"][k][7] == dts[-1]
+        if k == 1:
+            assert dts == [w.params["dt"]] * K
+        else:
+            assert len(set(dts)) > 1
+
+
+def test_fp32_adaptive_dt_matches_the_rule(T, oracle):
+    """FP32 state: v_max and dt are evaluated in double from the float
+    components, so the dt equals the oracle's rule on the float state."""
+    w = _adaptive(W.random_box(n=30000, seed=13, ncell=(12, 10, 8), bc=(P, P, P), d_over_w=0.5, dt_over=0.4))
+    f32 = W.copy_state(w.state, dtype=np.float32)
+    as64 = W.copy_state(f32)
+    dt = oracle.step_dt(as64, w.grid, w.params)
+    got, gouts, status = gpu_steps(T, w, T.FP32, state=f32)
+    assert gouts[0]["globals"][0][7] == dt
+    assert gouts[0]["counters"][0][T.CNT["fast"]] <= 1
+
+
+# ------------------------------------------------------------ planar (2D) gas
+PLANE_CASES = [
+    dict(seed=31, ncell=(6, 5), bc=(R, P)),
+    dict(seed=32, ncell=(3, 3), bc=(P, P)),
+    dict(seed=33, ncell=(1, 7), bc=(P, R)),
+    dict(seed=34, ncell=(2, 1), bc=(P, P)),
+    dict(seed=35, ncell=(9, 4), bc=(A, R)),
+]
+
+
+@pytest.mark.parametrize("case", PLANE_CASES, ids=lambda c: f"s{c['seed']}-{c['ncell']}-{c['bc']}")
+def test_fp64_planar_step_bit_exact(T, oracle, case):
+    """Two-dimensional gas: in-plane scattering directions and D = sigma/2,
+    bit for bit against the oracle over three steps."""
+    w = W.random_plane(n=2999, seed=case["seed"], ncell=case["ncell"], bc=case["bc"], d_over_w=0.7,
+                       dt_over=0.5)
+    w.state = W.shuffle_state(w.state, seed=case["seed"])
+    _say(f"planar case {case}")
+    got, gouts, _ = gpu_steps(T, w, T.FP64, steps=3)
+    want, routs = oracle_steps(oracle, w, steps=3)
+    assert_state_equal(got, want)
+    for go, ro in zip(gouts, routs):
+        assert_outputs_match(go, ro, w.params["mass"])
+    assert routs[0]["counters"][1] > 100
+    assert np.all(got["vz"] == 0.0) and np.all(got["z"] == 0.0)
+
+
+def test_fp64_planar_adaptive_batched_with_spatial(T, oracle):
+    """One batch holding a 2D Sod strip with the adaptive step and a 3D box:
+    each instance equals its own oracle run."""
+    ws = [_adaptive(W.sod2d(n=8000, seed=41, ncell=40, nobin=8), cap=1.0),
+          W.random_box(n=3000, seed=42, ncell=(4, 3, 3), bc=(R, P, P), d_over_w=0.7, dt_over=0.5)]
+    for k, w in enumerate(ws):
+        w.params["instance"] = k
+    st, specs = _concat(ws)
+    n = len(st["x"])
+    eng = T.Engine(max_particles=n, max_cells=sum(T.ncells(w.grid) + 1 for w in ws),
+                   max_obins=sum(T.nobins(w.grid) for w in ws), precision=T.FP64, max_instances=len(ws))
+    dst = T.to_device(st, T.FP64)
+    out = T.make_outputs(len(ws), sum(T.nobins(w.grid) for w in ws), pair_cap=n)
+    for s in range(2):
+        eng.step_batched(dst, [(o, c, g, dict(p, step=s)) for o, c, g, p in specs], out, flags=T.EMIT_PAIRS)
+    torch.cuda.synchronize()
+    got, go = T.to_host(dst), out.host()
+    eng.close()
+    for k, w in enumerate(ws):
+        ref_state = W.copy_state(w.state)
+        ref_state["id"] = st["id"][specs[k][0]:specs[k][0] + w.n].copy()
+        for s in range(2):
+            ro = oracle.step(ref_state, w.grid, dict(w.params, step=s))
+        sl = slice(specs[k][0], specs[k][0] + w.n)
+        assert_state_equal({kk: v[sl] for kk, v in got.items()}, ref_state)
+        assert go["counters"][k].tolist() == ro["counters"].tolist()
+        assert go["globals"][k][7] == ro["globals"][7]
+
+
+def test_fp32_planar_keeps_the_plane_and_conserves(T, oracle):
+    """FP32 2D blast: z and vz stay exactly as given, energy and the pair
+    count track the FP64 oracle."""
+    w = W.sedov2d(n=60000, seed=43, ncell=60, nobin=10, blast_fraction=0.02)
+    f32 = W.copy_state(w.state, dtype=np.float32)
+    got, gouts, _ = gpu_steps(T, w, T.FP32, steps=4, state=f32)
+    assert np.all(got["vz"] == 0.0) and np.all(got["z"] == 0.0)
+    e0 = 0.5 * w.params["mass"] * float(sum((f32[k].astype(np.float64) ** 2).sum() for k in ("vx", "vy")))
+    assert gouts[-1]["globals"][0][3] == pytest.approx(e0, rel=2e-5)
+    want, routs = oracle_steps(oracle, w, steps=1)
+    assert gouts[0]["counters"][0][1] == pytest.approx(routs[0]["counters"][1], rel=0.05)
+
+
+def test_planar_needs_one_bin_along_z(T):
+    w = W.random_plane(n=500, seed=44)
+    g = dict(w.grid, ncell=(6, 5, 2), nobin=(6, 5, 2))
+    eng = T.Engine(max_particles=500, max_cells=T.ncells(g) + 1, max_obins=T.nobins(g), precision=T.FP64)
+    dst = T.to_device(w.state, T.FP64)
+    assert eng.step(dst, g, w.params, None, rc_only=True) == T.EINVAL
+    eng.close()
+
+
+# ------------------------------------------------------------ search variants
+VARIANTS = [(0, 1, 256), (0, 2, 128), (0, 4, 64), (1, 4, 256), (1, 4, 64)]
+
+
+def _fp32_run(T, w, variant, steps=2, flags=None):
+    eng = engine_for(T, w, T.FP32)
+    if variant is not None:
+        eng.set_search(*variant)
+        assert eng.get_search() == variant
+    dst = T.to_device(W.copy_state(w.state, dtype=np.float32), T.FP32)
+    out = T.make_outputs(1, T.nobins(w.grid), pair_cap=w.n)
+    hs = []
+    for s in range(steps):
+        eng.step(dst, w.grid, dict(w.params, step=s), out, flags=T.EMIT_PAIRS if flags is None else flags)
+        torch.cuda.synchronize()
+        hs.append(out.host())
+    eng.close()
+    return T.to_host(dst), hs
+
+
+VARIANT_CASES = [
+    dict(seed=51, ncell=(7, 5, 4), bc=(R, P, P)),
+    dict(seed=52, ncell=(3, 3, 3), bc=(P, P, P)),
+    dict(seed=53, ncell=(2, 1, 6), bc=(P, P, R)),
+    dict(seed=54, ncell=(1, 1, 1), bc=(P, P, P)),
+    dict(seed=55, ncell=(4, 2, 9), bc=(P, R, P)),
+    dict(seed=56, ncell=(6, 6, 6), bc=(A, R, A)),
+]
+
+
+@pytest.mark.parametrize("case", VARIANT_CASES, ids=lambda c: f"s{c['seed']}-{c['ncell']}-{c['bc']}")
+def test_fp32_search_variants_are_identical(T, case):
+    """Every partner-search layout (records per lane, work-group size, the
+    c-bin-centric search) gives the same pairs, state and counters."""
+    w = W.random_box(n=3001, seed=case["seed"], ncell=case["ncell"], bc=case["bc"], d_over_w=0.7, dt_over=0.5)
+    _say(f"variants case {case}")
+    ref_state, ref_out = _fp32_run(T, w, VARIANTS[0])
+    assert ref_out[0]["counters"][0][1] > 50
+    for v in VARIANTS[1:]:
+        st, outs = _fp32_run(T, w, v)
+        for k in ("x", "y", "z", "vx", "vy", "vz"):
+            assert np.array_equal(st[k], ref_state[k]), (v, k)
+        for o, r in zip(outs, ref_out):
+            assert o["counters"][0].tolist() == r["counters"][0].tolist(), v
+            assert pairset(o["pairs"]) == pairset(r["pairs"]), v
+
+
+def test_fp32_cell_search_on_a_batch_with_an_empty_instance(T):
+    """The c-bin-centric search finds each wave's instance from its index:
+    a batch with an empty instance in the middle equals the lane search."""
+    ws = [W.random_box(n=2500, seed=61, ncell=(5, 4, 3), bc=(R, P, P), d_over_w=0.7, dt_over=0.5),
+          W.random_box(n=0, seed=62, ncell=(3, 3, 3)),
+          W.random_plane(n=2000, seed=63, ncell=(6, 5), d_over_w=0.7, dt_over=0.5),
+          W.random_box(n=1500, seed=64, ncell=(2, 2, 2), bc=(P, P, P), d_over_w=0.7, dt_over=0.5)]
+    for k, w in enumerate(ws):
+        w.params["instance"] = k
+    st, specs = _concat(ws)
+    n = len(st["x"])
+    kw = dict(max_particles=n, max_cells=sum(T.ncells(w.grid) + 1 for w in ws),
+              max_obins=sum(T.nobins(w.grid) for w in ws), precision=T.FP32, max_instances=len(ws))
+    res = []
+    for v in ((0, 2, 256), (1, 4, 128)):
+        eng = T.Engine(**kw)
+        eng.set_search(*v)
+        dst = T.to_device(W.copy_state(st, dtype=np.float32) | {"id": st["id"]}, T.FP32)
+        out = T.make_outputs(len(ws), kw["max_obins"], pair_cap=n)
+        eng.step_batched(dst, specs, out, flags=T.EMIT_PAIRS)
+        torch.cuda.synchronize()
+        res.append((T.to_host(dst), out.host()))
+        eng.close()
+    (s0, o0), (s1, o1) = res
+    for k in ("x", "y", "z", "vx", "vy", "vz"):
+        assert np.array_equal(s0[k], s1[k])
+    assert o0["counters"].tolist() == o1["counters"].tolist()
+    assert pairset(o0["pairs"]) == pairset(o1["pairs"])
+    assert o0["counters"][0][1] > 50 and o0["counters"][1][0] == 0
+
+
+def test_search_variant_arguments(T):
+    w = W.random_box(n=100, seed=65)
+    e32, e64 = engine_for(T, w, T.FP32), engine_for(T, w, T.FP64)
+    with pytest.raises(T.TpkmcError):
+        e32.set_search(0, 3, 64)
+    with pytest.raises(T.TpkmcError):
+        e32.set_search(0, 4, 256)
+    with pytest.raises(T.TpkmcError):
+        e32.set_search(1, 2, 64)
+    with pytest.raises(T.TpkmcError):
+        e64.set_search(1, 4, 64)
+    e64.set_search(0, 1, 64)
+    assert e64.get_search() == (0, 1, 64)
+    e32.close(); e64.close()
