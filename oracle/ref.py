@@ -28,6 +28,7 @@ GLB = dict(px=0, py=1, pz=2, ekin=3, vmax2=4, virial=5, mass=6, dt=7)
 M_STRIDE = 11
 ADAPTIVE_DT = 1  # ref_params.flags: step length from the rule of Sec. 3
 PLANAR = 2       # ref_params.flags: two-dimensional gas (x-y plane)
+RANK_TIME = 4    # ref_params.flags: criterion 3 by earliest contact time
 
 
 def build() -> str:
@@ -113,7 +114,8 @@ def make_params(p) -> Params:
     P.seed = int(p.get("seed", 0))
     P.step = int(p.get("step", 0))
     P.instance = int(p.get("instance", 0))
-    P.flags = (ADAPTIVE_DT if p.get("adaptive_dt") else 0) | (PLANAR if p.get("planar") else 0)
+    P.flags = ((ADAPTIVE_DT if p.get("adaptive_dt") else 0) | (PLANAR if p.get("planar") else 0) |
+               (RANK_TIME if p.get("rank_time") else 0))
     return P
 
 

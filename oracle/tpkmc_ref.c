@@ -123,6 +123,7 @@ int ref_direction_planar(uint64_t seed, uint64_t step, uint32_t instance,
 typedef struct {
     double L[3], w[3], inv_w[3], halfL[3], inv_wo[3];
     double D2;
+    int rank_time;          /* criterion 3 ranks by the contact time t_o1 */
     int32_t n[3], bc[3], no[3];
     int64_t C, B;
 } derived;
@@ -146,6 +147,7 @@ static int derive(const ref_grid* g, const ref_params* p, derived* G)
         G->C *= g->ncell[a];
         G->B *= g->nobin[a];
     }
+    G->rank_time = p && (p->flags & REF_RANK_TIME) != 0;
     if (p) {
         if (!(p->sigma >= 0.0) || !(p->dt > 0.0) || !(p->mass > 0.0)) return -1;
         if (p->instance >= (1u << 24)) return -1;
@@ -264,7 +266,7 @@ static void rel(const derived* G, const double ri[3], const double vi[3],
 static int test_pair(const derived* G, double dt,
                      const double ri[3], const double vi[3],
                      const double rj[3], const double vj[3],
-                     double* d2_out, double* tp_out)
+                     double* d2_out, double* tp_out, double* tc_out)
 {
     double r[3], u[3];
     rel(G, ri, vi, rj, vj, r, u);
@@ -287,6 +289,16 @@ static int test_pair(const derived* G, double dt,
     if (!(d2 <= G->D2)) return 0;
     *d2_out = d2;
     *tp_out = tp;
+    if (tc_out) {
+        /* The earlier root of the overlap quadratic of Sec. 2.4 (first
+         * contact of the effective radii): t_o1 = (-(u.r) - sqrt((u.r)^2 -
+         * |u|^2 (|r|^2 - D^2))) / |u|^2.  The discriminant equals
+         * |u|^2 (D^2 - d_min^2) >= 0; a rounding below zero is taken as 0. */
+        double rr = (r[0] * r[0] + r[1] * r[1]) + r[2] * r[2];
+        double disc = s0 * s0 - vv * (rr - G->D2);
+        if (!(disc > 0.0)) disc = 0.0;
+        *tc_out = (-s0 - sqrt(disc)) / vv;
+    }
     return 1;
 }
 
@@ -297,7 +309,7 @@ int ref_pair_test(const ref_grid* g, const ref_params* p,
 {
     derived G;
     if (derive(g, p, &G)) return -1;
-    return test_pair(&G, p->dt, ri, vi, rj, vj, d2, tp);
+    return test_pair(&G, p->dt, ri, vi, rj, vj, d2, tp, NULL);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -370,14 +382,18 @@ static void free_bins(bins* Bn)
 /* Criterion 3: the closest candidate, ties to the lower id. */
 static void consider(const derived* G, double dt, const view* V, int64_t j,
                      const double ri[3], const double vi[3],
-                     int64_t* bj, double* bd2, uint64_t* ncand)
+                     int64_t* bj, double* bkey, double* bd2, uint64_t* ncand)
 {
-    double rj[3], vj[3], d2, tp;
+    double rj[3], vj[3], d2, tp, tc;
     load(V, j, rj, vj);
-    if (!test_pair(G, dt, ri, vi, rj, vj, &d2, &tp)) return;
+    if (!test_pair(G, dt, ri, vi, rj, vj, &d2, &tp, G->rank_time ? &tc : NULL)) return;
     *ncand += 1;
-    if (*bj < 0 || d2 < *bd2 || (d2 == *bd2 && V->id[j] < V->id[*bj])) {
+    /* Criterion 3: the smallest d_min (or, ranked by time, the earliest
+     * contact), ties to the lower id. */
+    double key = G->rank_time ? tc : d2;
+    if (*bj < 0 || key < *bkey || (key == *bkey && V->id[j] < V->id[*bj])) {
         *bj = j;
+        *bkey = key;
         *bd2 = d2;
     }
 }
@@ -386,7 +402,7 @@ static void best_of(const derived* G, double dt, const view* V, const bins* Bn,
                     int mode, int64_t i, int64_t* bj_out, double* bd2_out, uint64_t* ncand)
 {
     int64_t bj = -1;
-    double bd2 = 0.0;
+    double bd2 = 0.0, bkey = 0.0;
     *bj_out = -1; *bd2_out = 0.0;
     if (Bn->cell[i] < 0) return;
     double ri[3], vi[3];
@@ -397,13 +413,13 @@ static void best_of(const derived* G, double dt, const view* V, const bins* Bn,
         for (int s = 0; s < k; ++s)
             for (int64_t m = Bn->first[nb[s]]; m < Bn->first[nb[s] + 1]; ++m) {
                 int64_t j = Bn->member[m];
-                if (j != i) consider(G, dt, V, j, ri, vi, &bj, &bd2, ncand);
+                if (j != i) consider(G, dt, V, j, ri, vi, &bj, &bkey, &bd2, ncand);
             }
     } else {
         for (int64_t j = 0; j < V->n; ++j) {
             if (j == i || Bn->cell[j] < 0) continue;
             if (mode == REF_MODE_BRUTE && !adjacent(G, Bn->cell[i], Bn->cell[j])) continue;
-            consider(G, dt, V, j, ri, vi, &bj, &bd2, ncand);
+            consider(G, dt, V, j, ri, vi, &bj, &bkey, &bd2, ncand);
         }
     }
     *bj_out = bj;

@@ -48,7 +48,7 @@ typedef struct {
     uint64_t seed;          /* Philox key                                     */
     uint64_t step;          /* step number (low 32 bits enter the counter)    */
     uint32_t instance;      /* instance number (< 2^24)                       */
-    uint32_t flags;         /* REF_ADAPTIVE_DT | REF_PLANAR                   */
+    uint32_t flags;         /* REF_ADAPTIVE_DT | REF_PLANAR | REF_RANK_TIME   */
 } ref_params;
 
 /* ref_params.flags.  REF_ADAPTIVE_DT: the step length follows the rule of
@@ -69,6 +69,13 @@ enum { REF_ADAPTIVE_DT = 1 };
  * place of sigma / pi, and the scattering direction is isotropic in the
  * plane. */
 enum { REF_PLANAR = 2 };
+
+/* ref_params.flags.  REF_RANK_TIME: criterion 3 takes, among the candidates,
+ * the one with the earliest contact of the effective radii (the earlier
+ * overlap time t_o1 of Sec. 2.4) instead of the smallest d_min; the paper
+ * names both choices and uses the distance.  Ties go to the lower id, and
+ * best_d2 outputs stay the d_min^2 of the chosen partner. */
+enum { REF_RANK_TIME = 4 };
 
 /* Counters written by ref_step (uint64[8]). */
 enum {
