@@ -90,7 +90,7 @@ enum {
                                   bound (also taken when v_max = 0).  Computed
                                   on the device, so graph replays adapt too;
                                   the dt used is globals slot 7.            */
-    TPKMC_PLANAR = 8u          /* two-dimensional gas in the x-y plane (the 2D
+    TPKMC_PLANAR = 8u,         /* two-dimensional gas in the x-y plane (the 2D
                                   runs of Sec. 4, f = 2): the grid has one
                                   c-bin along z and the caller gives every
                                   particle the same z and vz = 0, which the
@@ -98,6 +98,11 @@ enum {
                                   width 2 D of the strip one disk sweeps
                                   relative to another (D^2 = sigma^2 / 4),
                                   and directions are isotropic in the plane */
+    TPKMC_RANK_TIME = 16u      /* criterion 3 by time: among the candidates,
+                                  the one whose effective radii touch first
+                                  (the earlier overlap time t_o1 of Sec. 2.4)
+                                  instead of the smallest d_min; the paper
+                                  names both choices and uses the distance */
 };
 
 /* Bits of the device status word (sticky until read). */
@@ -170,7 +175,8 @@ typedef struct {
     uint64_t step;          /* step number (low 32 bits enter the counter)   */
     uint32_t instance;      /* instance number (< 2^24)                      */
     uint32_t flags;         /* TPKMC_EMIT_PAIRS | TPKMC_ALLOW_REORDER |
-                               TPKMC_ADAPTIVE_DT | TPKMC_PLANAR              */
+                               TPKMC_ADAPTIVE_DT | TPKMC_PLANAR |
+                               TPKMC_RANK_TIME                               */
 } tpkmc_params;
 
 /* Structure-of-arrays particle state, device pointers, n entries each.
@@ -247,20 +253,13 @@ int tpkmc_run(tpkmc_handle* h, const tpkmc_particles* s,
 int tpkmc_autotune(tpkmc_handle* h, const tpkmc_particles* s,
                    const tpkmc_instance* inst, int32_t n_inst, void* hip_stream);
 
-/* Partner-search variants.  All give the same pairs, state and counters; they
- * differ only in how the work is laid out on the GPU:
- *   TPKMC_SEARCH_LANES: one lane per `group` consecutive c-bin-ordered
- *     records (group 1, 2 or 4), `block` lanes per work-group (64, 128 or
- *     256, at most 256 / group);
- *   TPKMC_SEARCH_CELLS: FP32 handles only; one wave per `group` consecutive
- *     c-bins (group must be 4), the candidates of a c-bin spread over the
- *     lanes and its own records streamed through scalar registers; `block`
- *     lanes per work-group (64, 128 or 256).  Suited to sparse c-bins.
- * tpkmc_autotune picks among them; tpkmc_set_search fixes one (EINVAL for a
- * shape outside these lists, EUNSUPPORTED for CELLS on an FP64 handle). */
-enum { TPKMC_SEARCH_LANES = 0, TPKMC_SEARCH_CELLS = 1 };
-int tpkmc_set_search(tpkmc_handle* h, int32_t kind, int32_t group, int32_t block);
-int tpkmc_get_search(tpkmc_handle* h, int32_t* kind, int32_t* group, int32_t* block);
+/* Launch shape of the partner search: one lane per `group` consecutive
+ * c-bin-ordered records (1, 2 or 4) and `block` lanes per work-group (64,
+ * 128 or 256, at most 256 / group).  Every shape gives the same pairs, state
+ * and counters.  tpkmc_autotune picks one; tpkmc_set_search fixes one
+ * (EINVAL outside these lists). */
+int tpkmc_set_search(tpkmc_handle* h, int32_t group, int32_t block);
+int tpkmc_get_search(tpkmc_handle* h, int32_t* group, int32_t* block);
 
 /* Synchronises the handle's last stream, returns the status word in
  * *device_status and clears it. */

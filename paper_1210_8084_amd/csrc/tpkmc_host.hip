@@ -260,7 +260,6 @@ struct tpkmc_handle {
     uint32_t* status = nullptr;
     hipStream_t last_stream = nullptr;
     hipStream_t own_stream = nullptr;
-    int search_kind = SEARCH_LANES;
     int search_block = kBlock;
     int search_group = 2;
     bool profiling = false;
@@ -283,13 +282,14 @@ struct tpkmc_handle {
 namespace {
 
 // Host view of one validated call.
+// Target size of one band plane of records (see row_of).
+constexpr double kBandBytes = 1 << 20;
+
 struct Plan {
     int n_inst = 0;
     int64_t ncell_tot = 0, nob_tot = 0, max_nob = 0;
     int nblk = 0;
     bool adaptive = false;    // some instance takes the adaptive time step
-    bool any_periodic = false;
-    int64_t ncw = 0;          // waves of the c-bin-centric search
     std::vector<Blk> blk;
     std::vector<Chunk> chunks;
     std::vector<char> inst_bytes;
@@ -312,8 +312,6 @@ int make_plan(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* i
     P.chunks.clear();
     P.n_inst = n_inst;
     P.adaptive = false;
-    P.any_periodic = false;
-    P.ncw = 0;
     P.ncell_tot = 0;
     P.nob_tot = 0;
     P.max_nob = 0;
@@ -327,7 +325,8 @@ int make_plan(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* i
         if (!(std::isfinite(p.mass) && p.mass > 0.0)) return TPKMC_EINVAL;
         if (!(std::isfinite(p.dt) && p.dt > 0.0)) return TPKMC_EINVAL;
         if (p.instance >= (1u << 24)) return TPKMC_EINVAL;
-        if (p.flags & ~(uint32_t)(TPKMC_EMIT_PAIRS | TPKMC_ALLOW_REORDER | TPKMC_ADAPTIVE_DT | TPKMC_PLANAR))
+        if (p.flags & ~(uint32_t)(TPKMC_EMIT_PAIRS | TPKMC_ALLOW_REORDER | TPKMC_ADAPTIVE_DT | TPKMC_PLANAR |
+                                  TPKMC_RANK_TIME))
             return TPKMC_EINVAL;
         const bool planar = (p.flags & TPKMC_PLANAR) != 0;
         if (planar && g.ncell[2] != 1) return TPKMC_EINVAL;
@@ -341,7 +340,6 @@ int make_plan(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* i
             if (!(std::isfinite(g.lo[a]) && std::isfinite(g.hi[a]) && g.hi[a] > g.lo[a])) return TPKMC_EINVAL;
             if (g.bc[a] < TPKMC_BC_REFLECT || g.bc[a] > TPKMC_BC_ABSORB) return TPKMC_EINVAL;
             if (g.bc[a] == TPKMC_BC_ABSORB && s->alive == nullptr) return TPKMC_EINVAL;
-            if (g.bc[a] == TPKMC_BC_PERIODIC) P.any_periodic = true;
             C *= g.ncell[a];
             B *= g.nobin[a];
             // Derived grid quantities, in double, in the order of the reference.
@@ -382,9 +380,18 @@ int make_plan(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* i
         d.dt_d = p.dt;
         d.dt_cap = p.dt;
         d.dx_d = dx;
+        // Band height of the c-bin order: the largest power of two of rows
+        // whose band plane (rows x n_x c-bins of records) stays within
+        // kBandBytes, so that one XCD's L2 holds the plane its neighbourhood
+        // walk reads twice.  Planar and one-row grids keep a single band.
+        d.band_log2 = 30;
+        if (g.ncell[2] > 1 && g.ncell[1] > 1 && q.count > 0) {
+            const double row_bytes = (double)g.ncell[0] * ((double)q.count / (double)C) * 8.0 * sizeof(real);
+            int h = 0;
+            while (h < 30 && (double)(2 << h) * row_bytes <= (double)kBandBytes) ++h;
+            if ((1 << h) < g.ncell[1]) d.band_log2 = h;
+        }
         if (p.flags & TPKMC_ADAPTIVE_DT) P.adaptive = true;
-        d.cw0 = P.ncw;
-        if (q.count > 0) P.ncw += (C + kCellsPerWave - 1) / kCellsPerWave;
         d.blk0 = (int32_t)P.blk.size();
         for (int64_t o = 0; o < q.count; o += kBlock) P.blk.push_back({k, (int32_t)(q.offset + o)});
         d.nblk = (int32_t)P.blk.size() - d.blk0;
@@ -458,9 +465,6 @@ StepArgs<real> make_args(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_
     a.bkey = h->bkey;
     a.gpart = h->gpart;
     a.shift = h->shift;
-    a.n_inst = P.n_inst;
-    a.any_periodic = P.any_periodic ? 1 : 0;
-    a.ncw = P.ncw;
     a.pairs = o ? o->pairs : nullptr;
     a.pair_cap = (o && o->pairs) ? o->pair_cap : 0;
     a.pair_count = h->pair_count;
@@ -503,7 +507,7 @@ void enqueue_step(tpkmc_handle* h, const StepArgs<real>& a, const tpkmc_outputs*
         }
         {
             PhaseScope ps(h, PH_SEARCH, s, prof);
-            launch_search<real>(a, h->search_kind, h->search_block, h->search_group, s);
+            launch_search<real>(a, h->search_block, h->search_group, s);
         }
         {
             PhaseScope ps(h, PH_MOVE, s, prof);
@@ -626,32 +630,28 @@ int tune_impl(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* i
     hipEventCreate(&e0);
     hipEventCreate(&e1);
     // Results-neutral launch shapes: records per lane (1, 2, 4) and lanes per
-    // work-group (64, 128, 256); in FP32 also the c-bin-centric search.
-    struct Shape { int kind, group, block; };
-    std::vector<Shape> shapes;
-    for (int grp : {1, 2, 4})
-        for (int bs : {256, 128, 64})
-            if (bs <= kBlock / grp) shapes.push_back({SEARCH_LANES, grp, bs});
-    if (std::is_same<real, float>::value)
-        for (int bs : {256, 128, 64}) shapes.push_back({SEARCH_CELLS, kCellsPerWave, bs});
+    // work-group (64, 128, 256).
     float best_ms = 1e30f;
-    Shape best{SEARCH_LANES, 2, kBlock};
-    for (const Shape& sh : shapes) {
-        launch_search<real>(a, sh.kind, sh.block, sh.group, st);  // warm-up
-        hipEventRecord(e0, st);
-        for (int r = 0; r < 3; ++r) launch_search<real>(a, sh.kind, sh.block, sh.group, st);
-        hipEventRecord(e1, st);
-        if (hipEventSynchronize(e1) != hipSuccess) { rc = TPKMC_EHIP; break; }
-        float ms = 0.f;
-        hipEventElapsedTime(&ms, e0, e1);
-        if (ms < best_ms) { best_ms = ms; best = sh; }
+    int best_block = kBlock, best_group = 2;
+    for (int grp : {1, 2, 4}) {
+        for (int bs : {256, 128, 64}) {
+            if (bs > kBlock / grp) continue;
+            launch_search<real>(a, bs, grp, st);  // warm-up
+            hipEventRecord(e0, st);
+            for (int r = 0; r < 3; ++r) launch_search<real>(a, bs, grp, st);
+            hipEventRecord(e1, st);
+            if (hipEventSynchronize(e1) != hipSuccess) { rc = TPKMC_EHIP; break; }
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best_ms) { best_ms = ms; best_block = bs; best_group = grp; }
+        }
+        if (rc) break;
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     if (rc) return rc;
-    h->search_kind = best.kind;
-    h->search_block = best.block;
-    h->search_group = best.group;
+    h->search_block = best_block;
+    h->search_group = best_group;
     h->last_stream = st;
     return hipGetLastError() == hipSuccess ? TPKMC_OK : TPKMC_EHIP;
 }
@@ -806,27 +806,18 @@ int tpkmc_autotune(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instan
                                       : tune_impl<float>(h, s, inst, n_inst, st);
 }
 
-int tpkmc_set_search(tpkmc_handle* h, int32_t kind, int32_t group, int32_t block) {
+int tpkmc_set_search(tpkmc_handle* h, int32_t group, int32_t block) {
     if (!h) return TPKMC_EINVAL;
     if (block != 64 && block != 128 && block != 256) return TPKMC_EINVAL;
-    if (kind == TPKMC_SEARCH_LANES) {
-        if (group != 1 && group != 2 && group != 4) return TPKMC_EINVAL;
-        if (block > kBlock / group) return TPKMC_EINVAL;
-    } else if (kind == TPKMC_SEARCH_CELLS) {
-        if (group != kCellsPerWave) return TPKMC_EINVAL;
-        if (h->precision != TPKMC_FP32) return TPKMC_EUNSUPPORTED;
-    } else {
-        return TPKMC_EINVAL;
-    }
-    h->search_kind = kind;
+    if (group != 1 && group != 2 && group != 4) return TPKMC_EINVAL;
+    if (block > kBlock / group) return TPKMC_EINVAL;
     h->search_group = group;
     h->search_block = block;
     return TPKMC_OK;
 }
 
-int tpkmc_get_search(tpkmc_handle* h, int32_t* kind, int32_t* group, int32_t* block) {
-    if (!h || !kind || !group || !block) return TPKMC_EINVAL;
-    *kind = h->search_kind;
+int tpkmc_get_search(tpkmc_handle* h, int32_t* group, int32_t* block) {
+    if (!h || !group || !block) return TPKMC_EINVAL;
     *group = h->search_group;
     *block = h->search_block;
     return TPKMC_OK;

@@ -35,19 +35,12 @@ struct Inst {
     int32_t chunk0, nchunk;   // range in the chunk table (partials reduction)
     uint32_t seed_lo, seed_hi, step_lo, instance;
     uint32_t flags;           // TPKMC_EMIT_PAIRS | TPKMC_ALLOW_REORDER
-    int32_t pad;
+    int32_t band_log2;        // y-band height 2^band_log2 of the c-bin order
     real lo[3], hi[3], L[3], halfL[3], inv_w[3], inv_wo[3], w[3];
     real dt, D2, mass;
     double mass_d, dt_d;      // dt_d: this step's time step (set on the device with ADAPTIVE_DT)
     double dt_cap, dx_d;      // caller's dt; smallest c-bin width over axes with > 1 c-bin (0: none)
-    int64_t cw0;              // first wave of this instance in the c-bin-centric search
 };
-
-// c-bins per wave of the c-bin-centric search.
-constexpr int kCellsPerWave = 4;
-
-// Search variants (results-neutral; chosen by the autotuner or the caller).
-enum SearchKind { SEARCH_LANES = 0, SEARCH_CELLS = 1 };
 
 // Block table entry: instance index and first particle of the work-group.
 struct Blk {
@@ -83,9 +76,6 @@ struct StepArgs {
     unsigned long long* bkey; // record -> (d_min^2 bits, partner record) (FP32 search)
     double* gpart;            // [nblk][kGPart]
     double* shift;            // per-o-bin velocity shift (3 per o-bin)
-    int32_t n_inst;           // instances of this step
-    int32_t any_periodic;     // some instance has a periodic axis
-    int64_t ncw;              // waves of the c-bin-centric search
     // outputs
     uint32_t* pairs;
     int64_t pair_cap;
@@ -97,7 +87,7 @@ struct StepArgs {
 template <typename real> void launch_key(const StepArgs<real>& a, hipStream_t s);
 template <typename real> void launch_scatter(const StepArgs<real>& a, hipStream_t s);
 template <typename real> void launch_adapt_dt(Inst<real>* inst, const double* gpart, int n_inst, hipStream_t s);
-template <typename real> void launch_search(const StepArgs<real>& a, int kind, int block, int group, hipStream_t s);
+template <typename real> void launch_search(const StepArgs<real>& a, int block, int group, hipStream_t s);
 template <typename real> void launch_move(const StepArgs<real>& a, hipStream_t s);
 
 }  // namespace tpkmc

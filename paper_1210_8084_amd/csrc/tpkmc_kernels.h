@@ -95,6 +95,22 @@ __device__ __forceinline__ int axis_bin(real x, real lo, real inv_w, int n) {
     return (int)t;
 }
 
+// Row (y, z) of c-bins as its index in the c-bin order, in units of rows
+// (the c-bin index is x + n_x * row).  The order is band-major: the y axis is
+// cut into bands of 2^band_log2 rows, and within a band the rows run z-major.
+// A sweep over consecutive c-bins (one XCD's share of the work-groups) thus
+// stays inside one band while it walks through the planes.  The records of the
+// next plane, which the neighbourhood walk reads again one plane later, are
+// then a band plane away instead of a whole plane.  With one band this is the
+// plain y + n_y z.
+template <typename real>
+__device__ __forceinline__ int row_of(const Inst<real>& I, int y, int z) {
+    const int h = I.band_log2;
+    const int y0 = (y >> h) << h;                 // first row of y's band
+    const int rows = min(1 << h, I.n[1] - y0);    // rows in that band
+    return y0 * I.n[2] + (y - y0) + rows * z;
+}
+
 template <typename real>
 __device__ __forceinline__ bool finite3(real a, real b, real c) {
     return isfinite(a) && isfinite(b) && isfinite(c);
@@ -235,7 +251,7 @@ __global__ void __launch_bounds__(kBlock) k_key(StepArgs<real> a) {
             const int cx = axis_bin(x, I.lo[0], I.inv_w[0], I.n[0]);
             const int cy = axis_bin(y, I.lo[1], I.inv_w[1], I.n[1]);
             const int cz = axis_bin(z, I.lo[2], I.inv_w[2], I.n[2]);
-            key = (int)I.cell_off + cx + I.n[0] * (cy + I.n[1] * cz);
+            key = (int)I.cell_off + cx + I.n[0] * row_of(I, cy, cz);
             if (adaptive) v2 = speed2((double)vx, (double)vy, (double)vz);
         } else {
             key = (int)(I.cell_off + I.C);
@@ -395,6 +411,15 @@ template <bool PER> struct PairTest<float, PER> {
         const float cz = fmaf(S.rx, S.uy, -S.ry * S.ux);
         return fmaf(cz, cz, fmaf(cy, cy, cx * cx)) / S.vv;
     }
+    // First contact of the effective radii: the earlier root of
+    // |u|^2 t^2 + 2 (u.r) t + |r|^2 - D^2 = 0 (a rounding below zero of the
+    // discriminant is taken as 0).
+    static __device__ __forceinline__ float contact(const Geo<float>& G, const Screen<float>& S) {
+        const float rr = fmaf(S.rz, S.rz, fmaf(S.ry, S.ry, S.rx * S.rx));
+        float disc = fmaf(S.s0, S.s0, -S.vv * (rr - G.D2));
+        disc = disc > 0.0f ? disc : 0.0f;
+        return (-S.s0 - sqrtf(disc)) / S.vv;
+    }
 };
 
 template <bool PER> struct PairTest<double, PER> {
@@ -427,7 +452,20 @@ template <bool PER> struct PairTest<double, PER> {
         const double d2 = (px * px + py * py) + pz * pz;
         return d2 <= G.D2 ? d2 : -1.0;
     }
+    // First contact time, with the reference's expression and order.
+    static __device__ __forceinline__ double contact(const Geo<double>& G, const Screen<double>& S) {
+        const double rr = (S.rx * S.rx + S.ry * S.ry) + S.rz * S.rz;
+        double disc = S.s0 * S.s0 - S.vv * (rr - G.D2);
+        if (!(disc > 0.0)) disc = 0.0;
+        return (-S.s0 - sqrt(disc)) / S.vv;
+    }
 };
+
+// Order-preserving map of a float onto uint32 (negative values included).
+__device__ __forceinline__ uint32_t sortable(float v) {
+    const uint32_t b = __float_as_uint(v);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
 
 // Neighbour index along one axis (offset d in -1..1): whether it exists and
 // is not a repeat of another offset (periodic axes with 1 or 2 bins), and the
@@ -474,18 +512,19 @@ __device__ __forceinline__ int cz_of(real z, const Inst<real>& I) { return axis_
 // Visits the record ranges of the neighbourhood of record i (bin cx, cy, cz).
 // HALF: only pairs (i, j) not visited from j's side -- bins of larger index
 // and, in i's own bin, records after i -- so every unordered pair is met once.
-template <bool HALF, typename F>
-__device__ __forceinline__ void for_neighbourhood(const int32_t* start, int64_t cell_off, int64_t base,
+template <bool HALF, typename real, typename F>
+__device__ __forceinline__ void for_neighbourhood(const int32_t* start, const Inst<real>& I, int64_t base,
                                                   const int n[3], const bool per[3], int cx, int cy, int cz,
                                                   int32_t i, F&& visit) {
+    const int64_t cell_off = I.cell_off;
     int xa[2], xb[2];
     const int nxr = x_ranges(cx, n[0], per[0], xa, xb);
-    const int own_row = cy + n[1] * cz;
+    const int own_row = row_of(I, cy, cz);
     for (int k = 0; k < 9; ++k) {
         int y, z;
         if (!axis_nb(cz, k / 3 - 1, n[2], per[2], z)) continue;
         if (!axis_nb(cy, k % 3 - 1, n[1], per[1], y)) continue;
-        const int row_idx = y + n[1] * z;
+        const int row_idx = row_of(I, y, z);
         if (HALF && row_idx < own_row) continue;
         const bool own = row_idx == own_row;
         const int64_t row = cell_off + (int64_t)n[0] * row_idx;
@@ -565,19 +604,23 @@ __device__ __forceinline__ void search_group(const StepArgs<real>& a, const Inst
 #pragma unroll
     for (int k = 0; k < G; ++k) { mine[k] = ~0ull; bj[k] = -1; bd2[k] = real(0); bid[k] = 0; }
 
-    // Bookkeeping of a pair that passed both screening stages (rare).
+    // Bookkeeping of a pair that passed both screening stages (rare).  The
+    // ranking key of criterion 3 is d_min^2, or with TPKMC_RANK_TIME the
+    // first contact time.
+    const bool by_time = (I.flags & TPKMC_RANK_TIME) != 0;
     auto hit = [&](int k, int32_t j, uint32_t idj, const Screen<real>& S) {
         const real d2 = PairTest<real, PER>::finish(G_, S);
         if (d2 >= real(0)) {
             ++nc;
+            const real key = by_time ? PairTest<real, PER>::contact(G_, S) : d2;
             if constexpr (HALF) {
-                const unsigned long long hi = (unsigned long long)__float_as_uint((float)d2) << 32;
+                const unsigned long long hi = (unsigned long long)sortable((float)key) << 32;
                 atomicMin(a.bkey + j, hi | (uint32_t)(i0 + k));
-                const unsigned long long key = hi | (uint32_t)j;
-                mine[k] = key < mine[k] ? key : mine[k];
+                const unsigned long long kk = hi | (uint32_t)j;
+                mine[k] = kk < mine[k] ? kk : mine[k];
             } else {
-                if (bj[k] < 0 || d2 < bd2[k] || (d2 == bd2[k] && idj < bid[k])) {
-                    bj[k] = j; bd2[k] = d2; bid[k] = idj;
+                if (bj[k] < 0 || key < bd2[k] || (key == bd2[k] && idj < bid[k])) {
+                    bj[k] = j; bd2[k] = key; bid[k] = idj;
                 }
             }
         }
@@ -623,7 +666,7 @@ __device__ __forceinline__ void search_group(const StepArgs<real>& a, const Inst
         // UNIFORM: every lane of the wave shares the row and walks the union
         // of the wave's ranges (first record's lower end, wave_ub upper end)
         // in lock-step, so j is the same in all lanes.
-        const int own_row = cy + n[1] * cz;
+        const int own_row = row_of(I, cy, cz);
         const int ua = UNIFORM ? __builtin_amdgcn_readfirstlane(x_lo_of(wave_first, a, I, n[0], G_.per[0])) : xa[0];
         int ub = xb[0];
 #pragma unroll
@@ -634,7 +677,7 @@ __device__ __forceinline__ void search_group(const StepArgs<real>& a, const Inst
             int y, z;
             if (!axis_nb(cz, rr / 3 - 1, n[2], G_.per[2], z)) continue;
             if (!axis_nb(cy, rr % 3 - 1, n[1], G_.per[1], y)) continue;
-            const int row_idx = y + n[1] * z;
+            const int row_idx = row_of(I, y, z);
             if (HALF && row_idx < own_row) continue;
             const bool own = HALF && row_idx == own_row;
             const int64_t row = I.cell_off + (int64_t)n[0] * row_idx;
@@ -664,7 +707,7 @@ __device__ __forceinline__ void search_group(const StepArgs<real>& a, const Inst
         for (int k = 0; k < G; ++k) {
             if (k >= nrec) continue;
             const int32_t ik = i0 + k;
-            for_neighbourhood<HALF>(a.start, I.cell_off, base, n, G_.per, cxk[k], cy_of(yi[k], I), cz_of(zi[k], I),
+            for_neighbourhood<HALF>(a.start, I, base, n, G_.per, cxk[k], cy_of(yi[k], I), cz_of(zi[k], I),
                                     ik, [&](int32_t j0, int32_t j1) {
                 seen += j1 > j0 ? j1 - j0 : 0;
                 for (int32_t j = j0; j < j1; ++j) {
@@ -760,134 +803,6 @@ __global__ void __launch_bounds__(256) k_search(StepArgs<real> a) {
             unsafeAtomicAdd(gp + GP_TESTS2, 2.0 * t);
             unsafeAtomicAdd(gp + GP_CAND, c);
         }
-    }
-}
-
-// c-bin-centric half search (FP32).  One wave takes kCellsPerWave
-// consecutive c-bins.  For a c-bin c, the candidates are the records of the
-// neighbour c-bins of index >= c: up to two x-ranges in each of up to nine
-// rows.  They are flattened into one list and dealt to the 64 lanes, one
-// chunk of 64 at a time, and each lane keeps its candidate in registers.  The
-// c-bin's own records then stream through scalar registers, one at a time.
-// Every pair (i, j) with j > i in that list is tested once, the own c-bin
-// included, which is exactly the pair set, orientation and arithmetic of the
-// lane-per-record search.  Keys and counts therefore come out identical.
-// Compared with that search, this one has no per-pair address arithmetic, no
-// per-lane loop bounds (the loop is over the uniform i), and each candidate
-// record is loaded once per c-bin instead of once per record.
-template <bool PER>
-__device__ __forceinline__ void search_cell(const StepArgs<float>& a, const Inst<float>& I, const Geo<float>& G_,
-                                            int64_t base, int c, int lane, int32_t* rpre, int32_t* rdel,
-                                            uint64_t& tests, uint32_t& ncand) {
-    typedef __attribute__((address_space(4))) const int32_t cint;
-    const cint* st = (const cint*)a.start;
-    const int nx = I.n[0], ny = I.n[1], nz = I.n[2];
-    const int cx = c % nx, rest = c / nx;
-    const int cy = rest % ny, cz = rest / ny;
-    const int64_t co = I.cell_off;
-    const int32_t i_lo = (int32_t)(base + st[co + c]);
-    const int32_t i_hi = (int32_t)(base + st[co + c + 1]);
-    if (i_hi <= i_lo) return;
-    int xa[2], xb[2];
-    const int nxr = x_ranges(cx, nx, G_.per[0], xa, xb);
-    const int own_row = cy + ny * cz;
-    // Candidate list: range r holds list positions [rpre[r], rpre[r+1]) and
-    // record index = list position + rdel[r] (kept in this wave's LDS).
-    int nr = 0;
-    int32_t tot = 0;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        int y = 0, z = 0;
-        bool ok = axis_nb(cz, k / 3 - 1, nz, G_.per[2], z);
-        ok = ok && axis_nb(cy, k % 3 - 1, ny, G_.per[1], y);
-        const int row_idx = y + ny * z;
-        ok = ok && row_idx >= own_row;
-        const bool own = row_idx == own_row;
-        const int64_t row = co + (int64_t)nx * row_idx;
-#pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            bool use = ok && r < nxr;
-            int x0 = xa[r];
-            if (own) {
-                if (r == 0) x0 = cx;               // the own c-bin and those after it
-                else use = use && xa[r] > cx;      // a wrapped range above cx
-            }
-            if (use) {
-                const int32_t j0 = (int32_t)(base + st[row + x0]);
-                const int32_t j1 = (int32_t)(base + st[row + xb[r] + 1]);
-                if (j1 > j0) {
-                    if (lane == 0) { rpre[nr] = tot; rdel[nr] = j0 - tot; }
-                    ++nr;
-                    tot += j1 - j0;
-                }
-            }
-        }
-    }
-    // Pairs met: every own record i with every listed j > i.
-    const uint64_t m = (uint64_t)(i_hi - i_lo);
-    tests += m * (uint64_t)tot - m * (m + 1u) / 2u;
-    __builtin_amdgcn_wave_barrier();
-    for (int32_t q = 0; q < tot; q += 64) {
-        const int32_t f = q + lane;
-        const bool valid = f < tot;
-        int32_t j = i_lo;
-        for (int r = 0; r < nr; ++r)
-            if (f >= rpre[r]) j = f + rdel[r];
-        if (!valid) j = i_lo;
-        float xj, yj, zj, vxj, vyj, vzj;
-        Rec<float>::load6(a.rec, (uint32_t)j, xj, yj, zj, vxj, vyj, vzj);
-        for (int32_t i = i_lo; i < i_hi; ++i) {
-            float xi, yi, zi, vxi, vyi, vzi;
-            uint32_t idi;
-            RecU<float>::load(a.rec, i, xi, yi, zi, idi, vxi, vyi, vzi);
-            Screen<float> S;
-            const bool s1 = PairTest<float, PER>::stage1(G_, xi, yi, zi, vxi, vyi, vzi, xj, yj, zj, vxj, vyj, vzj, S);
-            const bool p1 = s1 && valid && j > i;
-            if (__builtin_amdgcn_ballot_w64(p1) == 0) continue;
-            const bool p2 = p1 && PairTest<float, PER>::stage2(G_, S);
-            bool hit = false;
-            if (p2) {
-                const float d2 = PairTest<float, PER>::finish(G_, S);
-                if (d2 >= 0.0f) {
-                    hit = true;
-                    const unsigned long long hk = (unsigned long long)__float_as_uint(d2) << 32;
-                    atomicMin(a.bkey + j, hk | (uint32_t)i);
-                    atomicMin(a.bkey + i, hk | (uint32_t)j);
-                }
-            }
-            ncand += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(hit));
-        }
-    }
-    __builtin_amdgcn_wave_barrier();
-}
-
-template <bool PER>
-__global__ void __launch_bounds__(256) k_search_cells(StepArgs<float> a) {
-    const int wpb = (int)(blockDim.x >> 6);
-    const int wib = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int lane = threadIdx.x & 63;
-    const int64_t w = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * wpb + wib;
-    if (w >= a.ncw) return;
-    int lo = 0, hi = a.n_inst - 1;  // the last instance with cw0 <= w
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (a.inst[mid].cw0 <= w) lo = mid; else hi = mid - 1;
-    }
-    const Inst<float>& I = a.inst[lo];
-    const Geo<float> G_(I);
-    const int64_t base = I.off - a.start[I.cell_off];
-    const int c0 = (int)(w - I.cw0) * kCellsPerWave;
-    const int c1 = c0 + kCellsPerWave < I.C ? c0 + kCellsPerWave : I.C;
-    __shared__ int32_t rpre[4][18], rdel[4][18];
-    uint64_t tests = 0;
-    uint32_t ncand = 0;
-    for (int c = c0; c < c1; ++c)
-        search_cell<PER>(a, I, G_, base, c, lane, rpre[wib], rdel[wib], tests, ncand);
-    if (lane == 0 && (tests | ncand)) {
-        // Spread over the instance's partial slots (summed per instance).
-        double* gp = a.gpart + (int64_t)(I.blk0 + (int)(w % I.nblk)) * kGPart;
-        unsafeAtomicAdd(gp + GP_TESTS2, 2.0 * (double)tests);
-        unsafeAtomicAdd(gp + GP_CAND, 2.0 * (double)ncand);
     }
 }
 
@@ -1145,19 +1060,8 @@ void launch_adapt_dt(Inst<real>* inst, const double* gpart, int n_inst, hipStrea
     hipLaunchKernelGGL(k_adapt_dt<real>, dim3(n_inst), dim3(256), 0, s, inst, gpart);
 }
 template <typename real>
-void launch_search(const StepArgs<real>& a, int kind, int block, int group, hipStream_t s) {
+void launch_search(const StepArgs<real>& a, int block, int group, hipStream_t s) {
     constexpr bool half = std::is_same<real, float>::value;
-    if constexpr (half) {
-        if (kind == SEARCH_CELLS) {
-            if (a.ncw <= 0) return;
-            const int wpb = block / kWave;
-            const unsigned grid = (unsigned)((a.ncw + wpb - 1) / wpb);
-            // Any periodic axis in the batch selects the minimum-image variant.
-            if (a.any_periodic) hipLaunchKernelGGL(k_search_cells<true>, dim3(grid), dim3(block), 0, s, a);
-            else hipLaunchKernelGGL(k_search_cells<false>, dim3(grid), dim3(block), 0, s, a);
-            return;
-        }
-    }
     const int lanes = kBlock / group;
     const int bs = block < lanes ? block : lanes;
     const unsigned grid = (unsigned)a.nblk * (unsigned)(lanes / bs);

@@ -22,11 +22,10 @@ LIB_PATH = os.path.join(HERE, "libtpkmc.so")
 
 FP64, FP32 = 0, 1
 REFLECT, PERIODIC, ABSORB = 0, 1, 2
-EMIT_PAIRS, ALLOW_REORDER, ADAPTIVE_DT, PLANAR = 1, 2, 4, 8
+EMIT_PAIRS, ALLOW_REORDER, ADAPTIVE_DT, PLANAR, RANK_TIME = 1, 2, 4, 8, 16
 STATUS_PAIR_OVERFLOW, STATUS_NONFINITE, STATUS_FAST = 1, 2, 4
 CNT = dict(alive=0, pairs=1, tests=2, cand=3, fast=4, nonfinite=5, absorbed=6, have_best=7)
 GLB = dict(px=0, py=1, pz=2, ekin=3, vmax2=4, virial=5, mass=6, dt=7)
-SEARCH_LANES, SEARCH_CELLS = 0, 1
 PHASES = ("clear", "key", "scan", "scatter", "search", "move", "finalize")
 MOMENT_STRIDE = 11
 
@@ -94,8 +93,8 @@ def lib():
         L.tpkmc_status.argtypes = [_P, _P]
         L.tpkmc_profile_enable.argtypes = [_P, ctypes.c_int32]
         L.tpkmc_profile_read.argtypes = [_P, _P, _P, ctypes.c_int32]
-        L.tpkmc_set_search.argtypes = [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
-        L.tpkmc_get_search.argtypes = [_P, _P, _P, _P]
+        L.tpkmc_set_search.argtypes = [_P, ctypes.c_int32, ctypes.c_int32]
+        L.tpkmc_get_search.argtypes = [_P, _P, _P]
         for f in ("tpkmc_create", "tpkmc_destroy", "tpkmc_step", "tpkmc_step_batched", "tpkmc_run",
                   "tpkmc_autotune", "tpkmc_status", "tpkmc_profile_enable", "tpkmc_profile_read",
                   "tpkmc_set_search", "tpkmc_get_search"):
@@ -134,6 +133,8 @@ def make_params(p, flags=0) -> Params:
         P.flags |= ADAPTIVE_DT
     if p.get("planar"):
         P.flags |= PLANAR
+    if p.get("rank_time"):
+        P.flags |= RANK_TIME
     return P
 
 
@@ -291,16 +292,15 @@ class Engine:
         _check(lib().tpkmc_autotune(self.h, ctypes.byref(S), arr, len(specs), _P(_stream_ptr(stream))),
                "tpkmc_autotune")
 
-    def set_search(self, kind, group, block):
-        """Fix the partner-search variant (SEARCH_LANES with group 1, 2, 4 or
-        SEARCH_CELLS with group 4; block 64, 128 or 256 lanes)."""
-        _check(lib().tpkmc_set_search(self.h, int(kind), int(group), int(block)), "tpkmc_set_search")
+    def set_search(self, group, block):
+        """Fix the partner-search launch shape: `group` records per lane (1, 2
+        or 4) and `block` lanes per work-group (64, 128 or 256)."""
+        _check(lib().tpkmc_set_search(self.h, int(group), int(block)), "tpkmc_set_search")
 
     def get_search(self):
-        k, g, b = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
-        _check(lib().tpkmc_get_search(self.h, ctypes.byref(k), ctypes.byref(g), ctypes.byref(b)),
-               "tpkmc_get_search")
-        return int(k.value), int(g.value), int(b.value)
+        g, b = ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(lib().tpkmc_get_search(self.h, ctypes.byref(g), ctypes.byref(b)), "tpkmc_get_search")
+        return int(g.value), int(b.value)
 
     def status(self) -> int:
         v = ctypes.c_int32(0)

@@ -516,27 +516,26 @@ def test_planar_needs_one_bin_along_z(T):
     eng.close()
 
 
-# ------------------------------------------------------------ search variants
-VARIANTS = [(0, 1, 256), (0, 2, 128), (0, 4, 64), (1, 4, 256), (1, 4, 64)]
+# ------------------------------------------------------------ search shapes
+SHAPES = [(1, 256), (2, 128), (2, 64), (4, 64)]
 
 
-def _fp32_run(T, w, variant, steps=2, flags=None):
+def _fp32_run(T, w, shape, steps=2):
     eng = engine_for(T, w, T.FP32)
-    if variant is not None:
-        eng.set_search(*variant)
-        assert eng.get_search() == variant
+    eng.set_search(*shape)
+    assert eng.get_search() == shape
     dst = T.to_device(W.copy_state(w.state, dtype=np.float32), T.FP32)
     out = T.make_outputs(1, T.nobins(w.grid), pair_cap=w.n)
     hs = []
     for s in range(steps):
-        eng.step(dst, w.grid, dict(w.params, step=s), out, flags=T.EMIT_PAIRS if flags is None else flags)
+        eng.step(dst, w.grid, dict(w.params, step=s), out, flags=T.EMIT_PAIRS)
         torch.cuda.synchronize()
         hs.append(out.host())
     eng.close()
     return T.to_host(dst), hs
 
 
-VARIANT_CASES = [
+SHAPE_CASES = [
     dict(seed=51, ncell=(7, 5, 4), bc=(R, P, P)),
     dict(seed=52, ncell=(3, 3, 3), bc=(P, P, P)),
     dict(seed=53, ncell=(2, 1, 6), bc=(P, P, R)),
@@ -546,15 +545,15 @@ VARIANT_CASES = [
 ]
 
 
-@pytest.mark.parametrize("case", VARIANT_CASES, ids=lambda c: f"s{c['seed']}-{c['ncell']}-{c['bc']}")
-def test_fp32_search_variants_are_identical(T, case):
-    """Every partner-search layout (records per lane, work-group size, the
-    c-bin-centric search) gives the same pairs, state and counters."""
+@pytest.mark.parametrize("case", SHAPE_CASES, ids=lambda c: f"s{c['seed']}-{c['ncell']}-{c['bc']}")
+def test_fp32_search_shapes_are_identical(T, case):
+    """Every launch shape of the FP32 partner search (records per lane,
+    work-group size) gives the same pairs, state and counters."""
     w = W.random_box(n=3001, seed=case["seed"], ncell=case["ncell"], bc=case["bc"], d_over_w=0.7, dt_over=0.5)
-    _say(f"variants case {case}")
-    ref_state, ref_out = _fp32_run(T, w, VARIANTS[0])
+    _say(f"shapes case {case}")
+    ref_state, ref_out = _fp32_run(T, w, SHAPES[0])
     assert ref_out[0]["counters"][0][1] > 50
-    for v in VARIANTS[1:]:
+    for v in SHAPES[1:]:
         st, outs = _fp32_run(T, w, v)
         for k in ("x", "y", "z", "vx", "vy", "vz"):
             assert np.array_equal(st[k], ref_state[k]), (v, k)
@@ -563,48 +562,43 @@ def test_fp32_search_variants_are_identical(T, case):
             assert pairset(o["pairs"]) == pairset(r["pairs"]), v
 
 
-def test_fp32_cell_search_on_a_batch_with_an_empty_instance(T):
-    """The c-bin-centric search finds each wave's instance from its index:
-    a batch with an empty instance in the middle equals the lane search."""
-    ws = [W.random_box(n=2500, seed=61, ncell=(5, 4, 3), bc=(R, P, P), d_over_w=0.7, dt_over=0.5),
-          W.random_box(n=0, seed=62, ncell=(3, 3, 3)),
-          W.random_plane(n=2000, seed=63, ncell=(6, 5), d_over_w=0.7, dt_over=0.5),
-          W.random_box(n=1500, seed=64, ncell=(2, 2, 2), bc=(P, P, P), d_over_w=0.7, dt_over=0.5)]
-    for k, w in enumerate(ws):
-        w.params["instance"] = k
-    st, specs = _concat(ws)
-    n = len(st["x"])
-    kw = dict(max_particles=n, max_cells=sum(T.ncells(w.grid) + 1 for w in ws),
-              max_obins=sum(T.nobins(w.grid) for w in ws), precision=T.FP32, max_instances=len(ws))
-    res = []
-    for v in ((0, 2, 256), (1, 4, 128)):
-        eng = T.Engine(**kw)
-        eng.set_search(*v)
-        dst = T.to_device(W.copy_state(st, dtype=np.float32) | {"id": st["id"]}, T.FP32)
-        out = T.make_outputs(len(ws), kw["max_obins"], pair_cap=n)
-        eng.step_batched(dst, specs, out, flags=T.EMIT_PAIRS)
-        torch.cuda.synchronize()
-        res.append((T.to_host(dst), out.host()))
-        eng.close()
-    (s0, o0), (s1, o1) = res
-    for k in ("x", "y", "z", "vx", "vy", "vz"):
-        assert np.array_equal(s0[k], s1[k])
-    assert o0["counters"].tolist() == o1["counters"].tolist()
-    assert pairset(o0["pairs"]) == pairset(o1["pairs"])
-    assert o0["counters"][0][1] > 50 and o0["counters"][1][0] == 0
-
-
-def test_search_variant_arguments(T):
+def test_search_shape_arguments(T):
     w = W.random_box(n=100, seed=65)
-    e32, e64 = engine_for(T, w, T.FP32), engine_for(T, w, T.FP64)
-    with pytest.raises(T.TpkmcError):
-        e32.set_search(0, 3, 64)
-    with pytest.raises(T.TpkmcError):
-        e32.set_search(0, 4, 256)
-    with pytest.raises(T.TpkmcError):
-        e32.set_search(1, 2, 64)
-    with pytest.raises(T.TpkmcError):
-        e64.set_search(1, 4, 64)
-    e64.set_search(0, 1, 64)
-    assert e64.get_search() == (0, 1, 64)
-    e32.close(); e64.close()
+    eng = engine_for(T, w, T.FP32)
+    for bad in ((3, 64), (4, 256), (2, 32), (0, 64)):
+        with pytest.raises(T.TpkmcError):
+            eng.set_search(*bad)
+    eng.set_search(1, 64)
+    assert eng.get_search() == (1, 64)
+    eng.close()
+
+
+# ------------------------------------------------------------ criterion 3 by time
+@pytest.mark.parametrize("case", CASES[:4] + [CASES[6]], ids=lambda c: f"s{c['seed']}-{c['ncell']}-{c['bc']}")
+def test_fp64_rank_by_contact_time_bit_exact(T, oracle, case):
+    """Criterion 3 by earliest contact (TPKMC_RANK_TIME): the same pairs and
+    state as the oracle, bit for bit, over two steps."""
+    w = W.random_box(n=2500, seed=case["seed"] + 70, ncell=case["ncell"], bc=case["bc"], d_over_w=0.8,
+                     dt_over=0.6, nobin=(3, 2, 1))
+    w.params = dict(w.params, rank_time=True)
+    _say(f"rank-time case {case}")
+    got, gouts, _ = gpu_steps(T, w, T.FP64, steps=2)
+    want, routs = oracle_steps(oracle, w, steps=2)
+    assert_state_equal(got, want)
+    for go, ro in zip(gouts, routs):
+        assert_outputs_match(go, ro, w.params["mass"])
+    assert routs[0]["counters"][1] > 50
+
+
+def test_fp32_rank_by_contact_time(T, oracle):
+    """FP32 with the time ranking: every launch shape agrees, and the pair
+    count tracks the FP64 oracle's."""
+    w = W.random_box(n=20000, seed=77, ncell=(10, 8, 6), bc=(P, P, R), d_over_w=0.8, dt_over=0.6)
+    w.params = dict(w.params, rank_time=True)
+    s0, o0 = _fp32_run(T, w, (2, 128), steps=1)
+    s1, o1 = _fp32_run(T, w, (1, 64), steps=1)
+    assert pairset(o0[0]["pairs"]) == pairset(o1[0]["pairs"])
+    ro = oracle.step(W.copy_state(W.copy_state(w.state, dtype=np.float32)), w.grid, w.params)
+    assert o0[0]["counters"][0][1] == pytest.approx(ro["counters"][1], rel=0.02)
+    common = set(pairset(o0[0]["pairs"])) & set(pairset(ro["pairs"]))
+    assert len(common) > 0.97 * len(ro["pairs"])
