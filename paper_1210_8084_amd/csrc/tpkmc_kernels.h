@@ -818,7 +818,7 @@ template <> __device__ __forceinline__ int32_t partner_of<float>(const StepArgs<
 }
 
 // Work-group table of o-bin sums, flushed with one atomic per value per bin.
-constexpr int kSlots = 128;
+constexpr int kSlots = 64;
 struct MomentTable {
     int key[kSlots];
     double val[kSlots][TPKMC_MOMENT_STRIDE];
@@ -839,174 +839,216 @@ __device__ __forceinline__ int table_slot(MomentTable& T, int ob) {
 }
 
 // Unambiguous pairs (each the other's closest candidate) scatter; every
-// particle moves and meets the walls; o-bin moments and global sums.
+// particle moves and meets the walls; o-bin moments and global sums.  Each
+// lane takes kMoveRec consecutive records: records in c-bin order come in
+// runs of one o-bin, so a lane sums its run in registers and touches the
+// work-group's o-bin table only when the o-bin changes, and the global sums
+// are reduced once per kMoveRec records.  The next record is loaded while the
+// current one is processed.  Two records per lane balance these savings
+// against the coalescing and occupancy of one record per lane.
+constexpr int kMoveRec = 2;
+constexpr int kMoveLanes = kBlock / kMoveRec;
+
 template <typename real>
-__global__ void __launch_bounds__(kBlock) k_move(StepArgs<real> a) {
-    __shared__ double red[16 * 11];
+__device__ __forceinline__ void moment_flush(MomentTable& tab, const StepArgs<real>& a, int ob, const double* mv) {
+    const int slot = table_slot(tab, ob);
+    double* dst = slot >= 0 ? tab.val[slot] : a.moments + (int64_t)ob * TPKMC_MOMENT_STRIDE;
+#pragma unroll
+    for (int k = 0; k < TPKMC_MOMENT_STRIDE; ++k)
+        if (k < 7 || mv[k] != 0.0) unsafeAtomicAdd(dst + k, mv[k]);
+}
+
+template <typename real>
+__global__ void __launch_bounds__(kMoveLanes) k_move(StepArgs<real> a) {
     __shared__ MomentTable tab;
+    __shared__ double red[kMoveLanes / 64][11];
     const Blk bt = a.blk[blockIdx.x];
     const Inst<real>& I = a.inst[bt.inst];
-    const int64_t i = (int64_t)bt.first + threadIdx.x;
-    const bool in = i < I.off + I.cnt;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int64_t end = I.off + I.cnt;
     const bool reorder = (I.flags & TPKMC_ALLOW_REORDER) != 0;
     if (a.moments) {
-        for (int t = threadIdx.x; t < kSlots; t += blockDim.x) {
+        for (int t = tid; t < kSlots; t += kMoveLanes) {
             tab.key[t] = -1;
             for (int k = 0; k < TPKMC_MOMENT_STRIDE; ++k) tab.val[t][k] = 0.0;
         }
         __syncthreads();
     }
     double gpx = 0, gpy = 0, gpz = 0, gek = 0, gvm = 0, gvir = 0, gm = 0, galive = 0, gpairs = 0, gabs = 0, ghave = 0;
-    bool emit = false;
-    uint32_t emit_a = 0, emit_b = 0;
-    if (in) {
-        real x, y, z, vx, vy, vz;
-        uint32_t idi, fl;
-        Rec<real>::load(a.rec, i, x, y, z, idi, vx, vy, vz, fl);
-        const int64_t dst = reorder ? i : (int64_t)a.src[i];
-        const bool alive = (fl & 1u) != 0;
-        if (!alive) {
-            if (reorder) {
-                a.x[dst] = x; a.y[dst] = y; a.z[dst] = z;
-                a.vx[dst] = vx; a.vy[dst] = vy; a.vz[dst] = vz;
-                a.id[dst] = idi;
-                if (a.alive) a.alive[dst] = 0;
-            }
-        } else {
-            const real dt = I.dt;
-            const int32_t j = partner_of<real>(a, i);
-            const bool mutual = j >= 0 && partner_of<real>(a, j) == (int32_t)i;
-            ghave = j >= 0 ? 1.0 : 0.0;
-            real nx = x, ny = y, nz = z, nvx = vx, nvy = vy, nvz = vz;
-            double virx = 0, viry = 0, virz = 0;
-            if (mutual) {
-                real xj, yj, zj, vxj, vyj, vzj;
-                uint32_t idj, flj;
-                Rec<real>::load(a.rec, j, xj, yj, zj, idj, vxj, vyj, vzj, flj);
-                const bool isA = idi < idj;
-                // Pair quantities with A = lower id, B = higher id.
-                const real xA = isA ? x : xj, yA = isA ? y : yj, zA = isA ? z : zj;
-                const real xB = isA ? xj : x, yB = isA ? yj : y, zB = isA ? zj : z;
-                const real vxA = isA ? vx : vxj, vyA = isA ? vy : vyj, vzA = isA ? vz : vzj;
-                const real vxB = isA ? vxj : vx, vyB = isA ? vyj : vy, vzB = isA ? vzj : vz;
-                real rx = xA - xB, ry = yA - yB, rz = zA - zB;
-                if (I.bc[0] == TPKMC_BC_PERIODIC) rx = min_image(rx, I.L[0], I.halfL[0]);
-                if (I.bc[1] == TPKMC_BC_PERIODIC) ry = min_image(ry, I.L[1], I.halfL[1]);
-                if (I.bc[2] == TPKMC_BC_PERIODIC) rz = min_image(rz, I.L[2], I.halfL[2]);
-                const real ux = vxA - vxB, uy = vyA - vyB, uz = vzA - vzB;
-                const real s0 = (rx * ux + ry * uy) + rz * uz;
-                const real vv = (ux * ux + uy * uy) + uz * uz;
-                const real tp = -s0 / vv;
-                double nh[3];
-                pair_direction(I.seed_lo, I.seed_hi, I.step_lo, I.instance, isA ? idi : idj, isA ? idj : idi,
-                               (I.flags & TPKMC_PLANAR) != 0, nh);
-                // Equal masses: centre-of-mass velocity kept, relative speed g
-                // kept, outgoing directions opposite along nhat.
-                const real g = sqrt(vv);
-                const real h = real(0.5) * g;
-                const real sg = isA ? real(1) : real(-1);
-                const real cmx = real(0.5) * (vxA + vxB), cmy = real(0.5) * (vyA + vyB), cmz = real(0.5) * (vzA + vzB);
-                const real hx = h * (real)nh[0], hy = h * (real)nh[1], hz = h * (real)nh[2];
-                nvx = isA ? cmx + hx : cmx - hx;
-                nvy = isA ? cmy + hy : cmy - hy;
-                nvz = isA ? cmz + hz : cmz - hz;
-                // Split move at the point of closest approach.
-                const real rest = dt - tp;
-                nx = (x + vx * tp) + nvx * rest;
-                ny = (y + vy * tp) + nvy * rest;
-                nz = (z + vz * tp) + nvz * rest;
-                // Virial: separation at closest approach (from the partner to
-                // this particle) times this particle's momentum change.
-                const real sx = sg * (rx + tp * ux), sy = sg * (ry + tp * uy), sz = sg * (rz + tp * uz);
-                virx = (double)(real(0.5) * sx * (I.mass * (nvx - vx)) / dt);
-                viry = (double)(real(0.5) * sy * (I.mass * (nvy - vy)) / dt);
-                virz = (double)(real(0.5) * sz * (I.mass * (nvz - vz)) / dt);
-                if (isA) {
-                    gpairs = 1.0;
-                    if (I.flags & TPKMC_EMIT_PAIRS) { emit = true; emit_a = idi; emit_b = idj; }
+    int mob = -1;                              // o-bin of the run being summed
+    double shx = 0, shy = 0, shz = 0;          // its velocity shift
+    double mv[TPKMC_MOMENT_STRIDE];            // its sums
+#pragma unroll
+    for (int k = 0; k < TPKMC_MOMENT_STRIDE; ++k) mv[k] = 0.0;
+    // The next record and its partner key are loaded while the current one
+    // is processed (two records in flight per lane).
+    const int64_t i_first = (int64_t)bt.first + kMoveRec * tid;
+    real nx_ = 0, ny_ = 0, nz_ = 0, nvx_ = 0, nvy_ = 0, nvz_ = 0;
+    uint32_t nid_ = 0, nfl_ = 0;
+    int32_t npj_ = -1;
+    if (i_first < end) {
+        Rec<real>::load(a.rec, i_first, nx_, ny_, nz_, nid_, nvx_, nvy_, nvz_, nfl_);
+        npj_ = partner_of<real>(a, i_first);
+    }
+#pragma unroll 1
+    for (int r = 0; r < kMoveRec; ++r) {
+        const int64_t i = i_first + r;
+        bool emit = false;
+        uint32_t emit_a = 0, emit_b = 0;
+        const real x = nx_, y = ny_, z = nz_, vx = nvx_, vy = nvy_, vz = nvz_;
+        const uint32_t idi = nid_, fl = nfl_;
+        const int32_t j_pre = npj_;
+        if (r + 1 < kMoveRec && i + 1 < end) {
+            Rec<real>::load(a.rec, i + 1, nx_, ny_, nz_, nid_, nvx_, nvy_, nvz_, nfl_);
+            npj_ = partner_of<real>(a, i + 1);
+        }
+        if (i < end) {
+            const int64_t dst = reorder ? i : (int64_t)a.src[i];
+            const bool alive = (fl & 1u) != 0;
+            if (!alive) {
+                if (reorder) {
+                    a.x[dst] = x; a.y[dst] = y; a.z[dst] = z;
+                    a.vx[dst] = vx; a.vy[dst] = vy; a.vz[dst] = vz;
+                    a.id[dst] = idi;
+                    if (a.alive) a.alive[dst] = 0;
                 }
             } else {
-                nx = x + vx * dt;
-                ny = y + vy * dt;
-                nz = z + vz * dt;
-            }
-            // Walls, once per axis.
-            bool gone = false;
-            real* pos[3] = {&nx, &ny, &nz};
-            real* vel[3] = {&nvx, &nvy, &nvz};
-#pragma unroll
-            for (int ax = 0; ax < 3; ++ax) {
-                const real lo = I.lo[ax], hi = I.hi[ax], q = *pos[ax];
-                if (I.bc[ax] == TPKMC_BC_REFLECT) {
-                    if (q < lo) { *pos[ax] = lo + (lo - q); *vel[ax] = -*vel[ax]; }
-                    else if (q > hi) { *pos[ax] = hi - (q - hi); *vel[ax] = -*vel[ax]; }
-                } else if (I.bc[ax] == TPKMC_BC_PERIODIC) {
-                    real r = q;
-                    if (r < lo) r = r + I.L[ax];
-                    if (r >= hi) r = r - I.L[ax];
-                    *pos[ax] = r;
+                const real dt = I.dt;
+                const int32_t j = j_pre;
+                const bool mutual = j >= 0 && partner_of<real>(a, j) == (int32_t)i;
+                ghave += j >= 0 ? 1.0 : 0.0;
+                real nx = x, ny = y, nz = z, nvx = vx, nvy = vy, nvz = vz;
+                double virx = 0, viry = 0, virz = 0;
+                if (mutual) {
+                    real xj, yj, zj, vxj, vyj, vzj;
+                    uint32_t idj, flj;
+                    Rec<real>::load(a.rec, j, xj, yj, zj, idj, vxj, vyj, vzj, flj);
+                    const bool isA = idi < idj;
+                    // Pair quantities with A = lower id, B = higher id.
+                    const real xA = isA ? x : xj, yA = isA ? y : yj, zA = isA ? z : zj;
+                    const real xB = isA ? xj : x, yB = isA ? yj : y, zB = isA ? zj : z;
+                    const real vxA = isA ? vx : vxj, vyA = isA ? vy : vyj, vzA = isA ? vz : vzj;
+                    const real vxB = isA ? vxj : vx, vyB = isA ? vyj : vy, vzB = isA ? vzj : vz;
+                    real rx = xA - xB, ry = yA - yB, rz = zA - zB;
+                    if (I.bc[0] == TPKMC_BC_PERIODIC) rx = min_image(rx, I.L[0], I.halfL[0]);
+                    if (I.bc[1] == TPKMC_BC_PERIODIC) ry = min_image(ry, I.L[1], I.halfL[1]);
+                    if (I.bc[2] == TPKMC_BC_PERIODIC) rz = min_image(rz, I.L[2], I.halfL[2]);
+                    const real ux = vxA - vxB, uy = vyA - vyB, uz = vzA - vzB;
+                    const real s0 = (rx * ux + ry * uy) + rz * uz;
+                    const real vv = (ux * ux + uy * uy) + uz * uz;
+                    const real tp = -s0 / vv;
+                    double nh[3];
+                    pair_direction(I.seed_lo, I.seed_hi, I.step_lo, I.instance, isA ? idi : idj, isA ? idj : idi,
+                                   (I.flags & TPKMC_PLANAR) != 0, nh);
+                    // Equal masses: centre-of-mass velocity kept, relative speed g
+                    // kept, outgoing directions opposite along nhat.
+                    const real g = sqrt(vv);
+                    const real h = real(0.5) * g;
+                    const real sg = isA ? real(1) : real(-1);
+                    const real cmx = real(0.5) * (vxA + vxB), cmy = real(0.5) * (vyA + vyB), cmz = real(0.5) * (vzA + vzB);
+                    const real hx = h * (real)nh[0], hy = h * (real)nh[1], hz = h * (real)nh[2];
+                    nvx = isA ? cmx + hx : cmx - hx;
+                    nvy = isA ? cmy + hy : cmy - hy;
+                    nvz = isA ? cmz + hz : cmz - hz;
+                    // Split move at the point of closest approach.
+                    const real rest = dt - tp;
+                    nx = (x + vx * tp) + nvx * rest;
+                    ny = (y + vy * tp) + nvy * rest;
+                    nz = (z + vz * tp) + nvz * rest;
+                    // Virial: separation at closest approach (from the partner to
+                    // this particle) times this particle's momentum change.
+                    const real sx = sg * (rx + tp * ux), sy = sg * (ry + tp * uy), sz = sg * (rz + tp * uz);
+                    virx = (double)(real(0.5) * sx * (I.mass * (nvx - vx)) / dt);
+                    viry = (double)(real(0.5) * sy * (I.mass * (nvy - vy)) / dt);
+                    virz = (double)(real(0.5) * sz * (I.mass * (nvz - vz)) / dt);
+                    if (isA) {
+                        gpairs += 1.0;
+                        if (I.flags & TPKMC_EMIT_PAIRS) { emit = true; emit_a = idi; emit_b = idj; }
+                    }
                 } else {
-                    if (q < lo || q >= hi) gone = true;
+                    nx = x + vx * dt;
+                    ny = y + vy * dt;
+                    nz = z + vz * dt;
+                }
+                // Walls, once per axis.
+                bool gone = false;
+                real* pos[3] = {&nx, &ny, &nz};
+                real* vel[3] = {&nvx, &nvy, &nvz};
+#pragma unroll
+                for (int ax = 0; ax < 3; ++ax) {
+                    const real lo = I.lo[ax], hi = I.hi[ax], q = *pos[ax];
+                    if (I.bc[ax] == TPKMC_BC_REFLECT) {
+                        if (q < lo) { *pos[ax] = lo + (lo - q); *vel[ax] = -*vel[ax]; }
+                        else if (q > hi) { *pos[ax] = hi - (q - hi); *vel[ax] = -*vel[ax]; }
+                    } else if (I.bc[ax] == TPKMC_BC_PERIODIC) {
+                        real r = q;
+                        if (r < lo) r = r + I.L[ax];
+                        if (r >= hi) r = r - I.L[ax];
+                        *pos[ax] = r;
+                    } else {
+                        if (q < lo || q >= hi) gone = true;
+                    }
+                }
+                a.x[dst] = nx; a.y[dst] = ny; a.z[dst] = nz;
+                a.vx[dst] = nvx; a.vy[dst] = nvy; a.vz[dst] = nvz;
+                if (reorder) a.id[dst] = idi;
+                if (a.alive && (reorder || gone)) a.alive[dst] = gone ? 0 : 1;
+                if (gone) gabs += 1.0;
+                const bool fin = finite3(nx, ny, nz) && finite3(nvx, nvy, nvz);
+                if (!gone && fin) {
+                    const double m = I.mass_d;
+                    const double dvx = (double)nvx, dvy = (double)nvy, dvz = (double)nvz;
+                    const double v2 = (dvx * dvx + dvy * dvy) + dvz * dvz;
+                    gpx += m * dvx; gpy += m * dvy; gpz += m * dvz;
+                    gek += (0.5 * m) * v2;
+                    gvm = v2 > gvm ? v2 : gvm;
+                    gvir += (virx + viry) + virz;
+                    gm += m;
+                    galive += 1.0;
+                    if (a.moments) {
+                        const int bx = axis_bin(nx, I.lo[0], I.inv_wo[0], I.no[0]);
+                        const int by = axis_bin(ny, I.lo[1], I.inv_wo[1], I.no[1]);
+                        const int bz = axis_bin(nz, I.lo[2], I.inv_wo[2], I.no[2]);
+                        const int ob = (int)(I.obin_off + bx + (int64_t)I.no[0] * (by + (int64_t)I.no[1] * bz));
+                        if (ob != mob) {
+                            if (mob >= 0) moment_flush(tab, a, mob, mv);
+                            mob = ob;
+                            const double* S = a.shift + (int64_t)ob * 3;
+                            shx = S[0]; shy = S[1]; shz = S[2];
+#pragma unroll
+                            for (int k = 0; k < TPKMC_MOMENT_STRIDE; ++k) mv[k] = 0.0;
+                        }
+                        const double ex = dvx - shx, ey = dvy - shy, ez = dvz - shz;
+                        mv[0] += 1.0; mv[1] += m * ex; mv[2] += m * ey; mv[3] += m * ez;
+                        mv[4] += m * ex * ex; mv[5] += m * ey * ey; mv[6] += m * ez * ez;
+                        mv[7] += virx; mv[8] += viry; mv[9] += virz; mv[10] += mutual ? 1.0 : 0.0;
+                    }
                 }
             }
-            a.x[dst] = nx; a.y[dst] = ny; a.z[dst] = nz;
-            a.vx[dst] = nvx; a.vy[dst] = nvy; a.vz[dst] = nvz;
-            if (reorder) a.id[dst] = idi;
-            if (a.alive && (reorder || gone)) a.alive[dst] = gone ? 0 : 1;
-            if (gone) gabs = 1.0;
-            const bool fin = finite3(nx, ny, nz) && finite3(nvx, nvy, nvz);
-            if (!gone && fin) {
-                const double m = I.mass_d;
-                const double dvx = (double)nvx, dvy = (double)nvy, dvz = (double)nvz;
-                const double v2 = (dvx * dvx + dvy * dvy) + dvz * dvz;
-                gpx = m * dvx; gpy = m * dvy; gpz = m * dvz;
-                gek = (0.5 * m) * v2;
-                gvm = v2;
-                gvir = (virx + viry) + virz;
-                gm = m;
-                galive = 1.0;
-                if (a.moments) {
-                    const int bx = axis_bin(nx, I.lo[0], I.inv_wo[0], I.no[0]);
-                    const int by = axis_bin(ny, I.lo[1], I.inv_wo[1], I.no[1]);
-                    const int bz = axis_bin(nz, I.lo[2], I.inv_wo[2], I.no[2]);
-                    const int64_t ob = I.obin_off + bx + (int64_t)I.no[0] * (by + (int64_t)I.no[1] * bz);
-                    const double* S = a.shift + ob * 3;
-                    const double ex = dvx - S[0], ey = dvy - S[1], ez = dvz - S[2];
-                    const double v[TPKMC_MOMENT_STRIDE] = {1.0, m * ex, m * ey, m * ez, m * ex * ex, m * ey * ey,
-                                                           m * ez * ez, virx, viry, virz, mutual ? 1.0 : 0.0};
-                    const int slot = table_slot(tab, (int)ob);
-                    const int nval = mutual ? TPKMC_MOMENT_STRIDE : 7;
-                    if (slot >= 0) {
-                        for (int k = 0; k < nval; ++k) unsafeAtomicAdd(&tab.val[slot][k], v[k]);
-                    } else {
-                        double* M = a.moments + ob * TPKMC_MOMENT_STRIDE;
-                        for (int k = 0; k < nval; ++k) unsafeAtomicAdd(M + k, v[k]);
+        }
+        // Pair list: one atomic per wave and record slot.
+        if (a.pairs) {
+            const uint64_t em = __ballot(emit);
+            if (em) {
+                const int leader = __ffsll((long long)em) - 1;
+                unsigned long long pos0 = 0;
+                if (lane == leader) pos0 = atomicAdd(a.pair_count, (unsigned long long)__popcll(em));
+                pos0 = __shfl(pos0, leader);
+                if (emit) {
+                    const unsigned long long pos = pos0 + __popcll(em & ((1ull << lane) - 1ull));
+                    if ((int64_t)pos < a.pair_cap) {
+                        a.pairs[2 * pos] = emit_a;
+                        a.pairs[2 * pos + 1] = emit_b;
                     }
                 }
             }
         }
     }
-    // Pair list: one atomic per wave.
-    if (a.pairs) {
-        const uint64_t em = __ballot(emit);
-        if (em) {
-            const int lane = threadIdx.x & 63;
-            const int leader = __ffsll((long long)em) - 1;
-            unsigned long long pos0 = 0;
-            if (lane == leader) pos0 = atomicAdd(a.pair_count, (unsigned long long)__popcll(em));
-            pos0 = __shfl(pos0, leader);
-            if (emit) {
-                const unsigned long long pos = pos0 + __popcll(em & ((1ull << lane) - 1ull));
-                if ((int64_t)pos < a.pair_cap) {
-                    a.pairs[2 * pos] = emit_a;
-                    a.pairs[2 * pos + 1] = emit_b;
-                }
-            }
-        }
-    }
     if (a.moments) {
+        if (mob >= 0) moment_flush(tab, a, mob, mv);
         __syncthreads();
-        for (int t = threadIdx.x; t < kSlots; t += blockDim.x) {
+        for (int t = tid; t < kSlots; t += kMoveLanes) {
             const int ob = tab.key[t];
             if (ob < 0) continue;
             double* M = a.moments + (int64_t)ob * TPKMC_MOMENT_STRIDE;
@@ -1014,10 +1056,25 @@ __global__ void __launch_bounds__(kBlock) k_move(StepArgs<real> a) {
                 if (k < 7 || tab.val[t][k] != 0.0) unsafeAtomicAdd(M + k, tab.val[t][k]);
         }
     }
-    double* gp = a.gpart + (int64_t)blockIdx.x * kGPart;
     double v[11] = {gpx, gpy, gpz, gek, gvm, gvir, gm, galive, gpairs, gabs, ghave};
-    block_reduce<11>(v, 4, red);
-    if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < 11; ++k)
+        for (int o = 32; o > 0; o >>= 1) {
+            const double u = __shfl_xor(v[k], o);
+            v[k] = k == 4 ? fmax(v[k], u) : v[k] + u;
+        }
+    if (kMoveLanes > 64) {
+        if (lane == 0)
+#pragma unroll
+            for (int k = 0; k < 11; ++k) red[tid >> 6][k] = v[k];
+        __syncthreads();
+        if (tid == 0)
+            for (int w = 1; w < kMoveLanes / 64; ++w)
+#pragma unroll
+                for (int k = 0; k < 11; ++k) v[k] = k == 4 ? fmax(v[k], red[w][k]) : v[k] + red[w][k];
+    }
+    if (tid == 0) {
+        double* gp = a.gpart + (int64_t)blockIdx.x * kGPart;
         gp[GP_PX] = v[0]; gp[GP_PY] = v[1]; gp[GP_PZ] = v[2]; gp[GP_EKIN] = v[3]; gp[GP_VMAX2] = v[4];
         gp[GP_VIR] = v[5]; gp[GP_MASS] = v[6]; gp[GP_ALIVE] = v[7]; gp[GP_PAIRS] = v[8]; gp[GP_ABSORBED] = v[9];
         gp[GP_HAVEBEST] = v[10];
@@ -1071,7 +1128,7 @@ void launch_search(const StepArgs<real>& a, int block, int group, hipStream_t s)
 }
 template <typename real>
 void launch_move(const StepArgs<real>& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_move<real>, dim3(a.nblk), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_move<real>, dim3(a.nblk), dim3(kMoveLanes), 0, s, a);
 }
 
 }  // namespace tpkmc
