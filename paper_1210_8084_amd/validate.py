@@ -140,6 +140,39 @@ def noh(precision, n=8_000_000, steps=800, planar=False):
                 **_conservation(w, r))
 
 
+def noh3d(precision, n=8_000_000, steps=160):
+    """Spherical Noh: radial number density against the analytic solution
+    with d = 3 (jump ((gamma + 1) / (gamma - 1))^3 = 64), and the shocked
+    temperature m v0^2 / f."""
+    from oracle import analytic as A
+    from paper_1210_8084_amd import workloads as W
+    w = W.noh3d(n=n, steps=steps)
+    r = _run(w, precision, steps, progress=40)
+    t = steps * w.params["dt"]
+    st = r["state"]
+    rad = np.sqrt(st["x"] ** 2 + st["y"] ** 2 + st["z"] ** 2)
+    edges = np.arange(0.0, 0.4 + 1e-12, 0.01)
+    cnt, _ = np.histogram(rad, bins=edges)
+    vol = 4.0 / 3.0 * math.pi * (edges[1:] ** 3 - edges[:-1] ** 3)
+    n_ = cnt / vol
+    rc = 0.5 * (edges[1:] + edges[:-1])
+    gamma = w.info["gamma"]
+    na, _, _, rs = A.noh_profile(rc, t, n0=w.info["n0"], v0=1.0, gamma=gamma, d=3)
+    inside = rc < rs * 0.8
+    core = rad < 0.8 * rs
+    t_core = None
+    if core.sum() > 100:
+        dv2 = sum((st[k][core] - st[k][core].mean()) ** 2 for k in ("vx", "vy", "vz"))
+        t_core = float(w.params["mass"] * dv2.mean() / 3.0)
+    return dict(workload=f"{w.name} n={n}", steps=steps, t=t, wall_s=r["wall"], r_shock=rs,
+                l1_density=float(np.mean(np.abs(n_ - na)) / w.info["n0"]),
+                shocked_density_over_n0=float(np.mean(n_[inside]) / w.info["n0"]) if inside.any() else None,
+                analytic_shocked=((gamma + 1.0) / (gamma - 1.0)) ** 3,
+                shocked_temperature=t_core, analytic_shocked_temperature=w.params["mass"] * 1.0 / 3.0,
+                profile_density=(n_ / w.info["n0"]).round(3).tolist(), analytic_density=(na / w.info["n0"]).round(3).tolist(),
+                **_conservation(w, r))
+
+
 def sedov(precision, n=16_000_000, steps=600, planar=False):
     from oracle import analytic as A
     from paper_1210_8084_amd import workloads as W
@@ -170,18 +203,20 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=None)
     ap.add_argument("--quick", action="store_true", help="smaller sizes and fewer steps")
-    ap.add_argument("--only", default="sod,noh,sedov,sod2d,noh2d,sedov2d")
+    ap.add_argument("--only", default="sod,noh,sedov,sod2d,noh2d,sedov2d,noh3d")
     args = ap.parse_args()
     from paper_1210_8084_amd import tpkmc as T
     report = {}
     for name in args.only.split(","):
         planar = name.endswith("2d")
-        base = name[:-2] if planar else name
+        base = name[:-2] if name.endswith(("2d", "3d")) else name
         for prec, label in ((T.FP32, "fp32"), (T.FP64, "fp64")):
             print(f"== {name} {label}", flush=True)
             if base == "sod":
                 res = sod(prec, n=400_000 if args.quick else 4_000_000, steps=100 if args.quick else 500,
                           planar=planar)
+            elif base == "noh" and name.endswith("3d"):
+                res = noh3d(prec, n=800_000 if args.quick else 8_000_000, steps=160)
             elif base == "noh":
                 res = noh(prec, n=800_000 if args.quick else 8_000_000, steps=200 if args.quick else 800,
                           planar=planar)

@@ -150,6 +150,28 @@ def noh(n=8_000_000, seed=1, kn=1e-3, ncell=256, nobin=None, dt=7.5e-4, steps=80
     return Workload("noh", st, g, params(sigma, dt, seed=seed), steps, info)
 
 
+def noh3d(n=8_000_000, seed=1, kn=1e-3, ncell=128, nobin=None, dt=None, steps=160, thermal=1e-3, v0=1.0):
+    """Spherical Noh implosion (Sec. 4.3, the 3D run; gamma = 5/3, density
+    jump 64): uniform ball of radius 1 in the box [-1, 1]^3 with reflecting
+    walls, radial inflow speed v0 plus a cold Maxwellian.  Without an explicit
+    dt, dt moves an inflowing particle a quarter c-bin."""
+    rng = np.random.default_rng(seed)
+    rad = rng.uniform(0.0, 1.0, n) ** (1.0 / 3.0)
+    d = _isotropic(rng, n)
+    x, y, z = rad * d[0], rad * d[1], rad * d[2]
+    vt = rng.normal(0.0, thermal, size=(3, n))
+    v = -v0 * d + vt
+    n0 = n / (4.0 / 3.0 * math.pi)
+    sigma = sigma_from_kn(kn, 1.0, n0)
+    if dt is None:
+        dt = 0.25 * (2.0 / ncell) / v0
+    nb = ncell if nobin is None else nobin
+    g = grid((-1, -1, -1), (1, 1, 1), (ncell,) * 3, (REFLECT,) * 3, (nb,) * 3)
+    st = make_state(x, y, z, v[0], v[1], v[2])
+    info = dict(kn=kn, lam=kn, n0=n0, v0=v0, gamma=5.0 / 3.0, f=3, geometry=3)
+    return Workload("noh3d", st, g, params(sigma, dt, seed=seed), steps, info)
+
+
 def sedov(n=16_000_000, seed=1, kn=1e-3, ncell=128, nobin=64, steps=600, blast_fraction=1e-3,
           energy=1.0, cold_ratio=1e-3):
     """Sedov point blast (Sec. 4.4) in the unit cube with reflecting walls:
