@@ -25,7 +25,8 @@ LIB = os.path.join(HERE, "libtpkmc_ref.so")
 MODE_BINNED, MODE_BRUTE, MODE_ALL = 0, 1, 2
 CNT = dict(alive=0, pairs=1, tests=2, cand=3, fast=4, nonfinite=5, absorbed=6, have_best=7)
 GLB = dict(px=0, py=1, pz=2, ekin=3, vmax2=4, virial=5, mass=6, dt=7)
-M_STRIDE = 11
+M_STRIDE = 12
+M_MASS = 11      # moments slot: sum m
 ADAPTIVE_DT = 1  # ref_params.flags: step length from the rule of Sec. 3
 PLANAR = 2       # ref_params.flags: two-dimensional gas (x-y plane)
 RANK_TIME = 4    # ref_params.flags: criterion 3 by earliest contact time
@@ -81,14 +82,14 @@ def lib():
         L.ref_best_sample.argtypes = ([_P, _P, ctypes.c_int64] + [_P] * 8 +
                                       [ctypes.c_int64, _P, ctypes.c_int, _P, _P])
         L.ref_best_sample.restype = ctypes.c_int
-        L.ref_step_sample.argtypes = ([_P, _P, ctypes.c_int64] + [_P] * 8 +
+        L.ref_step_sample.argtypes = ([_P, _P, ctypes.c_int64] + [_P] * 9 +
                                       [ctypes.c_int64, _P, ctypes.c_int, _P, _P, _P])
         L.ref_step_sample.restype = ctypes.c_int
         L.ref_step_dt.argtypes = [_P, _P, ctypes.c_int64] + [_P] * 7
         L.ref_step_dt.restype = ctypes.c_double
         L.ref_count_tests.argtypes = [_P, ctypes.c_int64] + [_P] * 7
         L.ref_count_tests.restype = ctypes.c_uint64
-        L.ref_step.argtypes = ([_P, _P, ctypes.c_int64] + [_P] * 8 +
+        L.ref_step.argtypes = ([_P, _P, ctypes.c_int64] + [_P] * 9 +
                                [ctypes.c_int, ctypes.c_int, _P, ctypes.c_int64, _P, _P, _P])
         L.ref_step.restype = ctypes.c_int
         _lib = L
@@ -138,6 +139,16 @@ def _check_state(s):
 
 def _state_ptrs(s):
     return [_ptr(s[k]) for k in ("x", "y", "z", "vx", "vy", "vz", "id")] + [_ptr(s.get("alive"))]
+
+
+def _mass_ptr(s, n):
+    """Per-particle masses (float64, one per particle) or None."""
+    m = s.get("mass")
+    if m is None:
+        return None
+    if m.dtype != np.float64 or len(m) != n or not m.flags["C_CONTIGUOUS"]:
+        raise ValueError("state['mass'] must be contiguous float64 of length n")
+    return _ptr(m)
 
 
 def philox(ctr, key):
@@ -219,8 +230,8 @@ def step_sample(state, grid, params, sample, nthreads=0):
     out = np.zeros((len(smp), 6))
     partner = np.full(len(smp), -1, dtype=np.int64)
     alive = np.zeros(len(smp), dtype=np.uint8)
-    rc = lib().ref_step_sample(ctypes.byref(G), ctypes.byref(P), n, *_state_ptrs(state), len(smp),
-                               _ptr(smp), nthreads, _ptr(out), _ptr(partner), _ptr(alive))
+    rc = lib().ref_step_sample(ctypes.byref(G), ctypes.byref(P), n, *_state_ptrs(state), _mass_ptr(state, n),
+                               len(smp), _ptr(smp), nthreads, _ptr(out), _ptr(partner), _ptr(alive))
     if rc:
         raise ValueError(f"ref_step_sample failed ({rc})")
     return out, partner, alive
@@ -261,8 +272,8 @@ def step(state, grid, params, mode=MODE_BINNED, nthreads=0, pair_cap=None, momen
     counters = np.zeros(8, dtype=np.uint64)
     glob = np.zeros(8)
     mom = np.zeros((nobins(grid), M_STRIDE)) if moments else None
-    rc = lib().ref_step(ctypes.byref(G), ctypes.byref(P), n, *_state_ptrs(state), mode, nthreads,
-                        _ptr(pairs), cap, _ptr(counters), _ptr(mom), _ptr(glob))
+    rc = lib().ref_step(ctypes.byref(G), ctypes.byref(P), n, *_state_ptrs(state), _mass_ptr(state, n), mode,
+                        nthreads, _ptr(pairs), cap, _ptr(counters), _ptr(mom), _ptr(glob))
     if rc:
         raise ValueError(f"ref_step failed ({rc})")
     k = min(int(counters[CNT["pairs"]]), cap)

@@ -320,12 +320,16 @@ typedef struct {
     const double *x, *y, *z, *vx, *vy, *vz;
     const uint32_t* id;
     const uint8_t* alive;
+    const double* mass;     /* per-particle mass, or NULL: params.mass for all */
 } view;
 
+/* Finite coordinates and velocities (and a finite positive mass when the
+ * particles carry their own). */
 static int finite6(const view* V, int64_t i)
 {
     return isfinite(V->x[i]) && isfinite(V->y[i]) && isfinite(V->z[i]) &&
-           isfinite(V->vx[i]) && isfinite(V->vy[i]) && isfinite(V->vz[i]);
+           isfinite(V->vx[i]) && isfinite(V->vy[i]) && isfinite(V->vz[i]) &&
+           (!V->mass || (isfinite(V->mass[i]) && V->mass[i] > 0.0));
 }
 
 /* A particle takes part in the partner search when it is alive and all of
@@ -497,7 +501,7 @@ double ref_step_dt(const ref_grid* g, const ref_params* p, int64_t n,
     if (derive(g, p, &G)) return -1.0;
     if (n < 0 || (n > 0 && (!x || !y || !z || !vx || !vy || !vz))) return -1.0;
     static const uint32_t no_id = 0;
-    view V = { n, x, y, z, vx, vy, vz, &no_id, alive };
+    view V = { n, x, y, z, vx, vy, vz, &no_id, alive, NULL };
     return step_dt(&G, p, &V);
 }
 
@@ -511,7 +515,7 @@ int ref_best(const ref_grid* g, const ref_params* p, int64_t n,
     if (derive(g, p, &G)) return -1;
     if (check_common(&G, g, p, n, x, y, z, vx, vy, vz, id)) return -1;
     if (mode < 0 || mode > 2 || (n > 0 && (!best || !best_d2))) return -1;
-    view V = { n, x, y, z, vx, vy, vz, id, alive };
+    view V = { n, x, y, z, vx, vy, vz, id, alive, NULL };
     const double dt = step_dt(&G, p, &V);
     bins Bn;
     if (make_bins(&G, g, &V, &Bn)) { free_bins(&Bn); return -2; }
@@ -533,7 +537,7 @@ int ref_best_sample(const ref_grid* g, const ref_params* p, int64_t n,
     if (ns < 0 || (ns > 0 && (!sample || !best || !best_d2))) return -1;
     for (int64_t k = 0; k < ns; ++k)
         if (sample[k] < 0 || sample[k] >= n) return -1;
-    view V = { n, x, y, z, vx, vy, vz, id, alive };
+    view V = { n, x, y, z, vx, vy, vz, id, alive, NULL };
     const double dt = step_dt(&G, p, &V);
     bins Bn;
     if (make_bins(&G, g, &V, &Bn)) { free_bins(&Bn); return -2; }
@@ -556,7 +560,7 @@ uint64_t ref_count_tests(const ref_grid* g, int64_t n,
     derived G;
     if (derive(g, NULL, &G) || n < 0) return 0;
     static const uint32_t no_id = 0;
-    view V = { n, x, y, z, vx, vy, vz, &no_id, alive };
+    view V = { n, x, y, z, vx, vy, vz, &no_id, alive, NULL };
     bins Bn;
     if (make_bins(&G, g, &V, &Bn)) { free_bins(&Bn); return 0; }
     uint64_t total = 0;
@@ -596,19 +600,32 @@ static void scatter_pair(const derived* G, const ref_params* p, const view* V, i
         ref_direction_planar(p->seed, p->step, p->instance, V->id[A], V->id[B], nhat);
     else
         ref_direction(p->seed, p->step, p->instance, V->id[A], V->id[B], nhat);
-    /* Centre-of-mass frame, equal masses: the relative speed g is kept and
-     * the outgoing velocities are opposite along nhat. */
+    /* Centre-of-mass frame (Sec. 3): the relative speed g is kept and the
+     * outgoing velocities are opposite along nhat.  Equal masses: v_cm is the
+     * mean and each moves g/2; masses mA, mB: v_cm is mass-weighted and A
+     * moves mB g / (mA + mB), B moves mA g / (mA + mB). */
     double gr = sqrt(vv);
-    double h = 0.5 * gr;
-    for (int a = 0; a < 3; ++a) {
-        double vcm = 0.5 * (vA[a] + vB[a]);
-        nA[a] = vcm + h * nhat[a];
-        nB[a] = vcm - h * nhat[a];
+    double mA = V->mass ? V->mass[A] : p->mass, mB = V->mass ? V->mass[B] : p->mass;
+    if (!V->mass) {
+        double h = 0.5 * gr;
+        for (int a = 0; a < 3; ++a) {
+            double vcm = 0.5 * (vA[a] + vB[a]);
+            nA[a] = vcm + h * nhat[a];
+            nB[a] = vcm - h * nhat[a];
+        }
+    } else {
+        double M = mA + mB;
+        double hA = (mB / M) * gr, hB = (mA / M) * gr;
+        for (int a = 0; a < 3; ++a) {
+            double vcm = (mA * vA[a] + mB * vB[a]) / M;
+            nA[a] = vcm + hA * nhat[a];
+            nB[a] = vcm - hB * nhat[a];
+        }
     }
     for (int a = 0; a < 3; ++a) {
         double sep = r[a] + tp * u[a];
-        double dpA = p->mass * (nA[a] - vA[a]);
-        double dpB = p->mass * (nB[a] - vB[a]);
+        double dpA = mA * (nA[a] - vA[a]);
+        double dpB = mB * (nB[a] - vB[a]);
         double virA = 0.5 * sep * dpA / p->dt;
         double virB = 0.5 * (-sep) * dpB / p->dt;
         vi_new[a] = i_is_A ? nA[a] : nB[a];
@@ -654,7 +671,7 @@ static int move_one(const derived* G, const ref_grid* g, double dt, double r[3],
 int ref_step_sample(const ref_grid* g, const ref_params* p, int64_t n,
                     const double* x, const double* y, const double* z,
                     const double* vx, const double* vy, const double* vz,
-                    const uint32_t* id, const uint8_t* alive,
+                    const uint32_t* id, const uint8_t* alive, const double* mass,
                     int64_t ns, const int64_t* sample, int nthreads,
                     double* out_state, int64_t* out_partner, uint8_t* out_alive)
 {
@@ -664,7 +681,7 @@ int ref_step_sample(const ref_grid* g, const ref_params* p, int64_t n,
     if (ns < 0 || (ns > 0 && (!sample || !out_state || !out_partner || !out_alive))) return -1;
     for (int64_t k = 0; k < ns; ++k)
         if (sample[k] < 0 || sample[k] >= n) return -1;
-    view V = { n, x, y, z, vx, vy, vz, id, alive };
+    view V = { n, x, y, z, vx, vy, vz, id, alive, mass };
     ref_params q;
     with_step_dt(&G, p, &V, &q);
     p = &q;
@@ -720,7 +737,7 @@ static double nval(const nsum* a) { return a->s + a->c; }
 int ref_step(const ref_grid* g, const ref_params* p, int64_t n,
              double* x, double* y, double* z,
              double* vx, double* vy, double* vz,
-             const uint32_t* id, uint8_t* alive, int mode, int nthreads,
+             const uint32_t* id, uint8_t* alive, const double* mass, int mode, int nthreads,
              uint32_t* pairs, int64_t pair_cap,
              uint64_t* counters, double* moments, double* globals)
 {
@@ -730,11 +747,11 @@ int ref_step(const ref_grid* g, const ref_params* p, int64_t n,
     if (mode < 0 || mode > 2 || pair_cap < 0) return -1;
     for (int a = 0; a < 3; ++a)
         if (G.bc[a] == REF_BC_ABSORB && !alive) return -1;
-    view V = { n, x, y, z, vx, vy, vz, id, alive };
+    view V = { n, x, y, z, vx, vy, vz, id, alive, mass };
     ref_params q;
     with_step_dt(&G, p, &V, &q);
     p = &q;
-    const double dt = p->dt, m = p->mass;
+    const double dt = p->dt;
     uint64_t cnt[8] = { 0 };
 
     size_t nn = (size_t)(n > 0 ? n : 1);
@@ -821,6 +838,7 @@ int ref_step(const ref_grid* g, const ref_params* p, int64_t n,
         int32_t bz = axis_bin(z[i], g->lo[2], G.inv_wo[2], G.no[2]);
         ob[i] = bx + (int64_t)G.no[0] * (by + (int64_t)G.no[1] * bz);
         double v2 = (vx[i] * vx[i] + vy[i] * vy[i]) + vz[i] * vz[i];
+        const double m = mass ? mass[i] : p->mass;
         nadd(&gp[0], m * vx[i]);
         nadd(&gp[1], m * vy[i]);
         nadd(&gp[2], m * vz[i]);
@@ -831,6 +849,7 @@ int ref_step(const ref_grid* g, const ref_params* p, int64_t n,
         if (moments) {
             double* M = moments + ob[i] * REF_M_STRIDE;
             M[REF_M_COUNT] += 1.0;
+            M[REF_M_MASS] += m;
             M[REF_M_PX] += m * vx[i];
             M[REF_M_PX + 1] += m * vy[i];
             M[REF_M_PX + 2] += m * vz[i];
@@ -845,7 +864,8 @@ int ref_step(const ref_grid* g, const ref_params* p, int64_t n,
         for (int64_t i = 0; i < n; ++i) {
             if (ob[i] < 0) continue;
             double* M = moments + ob[i] * REF_M_STRIDE;
-            double mass_bin = m * M[REF_M_COUNT];
+            const double m = mass ? mass[i] : p->mass;
+            double mass_bin = M[REF_M_MASS];
             double vb[3] = { M[REF_M_PX] / mass_bin, M[REF_M_PX + 1] / mass_bin, M[REF_M_PX + 2] / mass_bin };
             double dv0 = vx[i] - vb[0], dv1 = vy[i] - vb[1], dv2 = vz[i] - vb[2];
             M[REF_M_CXX] += m * dv0 * dv0;

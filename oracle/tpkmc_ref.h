@@ -106,7 +106,8 @@ enum {
     REF_M_CXX = 4,          /* 4..6: sum m (v_a - vbar_a)^2, vbar = bin mean  */
     REF_M_VIRX = 7,         /* 7..9: sum (1/2) r_a dp_a / dt over colliders   */
     REF_M_NCOLL = 10,
-    REF_M_STRIDE = 11
+    REF_M_MASS = 11,        /* sum m                                          */
+    REF_M_STRIDE = 12
 };
 
 /* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11). */
@@ -166,7 +167,7 @@ uint64_t ref_count_tests(const ref_grid* g, int64_t n,
 int ref_step_sample(const ref_grid* g, const ref_params* p, int64_t n,
                     const double* x, const double* y, const double* z,
                     const double* vx, const double* vy, const double* vz,
-                    const uint32_t* id, const uint8_t* alive,
+                    const uint32_t* id, const uint8_t* alive, const double* mass,
                     int64_t ns, const int64_t* sample, int nthreads,
                     double* out_state, int64_t* out_partner, uint8_t* out_alive);
 
@@ -178,7 +179,14 @@ double ref_step_dt(const ref_grid* g, const ref_params* p, int64_t n,
                    const double* vx, const double* vy, const double* vz,
                    const uint8_t* alive);
 
-/* One full collision step, in place, in caller order.
+/* Particle masses: mass may be NULL (every particle has params.mass) or
+ * hold one finite positive mass per particle (a mixture).  Scattering then
+ * keeps the mass-weighted centre-of-mass velocity and the relative speed
+ * (Sec. 3 for the equal-mass case, plain elastic kinematics otherwise), and
+ * moments and global sums weight each particle by its own mass.  A particle
+ * whose mass is not finite and positive counts as non-finite.
+ *
+ * One full collision step, in place, in caller order.
  * pairs (may be NULL): (idA, idB) with idA < idB, at most pair_cap entries.
  * moments (may be NULL): double[nobin * 11].  globals: double[8] or NULL.
  * counters: uint64[8] or NULL.  alive may be NULL (all alive), except when
@@ -186,7 +194,7 @@ double ref_step_dt(const ref_grid* g, const ref_params* p, int64_t n,
 int ref_step(const ref_grid* g, const ref_params* p, int64_t n,
              double* x, double* y, double* z,
              double* vx, double* vy, double* vz,
-             const uint32_t* id, uint8_t* alive, int mode, int nthreads,
+             const uint32_t* id, uint8_t* alive, const double* mass, int mode, int nthreads,
              uint32_t* pairs, int64_t pair_cap,
              uint64_t* counters, double* moments, double* globals);
 

@@ -63,6 +63,8 @@ def make_state(x, y, z, vx, vy, vz, ids=None):
 
 def copy_state(st, dtype=np.float64):
     out = {k: np.array(st[k], dtype=dtype) for k in ("x", "y", "z", "vx", "vy", "vz")}
+    if st.get("mass") is not None:
+        out["mass"] = np.array(st["mass"], dtype=dtype)
     out["id"] = st["id"].copy()
     out["alive"] = st["alive"].copy() if st.get("alive") is not None else np.ones(len(st["x"]), np.uint8)
     return out
