@@ -33,6 +33,7 @@ sys.path.insert(0, ROOT)
 FLOP_PER_TEST = 18
 PEAK_FLOPS = {"fp32": 157.3e12, "fp64": 78.6e12}
 HBM_PEAK = 8.0e12
+MOMENT_VALUES = 12  # doubles per o-bin
 
 
 def make_workload(name):
@@ -54,12 +55,12 @@ def phase_bytes(rs, n, ncell_tot, nobin, reorder):
     """Algorithmic HBM bytes per launch of each phase (rs = bytes per real)."""
     rec = 8 * rs
     return {
-        "clear": 4 * ncell_tot + 88 * nobin,
+        "clear": 4 * ncell_tot + 8 * MOMENT_VALUES * nobin,
         "key": n * (6 * rs + 1 + 8),
         "scan": 12 * ncell_tot,
         "scatter": n * (6 * rs + 4 + 1 + 8 + 4 + rec + 4),
         "search": n * (rec + 4) + 4 * ncell_tot,
-        "move": n * (rec + 4 + 6 * rs + 1 + (4 if reorder else 4)) + 2 * 88 * nobin,
+        "move": n * (rec + 4 + 6 * rs + 1 + (4 if reorder else 4)) + 2 * 8 * MOMENT_VALUES * nobin,
         "finalize": 0,
     }
 

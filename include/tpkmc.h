@@ -57,7 +57,7 @@
 extern "C" {
 #endif
 
-#define TPKMC_ABI_VERSION 1
+#define TPKMC_ABI_VERSION 2
 
 enum {
     TPKMC_OK = 0,
@@ -132,15 +132,15 @@ enum {
 enum { TPKMC_G_PX = 0, TPKMC_G_EKIN = 3, TPKMC_G_VMAX2 = 4, TPKMC_G_VIRIAL = 5, TPKMC_G_MASS = 6,
        TPKMC_G_DT = 7 };
 
-/* Per-o-bin moments (double[nobin * 11] per instance, o-bin index
+/* Per-o-bin moments (double[nobin * 12] per instance, o-bin index
  * bx + nobin[0] * (by + nobin[1] * bz) of the post-step position):
  *  0 count; 1..3 sum m v_a; 4..6 sum m (v_a - vbar_a)^2 with vbar the bin's
- *  mean velocity; 7..9 sum over colliders of (1/2) s_a dp_a / dt with s the
- *  separation from the partner at closest approach and dp the momentum
- *  change; 10 number of colliders.  Pressure of a bin of volume V:
- *  p = (sum_a [4+a] + sum_a [7+a]) / (3 V); temperature T = sum_a [4+a] /
- *  (3 count). */
-#define TPKMC_MOMENT_STRIDE 11
+ *  mass-weighted mean velocity; 7..9 sum over colliders of (1/2) s_a dp_a /
+ *  dt with s the separation from the partner at closest approach and dp the
+ *  momentum change; 10 number of colliders; 11 sum m.  Pressure of a bin of
+ *  volume V: p = (sum_a [4+a] + sum_a [7+a]) / (3 V); temperature
+ *  T = sum_a [4+a] / (3 count). */
+#define TPKMC_MOMENT_STRIDE 12
 
 typedef struct tpkmc_handle tpkmc_handle;
 
@@ -182,12 +182,19 @@ typedef struct {
 /* Structure-of-arrays particle state, device pointers, n entries each.
  * x..vz are double* (FP64 handle) or float* (FP32 handle).  id: unique
  * uint32 per particle (read; permuted only with ALLOW_REORDER).  alive:
- * uint8 0/1, or NULL for all alive (then no axis may be ABSORB). */
+ * uint8 0/1, or NULL for all alive (then no axis may be ABSORB).  mass:
+ * NULL (every particle has params.mass) or one mass per particle, of the
+ * handle's real type, for a mixture.  Scattering then keeps the
+ * mass-weighted centre-of-mass velocity and the relative speed, and moments
+ * and global sums weight each particle by its mass.  A mass that is not
+ * finite and positive makes the particle non-finite.  The masses are
+ * permuted with ALLOW_REORDER. */
 typedef struct {
     int64_t n;
     void *x, *y, *z, *vx, *vy, *vz;
     uint32_t* id;
     uint8_t* alive;
+    void* mass;
 } tpkmc_particles;
 
 /* Output device pointers; any may be NULL (that output is skipped).
@@ -220,7 +227,7 @@ int tpkmc_version(void);
 const char* tpkmc_strerror(int code);
 
 /* Allocates a handle and all its device scratch on cfg->device (memory is
- * sized from the capacities: about 50 B per particle in FP32, 90 B in FP64,
+ * sized from the capacities: about 54 B per particle in FP32, 98 B in FP64,
  * 8 B per c-bin, 24 B per o-bin).  *out is NULL on failure. */
 int tpkmc_create(const tpkmc_config* cfg, tpkmc_handle** out);
 

@@ -223,7 +223,7 @@ __global__ void k_moments_final(const Inst<real>* inst, double* moments, double*
     double* S = shift + ob * 3;
     const double cnt = M[0];
     if (cnt > 0.0) {
-        const double mass = I.mass_d * cnt;
+        const double mass = M[11];
         for (int a = 0; a < 3; ++a) {
             const double s1 = M[1 + a], s2 = M[4 + a];
             const double mean_off = s1 / mass;
@@ -248,6 +248,7 @@ struct tpkmc_handle {
     int32_t max_inst = 0;
     int32_t *key = nullptr, *rank = nullptr, *start = nullptr, *tiles = nullptr, *src = nullptr, *best = nullptr;
     void* rec = nullptr;
+    void* rmass = nullptr;
     void* inst = nullptr;
     Blk* blk = nullptr;
     Chunk* chunks = nullptr;
@@ -369,7 +370,7 @@ int make_plan(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* i
         d.seed_hi = (uint32_t)(p.seed >> 32);
         d.step_lo = (uint32_t)p.step;
         d.instance = p.instance;
-        d.flags = p.flags;
+        d.flags = p.flags | (s->mass ? kHasMass : 0u);
         d.dt = (real)p.dt;
         // Largest accepted d_min^2: sigma = pi D^2 in space, sigma = 2 D in
         // the plane (same expressions as the reference).
@@ -460,6 +461,8 @@ StepArgs<real> make_args(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_
     a.rank = h->rank;
     a.start = h->start;
     a.rec = (real*)h->rec;
+    a.mass = (real*)s->mass;
+    a.rmass = (real*)h->rmass;
     a.src = h->src;
     a.best = h->best;
     a.bkey = h->bkey;
@@ -669,7 +672,7 @@ void free_all(tpkmc_handle* h) {
         if (h->stage_ev[k]) hipEventDestroy(h->stage_ev[k]);
     }
     hipFree(h->key); hipFree(h->rank); hipFree(h->start); hipFree(h->tiles);
-    hipFree(h->src); hipFree(h->best); hipFree(h->rec); hipFree(h->inst);
+    hipFree(h->src); hipFree(h->best); hipFree(h->rec); hipFree(h->rmass); hipFree(h->inst);
     hipFree(h->blk); hipFree(h->chunks); hipFree(h->bkey); hipFree(h->cpart); hipFree(h->gpart); hipFree(h->shift); hipFree(h->pair_count); hipFree(h->status);
 }
 
@@ -726,6 +729,7 @@ int tpkmc_create(const tpkmc_config* cfg, tpkmc_handle** out) {
     bad |= dalloc(&h->src, h->max_n);
     bad |= dalloc(&h->best, h->max_n);
     bad |= hipMalloc(&h->rec, rs * 8 * (size_t)std::max<int64_t>(h->max_n, 1)) != hipSuccess;
+    bad |= hipMalloc(&h->rmass, rs * (size_t)std::max<int64_t>(h->max_n, 1)) != hipSuccess;
     bad |= hipMalloc(&h->inst, inst_sz * (size_t)h->max_inst) != hipSuccess;
     bad |= dalloc(&h->blk, h->max_blk);
     bad |= dalloc(&h->gpart, h->max_blk * kGPart);

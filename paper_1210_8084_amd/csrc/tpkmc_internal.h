@@ -42,6 +42,10 @@ struct Inst {
     double dt_cap, dx_d;      // caller's dt; smallest c-bin width over axes with > 1 c-bin (0: none)
 };
 
+// Bit of Inst::flags, set by the host (outside the public flag bits): the
+// particles carry their own masses.
+constexpr uint32_t kHasMass = 1u << 31;
+
 // Block table entry: instance index and first particle of the work-group.
 struct Blk {
     int32_t inst;
@@ -71,6 +75,8 @@ struct StepArgs {
     int32_t* rank;            // rank inside its c-bin
     int32_t* start;           // counts, then exclusive prefix (ncells + 1)
     real* rec;                // c-bin ordered records, 8 reals per particle
+    real* mass;               // caller's per-particle masses, or null
+    real* rmass;              // masses in record order (with mass only)
     int32_t* src;             // record -> caller index
     int32_t* best;            // record -> partner record or -1 (FP64 search)
     unsigned long long* bkey; // record -> (d_min^2 bits, partner record) (FP32 search)

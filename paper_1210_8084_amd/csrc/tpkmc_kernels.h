@@ -246,7 +246,11 @@ __global__ void __launch_bounds__(kBlock) k_key(StepArgs<real> a) {
         const bool alive = a.alive ? a.alive[p] != 0 : true;
         const real x = a.x[p], y = a.y[p], z = a.z[p];
         const real vx = a.vx[p], vy = a.vy[p], vz = a.vz[p];
-        const bool fin = finite3(x, y, z) && finite3(vx, vy, vz);
+        bool fin = finite3(x, y, z) && finite3(vx, vy, vz);
+        if (a.mass) {
+            const real m = a.mass[p];
+            fin = fin && m > real(0) && m < real(INFINITY);
+        }
         if (alive && fin) {
             const int cx = axis_bin(x, I.lo[0], I.inv_w[0], I.n[0]);
             const int cy = axis_bin(y, I.lo[1], I.inv_w[1], I.n[1]);
@@ -304,9 +308,11 @@ __global__ void __launch_bounds__(kBlock) k_scatter(StepArgs<real> a) {
         Rec<real>::store(a.rec, dst, x, y, z, a.id[p], vx, vy, vz, fl);
         a.src[dst] = (int32_t)p;
         if (a.bkey) a.bkey[dst] = ~0ull;
+        if (a.mass) a.rmass[dst] = a.mass[p];
         // Diagnostic: a particle faster than one c-bin per step on some axis.
         const real dt = I.dt;
-        fast = fl && finite3(x, y, z) && finite3(vx, vy, vz) &&
+        const bool mass_ok = !a.mass || (a.mass[p] > real(0) && a.mass[p] < real(INFINITY));
+        fast = fl && mass_ok && finite3(x, y, z) && finite3(vx, vy, vz) &&
                (fabs(vx) * dt > I.w[0] || fabs(vy) * dt > I.w[1] || fabs(vz) * dt > I.w[2]);
     }
     const uint64_t fm = __ballot(fast);
@@ -855,7 +861,7 @@ __device__ __forceinline__ void moment_flush(MomentTable& tab, const StepArgs<re
     double* dst = slot >= 0 ? tab.val[slot] : a.moments + (int64_t)ob * TPKMC_MOMENT_STRIDE;
 #pragma unroll
     for (int k = 0; k < TPKMC_MOMENT_STRIDE; ++k)
-        if (k < 7 || mv[k] != 0.0) unsafeAtomicAdd(dst + k, mv[k]);
+        if (k < 7 || k == 11 || mv[k] != 0.0) unsafeAtomicAdd(dst + k, mv[k]);
 }
 
 template <typename real>
@@ -868,6 +874,7 @@ __global__ void __launch_bounds__(kMoveLanes) k_move(StepArgs<real> a) {
     const int lane = tid & 63;
     const int64_t end = I.off + I.cnt;
     const bool reorder = (I.flags & TPKMC_ALLOW_REORDER) != 0;
+    const bool has_mass = (I.flags & kHasMass) != 0;
     if (a.moments) {
         for (int t = tid; t < kSlots; t += kMoveLanes) {
             tab.key[t] = -1;
@@ -912,9 +919,11 @@ __global__ void __launch_bounds__(kMoveLanes) k_move(StepArgs<real> a) {
                     a.vx[dst] = vx; a.vy[dst] = vy; a.vz[dst] = vz;
                     a.id[dst] = idi;
                     if (a.alive) a.alive[dst] = 0;
+                    if (has_mass) a.mass[dst] = a.rmass[i];
                 }
             } else {
                 const real dt = I.dt;
+                const real mi = has_mass ? a.rmass[i] : I.mass;
                 const int32_t j = j_pre;
                 const bool mutual = j >= 0 && partner_of<real>(a, j) == (int32_t)i;
                 ghave += j >= 0 ? 1.0 : 0.0;
@@ -941,16 +950,32 @@ __global__ void __launch_bounds__(kMoveLanes) k_move(StepArgs<real> a) {
                     double nh[3];
                     pair_direction(I.seed_lo, I.seed_hi, I.step_lo, I.instance, isA ? idi : idj, isA ? idj : idi,
                                    (I.flags & TPKMC_PLANAR) != 0, nh);
-                    // Equal masses: centre-of-mass velocity kept, relative speed g
-                    // kept, outgoing directions opposite along nhat.
+                    // Centre-of-mass velocity and relative speed g kept, outgoing
+                    // directions opposite along nhat.  Equal masses: the mean
+                    // velocity, each moving g/2; masses mA, mB: the
+                    // mass-weighted mean, A moving mB g / (mA + mB) and B
+                    // mA g / (mA + mB).
                     const real g = sqrt(vv);
-                    const real h = real(0.5) * g;
                     const real sg = isA ? real(1) : real(-1);
-                    const real cmx = real(0.5) * (vxA + vxB), cmy = real(0.5) * (vyA + vyB), cmz = real(0.5) * (vzA + vzB);
-                    const real hx = h * (real)nh[0], hy = h * (real)nh[1], hz = h * (real)nh[2];
-                    nvx = isA ? cmx + hx : cmx - hx;
-                    nvy = isA ? cmy + hy : cmy - hy;
-                    nvz = isA ? cmz + hz : cmz - hz;
+                    if (!has_mass) {
+                        const real h = real(0.5) * g;
+                        const real cmx = real(0.5) * (vxA + vxB), cmy = real(0.5) * (vyA + vyB),
+                                   cmz = real(0.5) * (vzA + vzB);
+                        const real hx = h * (real)nh[0], hy = h * (real)nh[1], hz = h * (real)nh[2];
+                        nvx = isA ? cmx + hx : cmx - hx;
+                        nvy = isA ? cmy + hy : cmy - hy;
+                        nvz = isA ? cmz + hz : cmz - hz;
+                    } else {
+                        const real mj = a.rmass[j];
+                        const real mA = isA ? mi : mj, mB = isA ? mj : mi;
+                        const real M = mA + mB;
+                        const real hA = (mB / M) * g, hB = (mA / M) * g;
+                        const real cmx = (mA * vxA + mB * vxB) / M, cmy = (mA * vyA + mB * vyB) / M,
+                                   cmz = (mA * vzA + mB * vzB) / M;
+                        nvx = isA ? cmx + hA * (real)nh[0] : cmx - hB * (real)nh[0];
+                        nvy = isA ? cmy + hA * (real)nh[1] : cmy - hB * (real)nh[1];
+                        nvz = isA ? cmz + hA * (real)nh[2] : cmz - hB * (real)nh[2];
+                    }
                     // Split move at the point of closest approach.
                     const real rest = dt - tp;
                     nx = (x + vx * tp) + nvx * rest;
@@ -959,9 +984,9 @@ __global__ void __launch_bounds__(kMoveLanes) k_move(StepArgs<real> a) {
                     // Virial: separation at closest approach (from the partner to
                     // this particle) times this particle's momentum change.
                     const real sx = sg * (rx + tp * ux), sy = sg * (ry + tp * uy), sz = sg * (rz + tp * uz);
-                    virx = (double)(real(0.5) * sx * (I.mass * (nvx - vx)) / dt);
-                    viry = (double)(real(0.5) * sy * (I.mass * (nvy - vy)) / dt);
-                    virz = (double)(real(0.5) * sz * (I.mass * (nvz - vz)) / dt);
+                    virx = (double)(real(0.5) * sx * (mi * (nvx - vx)) / dt);
+                    viry = (double)(real(0.5) * sy * (mi * (nvy - vy)) / dt);
+                    virz = (double)(real(0.5) * sz * (mi * (nvz - vz)) / dt);
                     if (isA) {
                         gpairs += 1.0;
                         if (I.flags & TPKMC_EMIT_PAIRS) { emit = true; emit_a = idi; emit_b = idj; }
@@ -993,11 +1018,13 @@ __global__ void __launch_bounds__(kMoveLanes) k_move(StepArgs<real> a) {
                 a.x[dst] = nx; a.y[dst] = ny; a.z[dst] = nz;
                 a.vx[dst] = nvx; a.vy[dst] = nvy; a.vz[dst] = nvz;
                 if (reorder) a.id[dst] = idi;
+                if (reorder && has_mass) a.mass[dst] = mi;
                 if (a.alive && (reorder || gone)) a.alive[dst] = gone ? 0 : 1;
                 if (gone) gabs += 1.0;
-                const bool fin = finite3(nx, ny, nz) && finite3(nvx, nvy, nvz);
+                const bool fin = finite3(nx, ny, nz) && finite3(nvx, nvy, nvz) &&
+                                 (!has_mass || (mi > real(0) && mi < real(INFINITY)));
                 if (!gone && fin) {
-                    const double m = I.mass_d;
+                    const double m = has_mass ? (double)mi : I.mass_d;
                     const double dvx = (double)nvx, dvy = (double)nvy, dvz = (double)nvz;
                     const double v2 = (dvx * dvx + dvy * dvy) + dvz * dvz;
                     gpx += m * dvx; gpy += m * dvy; gpz += m * dvz;
@@ -1023,6 +1050,7 @@ __global__ void __launch_bounds__(kMoveLanes) k_move(StepArgs<real> a) {
                         mv[0] += 1.0; mv[1] += m * ex; mv[2] += m * ey; mv[3] += m * ez;
                         mv[4] += m * ex * ex; mv[5] += m * ey * ey; mv[6] += m * ez * ez;
                         mv[7] += virx; mv[8] += viry; mv[9] += virz; mv[10] += mutual ? 1.0 : 0.0;
+                        mv[11] += m;
                     }
                 }
             }
@@ -1053,7 +1081,7 @@ __global__ void __launch_bounds__(kMoveLanes) k_move(StepArgs<real> a) {
             if (ob < 0) continue;
             double* M = a.moments + (int64_t)ob * TPKMC_MOMENT_STRIDE;
             for (int k = 0; k < TPKMC_MOMENT_STRIDE; ++k)
-                if (k < 7 || tab.val[t][k] != 0.0) unsafeAtomicAdd(M + k, tab.val[t][k]);
+                if (k < 7 || k == 11 || tab.val[t][k] != 0.0) unsafeAtomicAdd(M + k, tab.val[t][k]);
         }
     }
     double v[11] = {gpx, gpy, gpz, gek, gvm, gvir, gm, galive, gpairs, gabs, ghave};

@@ -27,7 +27,7 @@ STATUS_PAIR_OVERFLOW, STATUS_NONFINITE, STATUS_FAST = 1, 2, 4
 CNT = dict(alive=0, pairs=1, tests=2, cand=3, fast=4, nonfinite=5, absorbed=6, have_best=7)
 GLB = dict(px=0, py=1, pz=2, ekin=3, vmax2=4, virial=5, mass=6, dt=7)
 PHASES = ("clear", "key", "scan", "scatter", "search", "move", "finalize")
-MOMENT_STRIDE = 11
+MOMENT_STRIDE = 12
 
 OK, EINVAL, ENOMEM, EHIP, ECAPACITY, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 
@@ -58,7 +58,7 @@ class Params(ctypes.Structure):
 
 class Particles(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64)] + [(k, ctypes.c_void_p) for k in ("x", "y", "z", "vx", "vy", "vz")] + \
-               [("id", ctypes.c_void_p), ("alive", ctypes.c_void_p)]
+               [("id", ctypes.c_void_p), ("alive", ctypes.c_void_p), ("mass", ctypes.c_void_p)]
 
 
 class Outputs(ctypes.Structure):
@@ -164,6 +164,8 @@ def to_device(state, precision=FP64, device="cuda"):
     if alive is None:
         alive = np.ones(len(state["x"]), np.uint8)
     out["alive"] = torch.as_tensor(np.ascontiguousarray(alive, dtype=np.uint8), device=device).contiguous()
+    if state.get("mass") is not None:
+        out["mass"] = torch.as_tensor(np.ascontiguousarray(state["mass"]), device=device).to(dt).contiguous()
     return out
 
 
@@ -172,6 +174,8 @@ def to_host(dstate):
     out = {k: dstate[k].detach().cpu().numpy().astype(np.float64) for k in ("x", "y", "z", "vx", "vy", "vz")}
     out["id"] = dstate["id"].detach().cpu().numpy().view(np.uint32).copy()
     out["alive"] = dstate["alive"].detach().cpu().numpy().copy()
+    if dstate.get("mass") is not None:
+        out["mass"] = dstate["mass"].detach().cpu().numpy().astype(np.float64)
     return out
 
 
@@ -182,6 +186,7 @@ def particles(dstate, with_alive=True) -> Particles:
         setattr(S, k, dstate[k].data_ptr())
     S.id = dstate["id"].data_ptr()
     S.alive = dstate["alive"].data_ptr() if with_alive and dstate.get("alive") is not None else None
+    S.mass = dstate["mass"].data_ptr() if dstate.get("mass") is not None else None
     return S
 
 

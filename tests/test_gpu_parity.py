@@ -93,6 +93,7 @@ def assert_outputs_match(go, ro, mass):
     gm, rm = go["moments"], ro["moments"]
     assert np.array_equal(gm[:, 0], rm[:, 0])
     assert np.array_equal(gm[:, 10], rm[:, 10])
+    np.testing.assert_allclose(gm[:, 11], rm[:, 11], rtol=1e-12, atol=0)
     # Sums over up to a few thousand particles in another order: relative
     # error ~ count * eps of the largest magnitude involved.
     vmax = math.sqrt(rg[4])
@@ -602,3 +603,60 @@ def test_fp32_rank_by_contact_time(T, oracle):
     assert o0[0]["counters"][0][1] == pytest.approx(ro["counters"][1], rel=0.02)
     common = set(pairset(o0[0]["pairs"])) & set(pairset(ro["pairs"]))
     assert len(common) > 0.97 * len(ro["pairs"])
+
+
+# ------------------------------------------------------------ mixtures
+@pytest.mark.parametrize("case", CASES[:3] + [CASES[6]], ids=lambda c: f"s{c['seed']}-{c['ncell']}-{c['bc']}")
+def test_fp64_mixture_bit_exact(T, oracle, case):
+    """Per-particle masses: mass-weighted scattering, moments and sums; the
+    state and pairs equal the oracle's bit for bit over two steps."""
+    w = W.random_box(n=2999, seed=case["seed"] + 90, ncell=case["ncell"], bc=case["bc"], d_over_w=0.7,
+                     dt_over=0.6, nobin=(3, 2, 1))
+    w.state["mass"] = np.random.default_rng(case["seed"]).uniform(0.3, 3.0, w.n)
+    w.state = W.shuffle_state(w.state, seed=case["seed"] + 9)
+    _say(f"mixture case {case}")
+    got, gouts, _ = gpu_steps(T, w, T.FP64, steps=2)
+    want, routs = oracle_steps(oracle, w, steps=2)
+    assert_state_equal(got, want)
+    for go, ro in zip(gouts, routs):
+        assert_outputs_match(go, ro, 3.0)
+    assert routs[0]["counters"][1] > 50
+
+
+def test_mixture_reorder_keeps_masses_with_their_particles(T, oracle):
+    """With ALLOW_REORDER the mass array is permuted with the ids; an invalid
+    mass makes its particle non-finite on both sides."""
+    w = W.random_box(n=4000, seed=95, ncell=(6, 5, 4), d_over_w=0.6, dt_over=0.5)
+    m = np.random.default_rng(3).uniform(0.5, 2.0, w.n)
+    m[17] = 0.0
+    m[18] = np.nan
+    w.state["mass"] = m
+    got, gouts, status = gpu_steps(T, w, T.FP64, flags=T.ALLOW_REORDER | T.EMIT_PAIRS)
+    want, routs = oracle_steps(oracle, w)
+    by_id = {int(i): k for k, i in enumerate(got["id"])}
+    for k in range(w.n):
+        gk = by_id[int(w.state["id"][k])]
+        assert (got["mass"][gk] == m[k]) or (np.isnan(m[k]) and np.isnan(got["mass"][gk]))
+        assert got["x"][gk] == want["x"][k] or (np.isnan(want["x"][k]) and np.isnan(got["x"][gk]))
+    assert gouts[0]["counters"][0].tolist() == routs[0]["counters"].tolist()
+    assert routs[0]["counters"][oracle.CNT["nonfinite"]] == 2
+    assert status & T.STATUS_NONFINITE
+
+
+def test_fp32_mixture_conserves(T, oracle):
+    """FP32 mixture: momentum and energy kept to FP32 rounding, the pair count
+    tracks the oracle's."""
+    w = W.random_box(n=20000, seed=96, ncell=(10, 8, 6), bc=(P, P, P), d_over_w=0.6, dt_over=0.5)
+    w.state["mass"] = np.where(np.arange(w.n) % 3 == 0, 4.0, 1.0)
+    f32 = W.copy_state(w.state, dtype=np.float32)
+    got, gouts, _ = gpu_steps(T, w, T.FP32, steps=3, state=f32)
+    m = f32["mass"].astype(np.float64)
+    p0 = [float(np.sum(m * f32[k].astype(np.float64))) for k in ("vx", "vy", "vz")]
+    p1 = [float(np.sum(m * got[k])) for k in ("vx", "vy", "vz")]
+    e0 = 0.5 * float(np.sum(m * sum(f32[k].astype(np.float64) ** 2 for k in ("vx", "vy", "vz"))))
+    e1 = 0.5 * float(np.sum(m * sum(got[k] ** 2 for k in ("vx", "vy", "vz"))))
+    assert e1 == pytest.approx(e0, rel=2e-6)
+    assert np.allclose(p1, p0, atol=2e-6 * math.sqrt(2 * e0 * m.sum()))
+    assert gouts[-1]["globals"][0][6] == pytest.approx(m.sum(), rel=1e-12)
+    ro = oracle.step(W.copy_state(f32), w.grid, w.params)
+    assert gouts[0]["counters"][0][1] == pytest.approx(ro["counters"][1], rel=0.02)
