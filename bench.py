@@ -88,14 +88,15 @@ def read_traffic(workload, precision):
 
 def cpu_baseline(w, nthreads):
     """The oracle as it stands, on a bounded sample of the same workload:
-    one full step of an x-slab with the same density and c-bin size (uniform
-    workloads), else the closest-partner search of a random particle subset
-    scaled to all particles."""
+    one full step of the lower half (an x-slab with the same density and
+    c-bin size) for uniform workloads, about ten seconds on 16 host threads,
+    else the closest-partner search of a random particle subset scaled to
+    all particles."""
     from oracle import ref
     from paper_1210_8084_amd import workloads as W
     g = w.grid
     if w.name in ("sedov", "equilibration"):
-        frac = 4
+        frac = 2
         nx = g["ncell"][0] // frac
         hi_x = g["lo"][0] + (g["hi"][0] - g["lo"][0]) * nx / g["ncell"][0]
         sel = w.state["x"] < hi_x
