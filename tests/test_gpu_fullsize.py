@@ -4,7 +4,8 @@ FP32 handle: not bit-comparable with the FP64 oracle, so it is checked by
 properties (per-collision conservation to FP32 rounding, pair validity under
 the FP64 criteria, free streaming) and statistics (collision fraction).
 
-Full sizes (16M-particle Sedov, 4M Sod, 8M Noh): one step in the launch
+Full sizes (16M-particle Sedov, 4M Sod, 8M Noh, the 4M 2D blast, the 8M
+spherical Noh, the 16M Sedov with the adaptive time step): one step in the launch
 configuration of the benchmark; sampled particles are recomputed one by one
 by the oracle (their closest candidates, their partners' closest candidates,
 their post-step state)."""
@@ -157,11 +158,20 @@ def _sampled_parity(T, oracle, w, precision, flags, nsample, seed):
     return got, o, sample, ref, partner, alive, g
 
 
+def _sedov_adaptive():
+    w = W.sedov()
+    w.params = dict(w.params, dt=1.0, adaptive_dt=True)
+    return w
+
+
 @pytest.mark.parametrize("make", [
     lambda: W.sedov(),
     lambda: W.sod(n=4_000_000, ncell=1000, nobin=200, dt=1.134e-4),
     lambda: W.noh(),
-], ids=["sedov16M", "sod4M", "noh8M"])
+    lambda: W.sedov2d(),
+    lambda: W.noh3d(),
+    _sedov_adaptive,
+], ids=["sedov16M", "sod4M", "noh8M", "sedov2d4M", "noh3d8M", "sedov16M-adaptive"])
 def test_fp64_fullsize_sampled_bit_exact(T, oracle, make):
     w = make()
     got, o, sample, ref, partner, alive, g = _sampled_parity(T, oracle, w, T.FP64, T.ALLOW_REORDER, 3000, 1)
@@ -169,6 +179,7 @@ def test_fp64_fullsize_sampled_bit_exact(T, oracle, make):
     c = o["counters"][0]
     assert c[0] == w.n
     assert c[2] == oracle.count_tests(w.state, w.grid)
+    assert o["globals"][0][7] == oracle.step_dt(w.state, w.grid, w.params)
     frac = (partner >= 0).mean()
     assert abs(2 * c[1] / w.n - frac) < 5 * math.sqrt(frac * (1 - frac) / len(sample)) + 1e-3
     del got
