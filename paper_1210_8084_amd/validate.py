@@ -76,13 +76,13 @@ def _conservation(w, r):
                 collided_fraction=float(2 * r["counters"][:, 1].mean() / w.n))
 
 
-def sod(precision, n=4_000_000, steps=500, kn=1e-3, planar=False):
+def sod(precision, n=4_000_000, steps=500, kn=1e-3, planar=False, seed=1):
     from oracle import analytic as A
     from paper_1210_8084_amd import workloads as W
     if planar:
-        w = W.sod2d(n=n, ncell=1000, nobin=200, dt=1.134e-4, kn=kn)
+        w = W.sod2d(n=n, ncell=1000, nobin=200, dt=1.134e-4, kn=kn, seed=seed)
     else:
-        w = W.sod(n=n, ncell=1000, nobin=200, dt=1.134e-4, kn=kn)
+        w = W.sod(n=n, ncell=1000, nobin=200, dt=1.134e-4, kn=kn, seed=seed)
     f = 2 if planar else 3
     r = _run(w, precision, steps, progress=100)
     t = steps * w.params["dt"]
@@ -108,10 +108,10 @@ def sod(precision, n=4_000_000, steps=500, kn=1e-3, planar=False):
                 **_conservation(w, r))
 
 
-def noh(precision, n=8_000_000, steps=800, planar=False):
+def noh(precision, n=8_000_000, steps=800, planar=False, seed=1):
     from oracle import analytic as A
     from paper_1210_8084_amd import workloads as W
-    w = (W.noh2d if planar else W.noh)(n=n, steps=steps)
+    w = (W.noh2d if planar else W.noh)(n=n, steps=steps, seed=seed)
     f = 2 if planar else 3
     r = _run(w, precision, steps, progress=200)
     t = steps * w.params["dt"]
@@ -140,13 +140,13 @@ def noh(precision, n=8_000_000, steps=800, planar=False):
                 **_conservation(w, r))
 
 
-def noh3d(precision, n=8_000_000, steps=160):
+def noh3d(precision, n=8_000_000, steps=160, seed=1):
     """Spherical Noh: radial number density against the analytic solution
     with d = 3 (jump ((gamma + 1) / (gamma - 1))^3 = 64), and the shocked
     temperature m v0^2 / f."""
     from oracle import analytic as A
     from paper_1210_8084_amd import workloads as W
-    w = W.noh3d(n=n, steps=steps)
+    w = W.noh3d(n=n, steps=steps, seed=seed)
     r = _run(w, precision, steps, progress=40)
     t = steps * w.params["dt"]
     st = r["state"]
@@ -173,10 +173,10 @@ def noh3d(precision, n=8_000_000, steps=160):
                 **_conservation(w, r))
 
 
-def sedov(precision, n=16_000_000, steps=600, planar=False):
+def sedov(precision, n=16_000_000, steps=600, planar=False, seed=1):
     from oracle import analytic as A
     from paper_1210_8084_amd import workloads as W
-    w = (W.sedov2d if planar else W.sedov)(n=n, steps=steps)
+    w = (W.sedov2d if planar else W.sedov)(n=n, steps=steps, seed=seed)
     r = _run(w, precision, steps, progress=200)
     t = steps * w.params["dt"]
     st = r["state"]
@@ -199,38 +199,52 @@ def sedov(precision, n=16_000_000, steps=600, planar=False):
                 **_conservation(w, r))
 
 
+def _one(name, prec, quick, seed):
+    planar = name.endswith("2d")
+    base = name[:-2] if name.endswith(("2d", "3d")) else name
+    if base == "sod":
+        return sod(prec, n=400_000 if quick else 4_000_000, steps=100 if quick else 500, planar=planar, seed=seed)
+    if base == "noh" and name.endswith("3d"):
+        return noh3d(prec, n=800_000 if quick else 8_000_000, steps=160, seed=seed)
+    if base == "noh":
+        return noh(prec, n=800_000 if quick else 8_000_000, steps=200 if quick else 800, planar=planar, seed=seed)
+    n_full = 4_000_000 if planar else 16_000_000
+    return sedov(prec, n=n_full // 8 if quick else n_full, steps=150 if quick else 600, planar=planar, seed=seed)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=None)
     ap.add_argument("--quick", action="store_true", help="smaller sizes and fewer steps")
     ap.add_argument("--only", default="sod,noh,sedov,sod2d,noh2d,sedov2d,noh3d")
+    ap.add_argument("--seeds", default="1", help="comma-separated workload seeds; with several, the "
+                    "report adds the mean and spread of L1 and of the FP32 - FP64 difference")
     args = ap.parse_args()
     from paper_1210_8084_amd import tpkmc as T
+    seeds = [int(v) for v in args.seeds.split(",")]
     report = {}
     for name in args.only.split(","):
-        planar = name.endswith("2d")
-        base = name[:-2] if name.endswith(("2d", "3d")) else name
-        for prec, label in ((T.FP32, "fp32"), (T.FP64, "fp64")):
-            print(f"== {name} {label}", flush=True)
-            if base == "sod":
-                res = sod(prec, n=400_000 if args.quick else 4_000_000, steps=100 if args.quick else 500,
-                          planar=planar)
-            elif base == "noh" and name.endswith("3d"):
-                res = noh3d(prec, n=800_000 if args.quick else 8_000_000, steps=160)
-            elif base == "noh":
-                res = noh(prec, n=800_000 if args.quick else 8_000_000, steps=200 if args.quick else 800,
-                          planar=planar)
-            else:
-                n_full = 4_000_000 if planar else 16_000_000
-                res = sedov(prec, n=n_full // 8 if args.quick else n_full, steps=150 if args.quick else 600,
-                            planar=planar)
-            report[f"{name}_{label}"] = res
-            brief = {k: v for k, v in res.items() if not k.startswith(("profile", "analytic_density"))}
-            print(json.dumps(brief), flush=True)
-        a, b = report.get(f"{name}_fp32"), report.get(f"{name}_fp64")
-        if a and b:
-            report[f"{name}_fp32_minus_fp64_l1_density"] = a["l1_density"] - b["l1_density"]
-            print(f"{name}: L1 density FP32 - FP64 = {a['l1_density'] - b['l1_density']:.3e}", flush=True)
+        diffs, l1 = [], {"fp32": [], "fp64": []}
+        for seed in seeds:
+            for prec, label in ((T.FP32, "fp32"), (T.FP64, "fp64")):
+                print(f"== {name} {label} seed {seed}", flush=True)
+                res = _one(name, prec, args.quick, seed)
+                key = f"{name}_{label}" if len(seeds) == 1 else f"{name}_{label}_seed{seed}"
+                report[key] = res
+                l1[label].append(res["l1_density"])
+                brief = {k: v for k, v in res.items() if not k.startswith(("profile", "analytic_density"))}
+                print(json.dumps(brief), flush=True)
+            diffs.append(l1["fp32"][-1] - l1["fp64"][-1])
+            print(f"{name} seed {seed}: L1 density FP32 - FP64 = {diffs[-1]:.3e}", flush=True)
+        if len(seeds) == 1:
+            report[f"{name}_fp32_minus_fp64_l1_density"] = diffs[0]
+        else:
+            summ = dict(seeds=seeds, l1_fp32_mean=float(np.mean(l1["fp32"])), l1_fp64_mean=float(np.mean(l1["fp64"])),
+                        l1_fp64_spread=float(np.std(l1["fp64"], ddof=1)),
+                        diff_mean=float(np.mean(diffs)), diff_spread=float(np.std(diffs, ddof=1)),
+                        diff_mean_stderr=float(np.std(diffs, ddof=1) / math.sqrt(len(diffs))))
+            report[f"{name}_seed_summary"] = summ
+            print(f"{name}: " + json.dumps(summ), flush=True)
     if args.out:
         with open(args.out, "w") as f:
             json.dump(report, f, indent=1)
