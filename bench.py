@@ -56,9 +56,9 @@ def phase_bytes(rs, n, ncell_tot, nobin, reorder):
     rec = 8 * rs
     return {
         "clear": 4 * ncell_tot + 8 * MOMENT_VALUES * nobin,
-        "key": n * (6 * rs + 1 + 8),
+        "key": n * (6 * rs + 1 + 4),
         "scan": 12 * ncell_tot,
-        "scatter": n * (6 * rs + 4 + 1 + 8 + 4 + rec + 4),
+        "scatter": n * (6 * rs + 4 + 1 + 4 + 4 + rec + (0 if reorder else 4)),
         "search": n * (rec + 4) + 4 * ncell_tot,
         "move": n * (rec + 4 + 6 * rs + 1 + (4 if reorder else 4)) + 2 * 8 * MOMENT_VALUES * nobin,
         "finalize": 0,

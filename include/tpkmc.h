@@ -227,7 +227,7 @@ int tpkmc_version(void);
 const char* tpkmc_strerror(int code);
 
 /* Allocates a handle and all its device scratch on cfg->device (memory is
- * sized from the capacities: about 60 B per particle in FP32, 88 B in FP64,
+ * sized from the capacities: about 56 B per particle in FP32, 84 B in FP64,
  * 8 B per c-bin, 24 B per o-bin).  *out is NULL on failure. */
 int tpkmc_create(const tpkmc_config* cfg, tpkmc_handle** out);
 

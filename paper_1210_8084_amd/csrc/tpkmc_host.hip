@@ -246,7 +246,7 @@ struct tpkmc_handle {
     int device = 0, precision = TPKMC_FP64;
     int64_t max_n = 0, max_cells = 0, max_obins = 0, max_blk = 0;
     int32_t max_inst = 0;
-    int32_t *key = nullptr, *rank = nullptr, *start = nullptr, *tiles = nullptr, *src = nullptr, *best = nullptr;
+    int32_t *rank = nullptr, *start = nullptr, *tiles = nullptr, *src = nullptr, *best = nullptr;
     void* rec = nullptr;
     void* rmass = nullptr;
     void* inst = nullptr;
@@ -457,7 +457,6 @@ StepArgs<real> make_args(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_
     a.inst = (const Inst<real>*)h->inst;
     a.blk = h->blk;
     a.nblk = P.nblk;
-    a.key = h->key;
     a.rank = h->rank;
     a.start = h->start;
     a.rec = (real*)h->rec;
@@ -671,7 +670,7 @@ void free_all(tpkmc_handle* h) {
         if (h->stage[k]) hipHostFree(h->stage[k]);
         if (h->stage_ev[k]) hipEventDestroy(h->stage_ev[k]);
     }
-    hipFree(h->key); hipFree(h->rank); hipFree(h->start); hipFree(h->tiles);
+    hipFree(h->rank); hipFree(h->start); hipFree(h->tiles);
     hipFree(h->src); hipFree(h->best); hipFree(h->rec); hipFree(h->rmass); hipFree(h->inst);
     hipFree(h->blk); hipFree(h->chunks); hipFree(h->bkey); hipFree(h->cpart); hipFree(h->gpart); hipFree(h->shift); hipFree(h->pair_count); hipFree(h->status);
 }
@@ -722,7 +721,6 @@ int tpkmc_create(const tpkmc_config* cfg, tpkmc_handle** out) {
     const size_t inst_sz = cfg->precision == TPKMC_FP64 ? sizeof(Inst<double>) : sizeof(Inst<float>);
     const int64_t tiles = (cfg->max_cells + 1 + kScanTile - 1) / kScanTile + 1;
     int bad = 0;
-    bad |= dalloc(&h->key, h->max_n);
     bad |= dalloc(&h->rank, h->max_n);
     bad |= dalloc(&h->start, h->max_cells + 1);
     bad |= dalloc(&h->tiles, tiles);

@@ -71,7 +71,6 @@ struct StepArgs {
     const Inst<real>* inst;
     const Blk* blk;
     int32_t nblk;
-    int32_t* key;             // global c-bin of every caller-order particle
     int32_t* rank;            // rank inside its c-bin
     int32_t* start;           // counts, then exclusive prefix (ncells + 1)
     real* rec;                // c-bin ordered records, 8 reals per particle

@@ -229,9 +229,27 @@ __device__ __forceinline__ double speed2(double vx, double vy, double vz) {
 }
 
 // ---------------------------------------------------------------- 1. key
-// c-bin of every caller-order particle and its rank inside the c-bin.  Lanes
-// of a wave holding the same c-bin in a run (the common case for sorted input)
-// take one atomic for the whole run.
+// c-bin key of caller-order particle p: its c-bin, or the instance's trailing
+// bin for a dead or non-finite particle.  The key and scatter kernels both
+// evaluate it on the same loaded values, so the key is never stored.
+template <typename real>
+__device__ __forceinline__ int cbin_key(const StepArgs<real>& a, const Inst<real>& I, int64_t p, real x, real y,
+                                        real z, real vx, real vy, real vz, bool alive, bool& fin) {
+    fin = finite3(x, y, z) && finite3(vx, vy, vz);
+    if (a.mass) {
+        const real m = a.mass[p];
+        fin = fin && m > real(0) && m < real(INFINITY);
+    }
+    if (!(alive && fin)) return (int)(I.cell_off + I.C);
+    const int cx = axis_bin(x, I.lo[0], I.inv_w[0], I.n[0]);
+    const int cy = axis_bin(y, I.lo[1], I.inv_w[1], I.n[1]);
+    const int cz = axis_bin(z, I.lo[2], I.inv_w[2], I.n[2]);
+    return (int)I.cell_off + cx + I.n[0] * row_of(I, cy, cz);
+}
+
+// c-bin count of every caller-order particle and its rank inside the c-bin.
+// Lanes of a wave holding the same c-bin in a run (the common case for sorted
+// input) take one atomic for the whole run.
 template <typename real>
 __global__ void __launch_bounds__(kBlock) k_key(StepArgs<real> a) {
     __shared__ double lds[16];
@@ -246,19 +264,11 @@ __global__ void __launch_bounds__(kBlock) k_key(StepArgs<real> a) {
         const bool alive = a.alive ? a.alive[p] != 0 : true;
         const real x = a.x[p], y = a.y[p], z = a.z[p];
         const real vx = a.vx[p], vy = a.vy[p], vz = a.vz[p];
-        bool fin = finite3(x, y, z) && finite3(vx, vy, vz);
-        if (a.mass) {
-            const real m = a.mass[p];
-            fin = fin && m > real(0) && m < real(INFINITY);
-        }
+        bool fin;
+        key = cbin_key(a, I, p, x, y, z, vx, vy, vz, alive, fin);
         if (alive && fin) {
-            const int cx = axis_bin(x, I.lo[0], I.inv_w[0], I.n[0]);
-            const int cy = axis_bin(y, I.lo[1], I.inv_w[1], I.n[1]);
-            const int cz = axis_bin(z, I.lo[2], I.inv_w[2], I.n[2]);
-            key = (int)I.cell_off + cx + I.n[0] * row_of(I, cy, cz);
             if (adaptive) v2 = speed2((double)vx, (double)vy, (double)vz);
         } else {
-            key = (int)(I.cell_off + I.C);
             nonfin = alive && !fin;
         }
     }
@@ -274,10 +284,7 @@ __global__ void __launch_bounds__(kBlock) k_key(StepArgs<real> a) {
     int base = 0;
     if (head) base = atomicAdd(&a.start[key], seg1 - seg0);
     base = __shfl(base, seg0 < 0 ? 0 : seg0);
-    if (in) {
-        a.key[p] = key;
-        a.rank[p] = base + (lane - seg0);
-    }
+    if (in) a.rank[p] = base + (lane - seg0);
     const double nn = block_sum((double)nonfin, lds);
     const double vm = adaptive ? block_max(v2, lds) : 0.0;
     if (threadIdx.x == 0) {
@@ -292,7 +299,9 @@ __global__ void __launch_bounds__(kBlock) k_key(StepArgs<real> a) {
 }
 
 // ---------------------------------------------------------------- 3. scatter
-// Caller-order particle -> its c-bin-ordered record.
+// Caller-order particle -> its c-bin-ordered record.  The permutation back to
+// the caller's order is kept only when the state is written back in that
+// order (without TPKMC_ALLOW_REORDER).
 template <typename real>
 __global__ void __launch_bounds__(kBlock) k_scatter(StepArgs<real> a) {
     const Blk bt = a.blk[blockIdx.x];
@@ -301,18 +310,19 @@ __global__ void __launch_bounds__(kBlock) k_scatter(StepArgs<real> a) {
     bool fast = false;
     if (p < I.off + I.cnt) {
         const int64_t base = I.off - a.start[I.cell_off];
-        const int k = a.key[p];
-        const int64_t dst = base + a.start[k] + a.rank[p];
-        const uint32_t fl = a.alive ? (a.alive[p] != 0) : 1u;
+        const bool alive = a.alive ? a.alive[p] != 0 : true;
         const real x = a.x[p], y = a.y[p], z = a.z[p], vx = a.vx[p], vy = a.vy[p], vz = a.vz[p];
+        bool fin;
+        const int k = cbin_key(a, I, p, x, y, z, vx, vy, vz, alive, fin);
+        const int64_t dst = base + a.start[k] + a.rank[p];
+        const uint32_t fl = alive ? 1u : 0u;
         Rec<real>::store(a.rec, dst, x, y, z, a.id[p], vx, vy, vz, fl);
-        a.src[dst] = (int32_t)p;
+        if (!(I.flags & TPKMC_ALLOW_REORDER)) a.src[dst] = (int32_t)p;
         if (a.bkey) a.bkey[dst] = ~0ull;
         if (a.mass) a.rmass[dst] = a.mass[p];
         // Diagnostic: a particle faster than one c-bin per step on some axis.
         const real dt = I.dt;
-        const bool mass_ok = !a.mass || (a.mass[p] > real(0) && a.mass[p] < real(INFINITY));
-        fast = fl && mass_ok && finite3(x, y, z) && finite3(vx, vy, vz) &&
+        fast = alive && fin &&
                (fabs(vx) * dt > I.w[0] || fabs(vy) * dt > I.w[1] || fabs(vz) * dt > I.w[2]);
     }
     const uint64_t fm = __ballot(fast);
