@@ -65,9 +65,10 @@ def phase_bytes(rs, n, ncell_tot, nobin, reorder):
     }
 
 
-def read_traffic(workload, precision):
+def read_traffic(workload, precision, shape):
     """HBM bytes per search launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source."""
+    summary, if it was taken on the current kernel source and in the launch
+    shape (records per lane, lanes per work-group) this run uses."""
     path = os.path.join(ROOT, "profiles", f"search_{workload}_{precision}_traffic.txt")
     if not os.path.exists(path):
         return None
@@ -79,6 +80,8 @@ def read_traffic(workload, precision):
     src = os.path.join(ROOT, "paper_1210_8084_amd", "csrc", "tpkmc_kernels.h")
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     if vals.get("kernel_source_sha256") != sha:
+        return None
+    if vals.get("search_shape") != f"{shape[0]},{shape[1]}":
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -227,6 +230,9 @@ def main():
     ap.add_argument("--precision", choices=("fp32", "fp64"), default="fp32")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay timing")
+    ap.add_argument("--search", default="auto",
+                    help="search launch shape 'G,B' (records per lane, lanes per work-group) instead of the "
+                         "autotuner's choice (profiling runs pin it: a profiler changes the tuning timings)")
     ap.add_argument("--batch-scale", type=float, default=1.0, help="batched64: scale every instance size")
     ap.add_argument("--fp64-steps", type=int, default=5, help="batched64: plain FP64 steps per instance")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -277,7 +283,10 @@ def main():
             raise T.TpkmcError(rc, "tpkmc_step")
 
     torch.cuda.synchronize()
-    eng.autotune(dst, [(0, w.n, g, p)], stream=stream)
+    if args.search == "auto":
+        eng.autotune(dst, [(0, w.n, g, p)], stream=stream)
+    else:
+        eng.set_search(*[int(v) for v in args.search.split(",")])
     for k in range(Wm):
         step(k, 0)
     torch.cuda.synchronize()
@@ -313,7 +322,9 @@ def main():
     search_s = search_ms / 1e3
     achieved = tests * FLOP_PER_TEST / search_s if search_s > 0 else 0.0
     peak = PEAK_FLOPS[args.precision]
-    traffic = read_traffic(args.workload, args.precision)
+    shape = eng.get_search()
+    shape = (shape[0], min(shape[1], 256 // shape[0]))
+    traffic = read_traffic(args.workload, args.precision, shape)
     bytes_per = phase_bytes(rs, w.n, ncell_tot, nob, True)
     phases = {}
     for ph, (ms, n) in prof.items():
@@ -352,6 +363,7 @@ def main():
                      "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
                      "algorithmic_bytes": bytes_per["search"],
+                     "search_shape": list(shape),
                      "avg_launch_ms": search_ms / max(search_n, 1),
                      "flop_per_pair_test": FLOP_PER_TEST},
         "phases": phases,

@@ -263,7 +263,8 @@ int tpkmc_autotune(tpkmc_handle* h, const tpkmc_particles* s,
 /* Launch shape of the partner search: one lane per `group` consecutive
  * c-bin-ordered records (1, 2 or 4) and `block` lanes per work-group (64,
  * 128 or 256, at most 256 / group).  Every shape gives the same pairs, state
- * and counters.  tpkmc_autotune picks one; tpkmc_set_search fixes one
+ * and counters.  The default is group 2, block 64; tpkmc_autotune keeps it
+ * unless another shape is at least 3% faster; tpkmc_set_search fixes one
  * (EINVAL outside these lists). */
 int tpkmc_set_search(tpkmc_handle* h, int32_t group, int32_t block);
 int tpkmc_get_search(tpkmc_handle* h, int32_t* group, int32_t* block);

@@ -261,7 +261,7 @@ struct tpkmc_handle {
     uint32_t* status = nullptr;
     hipStream_t last_stream = nullptr;
     hipStream_t own_stream = nullptr;
-    int search_block = kBlock;
+    int search_block = kWave;
     int search_group = 2;
     bool profiling = false;
     std::vector<ProfRec> prof;
@@ -632,22 +632,29 @@ int tune_impl(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* i
     hipEventCreate(&e0);
     hipEventCreate(&e1);
     // Results-neutral launch shapes: records per lane (1, 2, 4) and lanes per
-    // work-group (64, 128, 256).
+    // work-group (64, 128, 256).  The default shape (2 records per lane, 64
+    // lanes, the fastest on sparse bins) is timed first and is replaced only
+    // by a shape at least 3% faster, so that near-ties do not flip the choice
+    // from run to run.
     float best_ms = 1e30f;
-    int best_block = kBlock, best_group = 2;
-    for (int grp : {1, 2, 4}) {
-        for (int bs : {256, 128, 64}) {
-            if (bs > kBlock / grp) continue;
-            launch_search<real>(a, bs, grp, st);  // warm-up
-            hipEventRecord(e0, st);
-            for (int r = 0; r < 3; ++r) launch_search<real>(a, bs, grp, st);
-            hipEventRecord(e1, st);
-            if (hipEventSynchronize(e1) != hipSuccess) { rc = TPKMC_EHIP; break; }
-            float ms = 0.f;
-            hipEventElapsedTime(&ms, e0, e1);
-            if (ms < best_ms) { best_ms = ms; best_block = bs; best_group = grp; }
-        }
-        if (rc) break;
+    int best_block = kWave, best_group = 2;
+    std::vector<std::pair<int, int>> shapes = {{2, kWave}};
+    for (int grp : {1, 2, 4})
+        for (int bs : {256, 128, 64})
+            if (bs <= kBlock / grp && !(grp == 2 && bs == kWave)) shapes.push_back({grp, bs});
+    // Warm the caches and clocks first: the first shape timed would
+    // otherwise look slower than it is.
+    for (int r = 0; r < 4; ++r) launch_search<real>(a, kWave, 2, st);
+    for (const auto& sh : shapes) {
+        const int grp = sh.first, bs = sh.second;
+        launch_search<real>(a, bs, grp, st);  // warm-up
+        hipEventRecord(e0, st);
+        for (int r = 0; r < 3; ++r) launch_search<real>(a, bs, grp, st);
+        hipEventRecord(e1, st);
+        if (hipEventSynchronize(e1) != hipSuccess) { rc = TPKMC_EHIP; break; }
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        if (ms < 0.97f * best_ms) { best_ms = ms; best_block = bs; best_group = grp; }
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
