@@ -230,9 +230,11 @@ def main():
     ap.add_argument("--precision", choices=("fp32", "fp64"), default="fp32")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay timing")
-    ap.add_argument("--search", default="auto",
-                    help="search launch shape 'G,B' (records per lane, lanes per work-group) instead of the "
-                         "autotuner's choice (profiling runs pin it: a profiler changes the tuning timings)")
+    ap.add_argument("--search", default="2,64",
+                    help="search launch shape 'G,B' (records per lane, lanes per work-group), or 'auto' for the "
+                         "autotuner's choice.  The default is the library's default shape, the one the "
+                         "profiles in profiles/ were taken with; the autotuner's timings of the near-equal "
+                         "(2, 64) and (2, 128) shapes differ by a few per cent from run to run")
     ap.add_argument("--batch-scale", type=float, default=1.0, help="batched64: scale every instance size")
     ap.add_argument("--fp64-steps", type=int, default=5, help="batched64: plain FP64 steps per instance")
     ap.add_argument("--calibrate-copy", action="store_true",
