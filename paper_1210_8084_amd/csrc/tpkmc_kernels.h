@@ -248,7 +248,7 @@ __device__ __forceinline__ int cbin_key(const StepArgs<real>& a, const Inst<real
 }
 
 // The key kernel runs one wave per block-table entry, each lane taking
-// kBinRec particles kWave apart, so that every lane has all its loads, and
+// kKeyRec particles kWave apart, so that every lane has all its loads, and
 // then all its atomics, in flight at once.  With dense c-bins (long runs,
 // few atomics) the kernel is otherwise bound by the latency of those two
 // dependent steps: measured 1.07 -> 0.50 ms on the 4M-particle Sod tube and
@@ -256,7 +256,7 @@ __device__ __forceinline__ int cbin_key(const StepArgs<real>& a, const Inst<real
 // by the throughput of its one atomic per c-bin, is unchanged.  The same
 // layout made the scatter kernel slower on the Sedov blast (0.226 -> 0.247 ms),
 // so that one keeps a particle per lane.
-constexpr int kBinRec = kBlock / kWave;
+constexpr int kKeyRec = kBlock / kWave;
 
 // c-bin count of every caller-order particle and its rank inside the c-bin.
 // Lanes holding the same c-bin in a run (the common case for sorted input)
@@ -268,10 +268,10 @@ __global__ void __launch_bounds__(kWave) k_key(StepArgs<real> a) {
     const int lane = threadIdx.x;
     const int64_t end = I.off + I.cnt;
     const bool adaptive = (I.flags & TPKMC_ADAPTIVE_DT) != 0;
-    real x[kBinRec], y[kBinRec], z[kBinRec], vx[kBinRec], vy[kBinRec], vz[kBinRec];
-    bool alive[kBinRec];
+    real x[kKeyRec], y[kKeyRec], z[kKeyRec], vx[kKeyRec], vy[kKeyRec], vz[kKeyRec];
+    bool alive[kKeyRec];
 #pragma unroll
-    for (int r = 0; r < kBinRec; ++r) {
+    for (int r = 0; r < kKeyRec; ++r) {
         const int64_t p = (int64_t)bt.first + r * kWave + lane;
         x[r] = y[r] = z[r] = vx[r] = vy[r] = vz[r] = real(0);
         alive[r] = false;
@@ -281,10 +281,10 @@ __global__ void __launch_bounds__(kWave) k_key(StepArgs<real> a) {
             vx[r] = a.vx[p]; vy[r] = a.vy[p]; vz[r] = a.vz[p];
         }
     }
-    int key[kBinRec], base[kBinRec], seg0[kBinRec];
+    int key[kKeyRec], base[kKeyRec], seg0[kKeyRec];
     double nonfin = 0.0, v2 = 0.0;
 #pragma unroll
-    for (int r = 0; r < kBinRec; ++r) {
+    for (int r = 0; r < kKeyRec; ++r) {
         const int64_t p = (int64_t)bt.first + r * kWave + lane;
         const bool in = p < end;
         bool fin = true;
@@ -304,7 +304,7 @@ __global__ void __launch_bounds__(kWave) k_key(StepArgs<real> a) {
         base[r] = head ? atomicAdd(&a.start[key[r]], seg1 - seg0[r]) : 0;
     }
 #pragma unroll
-    for (int r = 0; r < kBinRec; ++r) {
+    for (int r = 0; r < kKeyRec; ++r) {
         const int64_t p = (int64_t)bt.first + r * kWave + lane;
         const int b = __shfl(base[r], seg0[r] < 0 ? 0 : seg0[r]);
         if (p < end) a.rank[p] = b + (lane - seg0[r]);
