@@ -8,10 +8,11 @@ density and pressure profiles against the analytic solutions, the FP32-FP64
 difference of those errors, and the conservation of particles, momentum and
 energy over the run.
 
-The analytic solutions and the CPU reference live in ``oracle/`` (test
-infrastructure); this script only reads them to score the GPU results.
+Test infrastructure, like ``oracle/``: it scores the GPU runs against the
+analytic solutions in ``oracle/analytic.py``; nothing in the library imports
+it.
 
-Usage:  python -m paper_1210_8084_amd.validate [--out file.json] [--quick]
+Usage:  python tests/validate.py [--out file.json] [--quick] [--only ...] [--seeds ...]
 """
 from __future__ import annotations
 
@@ -29,12 +30,13 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 
-def _run(w, precision, steps, progress=None):
+def _run(w, precision, steps, progress=None, rank_time=False):
     """Advance workload w by `steps` steps on the GPU; returns host state,
-    the last step's moments and per-step globals/counters."""
+    the last step's moments and per-step globals/counters.  rank_time:
+    criterion 3 by earliest contact instead of closest approach."""
     import torch
     from paper_1210_8084_amd import tpkmc as T
-    g, p = w.grid, w.params
+    g, p = w.grid, dict(w.params, rank_time=rank_time)
     eng = T.Engine(max_particles=w.n, max_cells=T.ncells(g) + 1, max_obins=T.nobins(g), precision=precision)
     dst = T.to_device(w.state, precision)
     out = T.make_outputs(1, T.nobins(g))
@@ -76,7 +78,19 @@ def _conservation(w, r):
                 collided_fraction=float(2 * r["counters"][:, 1].mean() / w.n))
 
 
-def sod(precision, n=4_000_000, steps=500, kn=1e-3, planar=False, seed=1):
+def _tanh_width(x, n, x_s, lo, hi):
+    """Width of a shock front: least-squares fit of
+    n(x) = lo + (hi - lo) (1 - tanh((x - c) / d)) / 2 near x_s; returns the
+    10-90% rise distance 2 atanh(0.8) d."""
+    from scipy.optimize import curve_fit
+
+    def model(x, c, d):
+        return lo + (hi - lo) * 0.5 * (1.0 - np.tanh((x - c) / d))
+    (c, d), _ = curve_fit(model, x, n, p0=(x_s, 0.005), maxfev=20000)
+    return float(2.0 * math.atanh(0.8) * abs(d)), float(c)
+
+
+def sod(precision, n=4_000_000, steps=500, kn=1e-3, planar=False, seed=1, rank_time=False):
     from oracle import analytic as A
     from paper_1210_8084_amd import workloads as W
     if planar:
@@ -84,7 +98,7 @@ def sod(precision, n=4_000_000, steps=500, kn=1e-3, planar=False, seed=1):
     else:
         w = W.sod(n=n, ncell=1000, nobin=200, dt=1.134e-4, kn=kn, seed=seed)
     f = 2 if planar else 3
-    r = _run(w, precision, steps, progress=100)
+    r = _run(w, precision, steps, progress=100, rank_time=rank_time)
     t = steps * w.params["dt"]
     M = r["moments"]
     nob = w.grid["nobin"][0]
@@ -100,7 +114,24 @@ def sod(precision, n=4_000_000, steps=500, kn=1e-3, planar=False, seed=1):
     nl, nr = w.info["n_left"], w.info["n_right"]
     tl, tr = w.info["t_left"], w.info["t_right"]
     rho, u, p = A.sod_profile(xc, t, (nl, 0.0, nl * tl), (nr, 0.0, nr * tr), gamma=w.info["gamma"])
+    # Shock front: the exact shock speed and post-shock density, and the
+    # 10-90% width of a tanh fit to a fine density profile (bins of half a
+    # mean free path) within 0.02 of the exact front.
+    g_ = w.info["gamma"]
+    left, right = (nl, 0.0, nl * tl), (nr, 0.0, nr * tr)
+    ps, _ = A.riemann_star(left, right, g_)
+    a_r = math.sqrt(g_ * nr * tr / nr)
+    x_s = 0.5 + t * a_r * math.sqrt((g_ + 1.0) / (2.0 * g_) * ps / (nr * tr) + (g_ - 1.0) / (2.0 * g_))
+    q = ps / (nr * tr)
+    n2 = nr * (q + (g_ - 1.0) / (g_ + 1.0)) / ((g_ - 1.0) / (g_ + 1.0) * q + 1.0)
+    lam = w.info.get("lam", kn)
+    fe = np.arange(x_s - 0.02, x_s + 0.02 + 1e-12, 0.5 * lam)
+    fc, _ = np.histogram(r["state"]["x"], bins=fe)
+    fn = fc / ((fe[1] - fe[0]) * (w.info["side"] if planar else 0.05 * 0.05))
+    width, x_fit = _tanh_width(0.5 * (fe[1:] + fe[:-1]), fn, x_s, nr, n2)
     return dict(workload=f"{w.name} n={n} kn={kn}", steps=steps, t=t, wall_s=r["wall"],
+                rank="contact time" if rank_time else "closest approach",
+                shock_x_exact=x_s, shock_x_fit=x_fit, shock_width=width, shock_width_mfp=width / lam,
                 l1_density=float(np.mean(np.abs(n_ - rho)) / nl),
                 l1_pressure_kinetic=float(np.mean(np.abs(p_kin - p)) / (nl * tl)),
                 l1_pressure_with_virial=float(np.mean(np.abs(p_tot - p)) / (nl * tl)),
@@ -173,11 +204,11 @@ def noh3d(precision, n=8_000_000, steps=160, seed=1):
                 **_conservation(w, r))
 
 
-def sedov(precision, n=16_000_000, steps=600, planar=False, seed=1):
+def sedov(precision, n=16_000_000, steps=600, planar=False, seed=1, rank_time=False):
     from oracle import analytic as A
     from paper_1210_8084_amd import workloads as W
     w = (W.sedov2d if planar else W.sedov)(n=n, steps=steps, seed=seed)
-    r = _run(w, precision, steps, progress=200)
+    r = _run(w, precision, steps, progress=200, rank_time=rank_time)
     t = steps * w.params["dt"]
     st = r["state"]
     j = 2 if planar else 3
@@ -192,7 +223,26 @@ def sedov(precision, n=16_000_000, steps=600, planar=False, seed=1):
     rc = 0.5 * (edges[1:] + edges[:-1])
     ra, _, _, R = A.sedov_profile(rc, t, energy=w.info["energy"], rho0=1.0, gamma=w.info["gamma"], j=j)
     peak = int(np.argmax(rho))
+    # Front width: 10-90% of the rise from rho0 to the peak on the outer flank
+    # of a fine radial profile (shells of a fifth of the coarse ones).
+    fe = np.arange(0.0, 0.5 + 1e-12, 0.002)
+    fc, _ = np.histogram(rad, bins=fe)
+    fv = math.pi * (fe[1:] ** 2 - fe[:-1] ** 2) if planar else 4.0 / 3.0 * math.pi * (fe[1:] ** 3 - fe[:-1] ** 3)
+    fr = fc * w.params["mass"] / fv
+    frc = 0.5 * (fe[1:] + fe[:-1])
+    k = int(np.argmax(fr))
+    top = fr[k]
+
+    def outer_cross(level):
+        for i in range(k, len(fr) - 1):
+            if fr[i] >= level > fr[i + 1]:
+                return frc[i] + (fr[i] - level) / (fr[i] - fr[i + 1]) * (frc[i + 1] - frc[i])
+        return float("nan")
+    width = float(outer_cross(1.0 + 0.1 * (top - 1.0)) - outer_cross(1.0 + 0.9 * (top - 1.0)))
+    lam = w.info.get("lam", 1e-3)
     return dict(workload=f"{w.name} n={n}", steps=steps, t=t, wall_s=r["wall"], r_shock_analytic=R,
+                rank="contact time" if rank_time else "closest approach",
+                front_width=width, front_width_mfp=width / lam,
                 r_density_peak=float(rc[peak]), peak_density=float(rho[peak]),
                 l1_density=float(np.mean(np.abs(rho - ra))),
                 profile_density=rho.round(3).tolist(), analytic_density=ra.round(3).tolist(),
@@ -219,10 +269,31 @@ def main():
     ap.add_argument("--only", default="sod,noh,sedov,sod2d,noh2d,sedov2d,noh3d")
     ap.add_argument("--seeds", default="1", help="comma-separated workload seeds; with several, the "
                     "report adds the mean and spread of L1 and of the FP32 - FP64 difference")
+    ap.add_argument("--rank-compare", action="store_true",
+                    help="criterion 3 by closest approach against by earliest contact (FP32): collided "
+                    "fraction, L1 density and shock width of the Sod tube and the Sedov blast")
     args = ap.parse_args()
     from paper_1210_8084_amd import tpkmc as T
     seeds = [int(v) for v in args.seeds.split(",")]
     report = {}
+    if args.rank_compare:
+        keys = ("rank", "collided_fraction", "l1_density", "shock_width_mfp", "front_width_mfp", "peak_density",
+                "energy_rel_drift")
+        for name in ("sod", "sedov"):
+            for rank_time in (False, True):
+                print(f"== {name} rank_time={rank_time}", flush=True)
+                if name == "sod":
+                    res = sod(T.FP32, n=400_000 if args.quick else 4_000_000, steps=100 if args.quick else 500,
+                              rank_time=rank_time)
+                else:
+                    res = sedov(T.FP32, n=2_000_000 if args.quick else 16_000_000, steps=150 if args.quick else 600,
+                                rank_time=rank_time)
+                report[f"{name}_{'time' if rank_time else 'distance'}"] = res
+                print(json.dumps({k: res[k] for k in keys if k in res}), flush=True)
+        if args.out:
+            with open(args.out, "w") as f:
+                json.dump(report, f, indent=1)
+        return
     for name in args.only.split(","):
         diffs, l1 = [], {"fp32": [], "fp64": []}
         for seed in seeds:
