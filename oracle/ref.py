@@ -30,6 +30,7 @@ M_MASS = 11      # moments slot: sum m
 ADAPTIVE_DT = 1  # ref_params.flags: step length from the rule of Sec. 3
 PLANAR = 2       # ref_params.flags: two-dimensional gas (x-y plane)
 RANK_TIME = 4    # ref_params.flags: criterion 3 by earliest contact time
+PAIR_RANDOM = 8  # ref_params.flags: random partners inside each c-bin (DSMC rule)
 
 
 def build() -> str:
@@ -116,7 +117,8 @@ def make_params(p) -> Params:
     P.step = int(p.get("step", 0))
     P.instance = int(p.get("instance", 0))
     P.flags = ((ADAPTIVE_DT if p.get("adaptive_dt") else 0) | (PLANAR if p.get("planar") else 0) |
-               (RANK_TIME if p.get("rank_time") else 0))
+               (RANK_TIME if p.get("rank_time") else 0) |
+               (PAIR_RANDOM if p.get("pair_random") else 0))
     return P
 
 

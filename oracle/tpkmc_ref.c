@@ -72,7 +72,7 @@ int ref_direction(uint64_t seed, uint64_t step, uint32_t instance,
                   uint32_t idA, uint32_t idB, double n[3])
 {
     uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
-    for (uint32_t attempt = 0; attempt < 256u; ++attempt) {
+    for (uint32_t attempt = 0; attempt < 255u; ++attempt) {
         uint32_t ctr[4] = { (uint32_t)step, idA, idB, (instance << 8) | attempt };
         uint32_t w[4];
         ref_philox4x32_10(ctr, key, w);
@@ -90,14 +90,14 @@ int ref_direction(uint64_t seed, uint64_t step, uint32_t instance,
         }
     }
     n[0] = 0.0; n[1] = 0.0; n[2] = 1.0;
-    return 256;
+    return 255;
 }
 
 int ref_direction_planar(uint64_t seed, uint64_t step, uint32_t instance,
                          uint32_t idA, uint32_t idB, double n[3])
 {
     uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
-    for (uint32_t attempt = 0; attempt < 256u; ++attempt) {
+    for (uint32_t attempt = 0; attempt < 255u; ++attempt) {
         uint32_t ctr[4] = { (uint32_t)step, idA, idB, (instance << 8) | attempt };
         uint32_t w[4];
         ref_philox4x32_10(ctr, key, w);
@@ -114,7 +114,7 @@ int ref_direction_planar(uint64_t seed, uint64_t step, uint32_t instance,
         }
     }
     n[0] = 1.0; n[1] = 0.0; n[2] = 0.0;
-    return 256;
+    return 255;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -123,7 +123,9 @@ int ref_direction_planar(uint64_t seed, uint64_t step, uint32_t instance,
 typedef struct {
     double L[3], w[3], inv_w[3], halfL[3], inv_wo[3];
     double D2;
+    double cellvol;         /* c-bin volume (area in the plane) */
     int rank_time;          /* criterion 3 ranks by the contact time t_o1 */
+    int pair_random;        /* random partners inside each c-bin */
     int32_t n[3], bc[3], no[3];
     int64_t C, B;
 } derived;
@@ -148,6 +150,9 @@ static int derive(const ref_grid* g, const ref_params* p, derived* G)
         G->B *= g->nobin[a];
     }
     G->rank_time = p && (p->flags & REF_RANK_TIME) != 0;
+    G->pair_random = p && (p->flags & REF_PAIR_RANDOM) != 0;
+    if (G->rank_time && G->pair_random) return -1;
+    G->cellvol = (G->w[0] * G->w[1]) * G->w[2];
     if (p) {
         if (!(p->sigma >= 0.0) || !(p->dt > 0.0) || !(p->mass > 0.0)) return -1;
         if (p->instance >= (1u << 24)) return -1;
@@ -158,6 +163,7 @@ static int derive(const ref_grid* g, const ref_params* p, derived* G)
             if (g->ncell[2] != 1) return -1;
             double D = 0.5 * p->sigma;
             G->D2 = D * D;
+            G->cellvol = G->w[0] * G->w[1];
         } else {
             G->D2 = p->sigma / M_PI;
         }
@@ -513,6 +519,7 @@ int ref_best(const ref_grid* g, const ref_params* p, int64_t n,
 {
     derived G;
     if (derive(g, p, &G)) return -1;
+    if (G.pair_random) return -1;
     if (check_common(&G, g, p, n, x, y, z, vx, vy, vz, id)) return -1;
     if (mode < 0 || mode > 2 || (n > 0 && (!best || !best_d2))) return -1;
     view V = { n, x, y, z, vx, vy, vz, id, alive, NULL };
@@ -533,6 +540,7 @@ int ref_best_sample(const ref_grid* g, const ref_params* p, int64_t n,
 {
     derived G;
     if (derive(g, p, &G)) return -1;
+    if (G.pair_random) return -1;
     if (check_common(&G, g, p, n, x, y, z, vx, vy, vz, id)) return -1;
     if (ns < 0 || (ns > 0 && (!sample || !best || !best_d2))) return -1;
     for (int64_t k = 0; k < ns; ++k)
@@ -577,6 +585,76 @@ uint64_t ref_count_tests(const ref_grid* g, int64_t n,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Random partners inside a c-bin (REF_PAIR_RANDOM, the usual DSMC rule that */
+/* Sec. 2.3 describes).                                                      */
+/* ------------------------------------------------------------------------ */
+static void philox_words(const ref_params* p, uint32_t c1, uint32_t c2, uint32_t w[4])
+{
+    uint32_t key[2] = { (uint32_t)p->seed, (uint32_t)(p->seed >> 32) };
+    uint32_t ctr[4] = { (uint32_t)p->step, c1, c2, (p->instance << 8) | 255u };
+    ref_philox4x32_10(ctr, key, w);
+}
+
+typedef struct { uint32_t key, id; int64_t idx; } keyed;
+
+static int by_key_then_id(const void* a, const void* b)
+{
+    const keyed* x = (const keyed*)a;
+    const keyed* y = (const keyed*)b;
+    if (x->key != y->key) return x->key < y->key ? -1 : 1;
+    if (x->id != y->id) return x->id < y->id ? -1 : 1;
+    return 0;
+}
+
+/* best[i] = the random partner of i (or -1); returns the pairs formed. */
+static int64_t random_pairs(const derived* G, const ref_params* p, const view* V, const bins* Bn,
+                            int64_t* best)
+{
+    int64_t formed = 0, most = 0;
+    for (int64_t i = 0; i < V->n; ++i) best[i] = -1;
+    for (int64_t c = 0; c < G->C; ++c)
+        if (Bn->first[c + 1] - Bn->first[c] > most) most = Bn->first[c + 1] - Bn->first[c];
+    keyed* t = (keyed*)malloc(sizeof(keyed) * (size_t)(most > 0 ? most : 1));
+    if (!t) return -1;
+    for (int64_t c = 0; c < G->C; ++c) {
+        const int64_t m = Bn->first[c + 1] - Bn->first[c];
+        for (int64_t k = 0; k < m; ++k) {
+            const int64_t i = Bn->member[Bn->first[c] + k];
+            uint32_t w[4];
+            philox_words(p, V->id[i], V->id[i], w);
+            t[k].key = w[0];
+            t[k].id = V->id[i];
+            t[k].idx = i;
+        }
+        qsort(t, (size_t)m, sizeof(keyed), by_key_then_id);
+        for (int64_t k = 0; k + 1 < m; k += 2) {
+            best[t[k].idx] = t[k + 1].idx;
+            best[t[k + 1].idx] = t[k].idx;
+            formed++;
+        }
+    }
+    free(t);
+    return formed;
+}
+
+/* Whether the random pair {i, j} of a c-bin with nc particles collides. */
+static int random_pair_collides(const derived* G, const ref_params* p, const view* V, int64_t i, int64_t j,
+                                int64_t nc)
+{
+    const int64_t A = V->id[i] < V->id[j] ? i : j, B = A == i ? j : i;
+    double rA[3], vA[3], rB[3], vB[3], r[3], u[3];
+    load(V, A, rA, vA);
+    load(V, B, rB, vB);
+    rel(G, rA, vA, rB, vB, r, u);
+    double vv = (u[0] * u[0] + u[1] * u[1]) + u[2] * u[2];
+    double g = sqrt(vv);
+    double prob = ((((double)(nc - 1) * p->sigma) * g) * p->dt) / G->cellvol;
+    uint32_t w[4];
+    philox_words(p, V->id[A], V->id[B], w);
+    return unit_double(w[0], w[1]) < prob;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Scattering and position update                                            */
 /* ------------------------------------------------------------------------ */
 /* Scattering of the accepted pair {i, j} (Sec. 3): A is the lower id, B the
@@ -587,6 +665,8 @@ static void scatter_pair(const derived* G, const ref_params* p, const view* V, i
                          double vi_new[3], double vj_new[3], double* tp_out,
                          double vir_i[3], double vir_j[3])
 {
+    /* Random partners have no point of closest approach: t_poca = 0, the
+     * collision happens at the start of the step. */
     const int i_is_A = V->id[i] < V->id[j];
     const int64_t A = i_is_A ? i : j, B = i_is_A ? j : i;
     double rA[3], vA[3], rB[3], vB[3], r[3], u[3], nhat[3], nA[3], nB[3];
@@ -595,7 +675,7 @@ static void scatter_pair(const derived* G, const ref_params* p, const view* V, i
     rel(G, rA, vA, rB, vB, r, u);
     double s0 = (r[0] * u[0] + r[1] * u[1]) + r[2] * u[2];
     double vv = (u[0] * u[0] + u[1] * u[1]) + u[2] * u[2];
-    double tp = -s0 / vv;
+    double tp = G->pair_random ? 0.0 : -s0 / vv;
     if (p->flags & REF_PLANAR)
         ref_direction_planar(p->seed, p->step, p->instance, V->id[A], V->id[B], nhat);
     else
@@ -677,6 +757,7 @@ int ref_step_sample(const ref_grid* g, const ref_params* p, int64_t n,
 {
     derived G;
     if (derive(g, p, &G)) return -1;
+    if (G.pair_random) return -1;
     if (check_common(&G, g, p, n, x, y, z, vx, vy, vz, id)) return -1;
     if (ns < 0 || (ns > 0 && (!sample || !out_state || !out_partner || !out_alive))) return -1;
     for (int64_t k = 0; k < ns; ++k)
@@ -775,6 +856,25 @@ int ref_step(const ref_grid* g, const ref_params* p, int64_t n,
 
     /* 1. Sort into c-bins. */
     if (make_bins(&G, g, &V, &Bn)) { rc = -2; goto done; }
+    if (G.pair_random) {
+        /* 2'-3'. Random partners inside each c-bin, each pair its own
+         * acceptance draw (REF_PAIR_RANDOM). */
+        int64_t formed = random_pairs(&G, p, &V, &Bn, best);
+        if (formed < 0) { rc = -2; goto done; }
+        cnt[REF_CNT_TESTS] = (uint64_t)formed;
+        cnt[REF_CNT_CAND] = cnt[REF_CNT_HAVE_BEST] = 2 * (uint64_t)formed;
+        for (int64_t i = 0; i < n; ++i) partner[i] = -1;
+        for (int64_t i = 0; i < n; ++i) {
+            int64_t j = best[i];
+            if (j < 0 || !(id[i] < id[j])) continue;
+            int64_t c = Bn.cell[i];
+            if (random_pair_collides(&G, p, &V, i, j, Bn.first[c + 1] - Bn.first[c])) {
+                partner[i] = j;
+                partner[j] = i;
+            }
+        }
+        goto scatter;
+    }
     for (int64_t c = 0; c < G.C; ++c) {
         uint64_t nc = (uint64_t)(Bn.first[c + 1] - Bn.first[c]);
         cnt[REF_CNT_TESTS] += nc * (nc - (nc > 0 ? 1 : 0)) / 2;
@@ -796,6 +896,7 @@ int ref_step(const ref_grid* g, const ref_params* p, int64_t n,
     }
 
     /* 4. Scattering of every accepted pair, visited once from its lower id. */
+scatter:;
     int64_t npairs = 0;
     for (int64_t i = 0; i < n; ++i) {
         int64_t j = partner[i];

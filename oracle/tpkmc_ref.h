@@ -48,7 +48,7 @@ typedef struct {
     uint64_t seed;          /* Philox key                                     */
     uint64_t step;          /* step number (low 32 bits enter the counter)    */
     uint32_t instance;      /* instance number (< 2^24)                       */
-    uint32_t flags;         /* REF_ADAPTIVE_DT | REF_PLANAR | REF_RANK_TIME   */
+    uint32_t flags;         /* REF_ADAPTIVE_DT | REF_PLANAR | REF_RANK_TIME | REF_PAIR_RANDOM */
 } ref_params;
 
 /* ref_params.flags.  REF_ADAPTIVE_DT: the step length follows the rule of
@@ -76,6 +76,31 @@ enum { REF_PLANAR = 2 };
  * names both choices and uses the distance.  Ties go to the lower id, and
  * best_d2 outputs stay the d_min^2 of the chosen partner. */
 enum { REF_RANK_TIME = 4 };
+
+/* ref_params.flags.  REF_PAIR_RANDOM: random partners inside each c-bin,
+ * the usual DSMC rule that Sec. 2.3 sets against the point of closest
+ * approach, in place of criteria 1-3 (the criteria select no pair in this
+ * mode):
+ *  - every usable particle of a c-bin gets the key w0 of Philox4x32-10 with
+ *    counter (step, id, id, instance * 2^8 + 255) and the seed as key; the
+ *    c-bin's particles are ordered by (key, id), and positions (0, 1),
+ *    (2, 3), ... form pairs (an odd last particle has none);
+ *  - a pair {A, B} (A the lower id) of a c-bin holding n_c particles
+ *    collides when u < (((n_c - 1) sigma) g) dt / V_c, with g = |v_A - v_B|,
+ *    V_c the c-bin volume (w_x w_y w_z; w_x w_y in the plane, where sigma is
+ *    a length) and u the 53-bit uniform of the words w0, w1 of Philox with
+ *    counter (step, id_A, id_B, instance * 2^8 + 255).  Each particle of the
+ *    c-bin then collides with probability n sigma g dt on average, the
+ *    kinetic-theory rate;
+ *  - a colliding pair scatters as in Sec. 3 and then moves with the new
+ *    velocity for the whole step (no point of closest approach); its virial
+ *    term takes the separation at the start of the step.
+ * Counters: TESTS = pairs formed, CAND = HAVE_BEST = particles in a formed
+ * pair, PAIRS = colliding pairs.  Not combinable with REF_RANK_TIME; the
+ * searches (ref_best, ref_best_sample) and ref_step_sample reject it.  In
+ * every mode the scattering direction draws at most 255 times, so that the
+ * counter ending in 255 belongs to the key and acceptance draws alone. */
+enum { REF_PAIR_RANDOM = 8 };
 
 /* Counters written by ref_step (uint64[8]). */
 enum {

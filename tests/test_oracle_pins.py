@@ -216,7 +216,7 @@ def test_directions_are_unit_and_isotropic(oracle):
     ns = []
     for k in range(20000):
         n, used = oracle.direction(99, 3, 1, k, k + 1)
-        assert 1 <= used <= 256
+        assert 1 <= used <= 255
         assert abs(float(n @ n) - 1.0) <= 8e-16
         ns.append(n)
     ns = np.array(ns)
