@@ -98,11 +98,37 @@ enum {
                                   width 2 D of the strip one disk sweeps
                                   relative to another (D^2 = sigma^2 / 4),
                                   and directions are isotropic in the plane */
-    TPKMC_RANK_TIME = 16u      /* criterion 3 by time: among the candidates,
+    TPKMC_RANK_TIME = 16u,     /* criterion 3 by time: among the candidates,
                                   the one whose effective radii touch first
                                   (the earlier overlap time t_o1 of Sec. 2.4)
                                   instead of the smallest d_min; the paper
                                   names both choices and uses the distance */
+    TPKMC_PAIR_RANDOM = 32u    /* random partners inside each c-bin, the usual
+                                  DSMC rule that Sec. 2.3 sets against the
+                                  point of closest approach, in place of
+                                  criteria 1-3.  The c-bin's particles are
+                                  ordered by (key, id), key = word 0 of
+                                  Philox4x32-10 (counter (step, id, id,
+                                  instance * 2^8 + 255), key = seed), and
+                                  positions (0, 1), (2, 3), ... pair up.  A
+                                  pair {A, B} (A the lower id) of a c-bin of
+                                  n_c particles collides when
+                                  u < (((n_c - 1) sigma) g) dt / V_c, in
+                                  double: g = |v_A - v_B|, V_c the c-bin
+                                  volume (area in the plane), u the 53-bit
+                                  uniform of words 0 and 1 of Philox with
+                                  counter (step, id_A, id_B,
+                                  instance * 2^8 + 255).  Colliders scatter
+                                  at the start of the step (no point of
+                                  closest approach; the virial takes the
+                                  separation then) and move with the new
+                                  velocity.  Counters: tests = pairs formed,
+                                  cand = have_best = particles in a formed
+                                  pair, pairs = colliding pairs.  Not with
+                                  TPKMC_RANK_TIME.  In every mode the
+                                  scattering direction draws at most 255
+                                  times, so the counters ending in 255 are
+                                  these draws' alone. */
 };
 
 /* Bits of the device status word (sticky until read). */
@@ -227,7 +253,7 @@ int tpkmc_version(void);
 const char* tpkmc_strerror(int code);
 
 /* Allocates a handle and all its device scratch on cfg->device (memory is
- * sized from the capacities: about 56 B per particle in FP32, 84 B in FP64,
+ * sized from the capacities: about 60 B per particle in FP32, 88 B in FP64,
  * 8 B per c-bin, 24 B per o-bin).  *out is NULL on failure. */
 int tpkmc_create(const tpkmc_config* cfg, tpkmc_handle** out);
 

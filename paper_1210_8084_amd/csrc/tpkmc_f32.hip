@@ -9,4 +9,5 @@ template void launch_scatter<float>(const StepArgs<float>&, hipStream_t);
 template void launch_adapt_dt<float>(Inst<float>*, const double*, int, hipStream_t);
 template void launch_search<float>(const StepArgs<float>&, int, int, hipStream_t);
 template void launch_move<float>(const StepArgs<float>&, hipStream_t);
+template void launch_random_pairs<float>(const StepArgs<float>&, hipStream_t);
 }  // namespace tpkmc

@@ -11,4 +11,5 @@ template void launch_scatter<double>(const StepArgs<double>&, hipStream_t);
 template void launch_adapt_dt<double>(Inst<double>*, const double*, int, hipStream_t);
 template void launch_search<double>(const StepArgs<double>&, int, int, hipStream_t);
 template void launch_move<double>(const StepArgs<double>&, hipStream_t);
+template void launch_random_pairs<double>(const StepArgs<double>&, hipStream_t);
 }  // namespace tpkmc

@@ -246,7 +246,7 @@ struct tpkmc_handle {
     int device = 0, precision = TPKMC_FP64;
     int64_t max_n = 0, max_cells = 0, max_obins = 0, max_blk = 0;
     int32_t max_inst = 0;
-    int32_t *rank = nullptr, *start = nullptr, *tiles = nullptr, *src = nullptr, *best = nullptr;
+    int32_t *perm = nullptr, *rank = nullptr, *start = nullptr, *tiles = nullptr, *src = nullptr, *best = nullptr;
     void* rec = nullptr;
     void* rmass = nullptr;
     void* inst = nullptr;
@@ -291,6 +291,8 @@ struct Plan {
     int64_t ncell_tot = 0, nob_tot = 0, max_nob = 0;
     int nblk = 0;
     bool adaptive = false;    // some instance takes the adaptive time step
+    bool any_search = false;  // some instance takes partners by closest approach
+    bool any_random = false;  // some instance takes random partners
     std::vector<Blk> blk;
     std::vector<Chunk> chunks;
     std::vector<char> inst_bytes;
@@ -313,6 +315,8 @@ int make_plan(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* i
     P.chunks.clear();
     P.n_inst = n_inst;
     P.adaptive = false;
+    P.any_search = false;
+    P.any_random = false;
     P.ncell_tot = 0;
     P.nob_tot = 0;
     P.max_nob = 0;
@@ -327,14 +331,17 @@ int make_plan(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* i
         if (!(std::isfinite(p.dt) && p.dt > 0.0)) return TPKMC_EINVAL;
         if (p.instance >= (1u << 24)) return TPKMC_EINVAL;
         if (p.flags & ~(uint32_t)(TPKMC_EMIT_PAIRS | TPKMC_ALLOW_REORDER | TPKMC_ADAPTIVE_DT | TPKMC_PLANAR |
-                                  TPKMC_RANK_TIME))
+                                  TPKMC_RANK_TIME | TPKMC_PAIR_RANDOM))
             return TPKMC_EINVAL;
+        if ((p.flags & TPKMC_RANK_TIME) && (p.flags & TPKMC_PAIR_RANDOM)) return TPKMC_EINVAL;
+        if (p.flags & TPKMC_PAIR_RANDOM) P.any_random = true;
+        else P.any_search = true;
         const bool planar = (p.flags & TPKMC_PLANAR) != 0;
         if (planar && g.ncell[2] != 1) return TPKMC_EINVAL;
         Inst<real>& d = I[k];
         std::memset(&d, 0, sizeof(d));
         int64_t C = 1, B = 1;
-        double dx = 0.0;
+        double dx = 0.0, wd[3];
         for (int a = 0; a < 3; ++a) {
             if (g.ncell[a] < 1 || g.nobin[a] < 1) return TPKMC_EINVAL;
             if (g.ncell[a] > (1 << 24) || g.nobin[a] > (1 << 24)) return TPKMC_EINVAL;
@@ -353,6 +360,7 @@ int make_plan(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* i
             d.L[a] = (real)L;
             d.halfL[a] = (real)(0.5 * L);
             d.w[a] = (real)(L / (double)g.ncell[a]);
+            wd[a] = L / (double)g.ncell[a];
             if (g.ncell[a] > 1 && (dx == 0.0 || L / (double)g.ncell[a] < dx)) dx = L / (double)g.ncell[a];
             d.inv_w[a] = (real)((double)g.ncell[a] / L);
             d.inv_wo[a] = (real)((double)g.nobin[a] / L);
@@ -381,6 +389,10 @@ int make_plan(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* i
         d.dt_d = p.dt;
         d.dt_cap = p.dt;
         d.dx_d = dx;
+        // Random partners: the cross section and the c-bin volume (an area
+        // in the plane), in the reference's order.
+        d.sigma_d = p.sigma;
+        d.cellvol_d = planar ? wd[0] * wd[1] : (wd[0] * wd[1]) * wd[2];
         // Band height of the c-bin order: the largest power of two of rows
         // whose band plane (rows x n_x c-bins of records) stays within
         // kBandBytes, so that one XCD's L2 holds the plane its neighbourhood
@@ -464,6 +476,7 @@ StepArgs<real> make_args(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_
     a.rmass = (real*)h->rmass;
     a.src = h->src;
     a.best = h->best;
+    a.perm = h->perm;
     a.bkey = h->bkey;
     a.gpart = h->gpart;
     a.shift = h->shift;
@@ -509,7 +522,8 @@ void enqueue_step(tpkmc_handle* h, const StepArgs<real>& a, const tpkmc_outputs*
         }
         {
             PhaseScope ps(h, PH_SEARCH, s, prof);
-            launch_search<real>(a, h->search_block, h->search_group, s);
+            if (P.any_search) launch_search<real>(a, h->search_block, h->search_group, s);
+            if (P.any_random) launch_random_pairs<real>(a, s);
         }
         {
             PhaseScope ps(h, PH_MOVE, s, prof);
@@ -678,7 +692,7 @@ void free_all(tpkmc_handle* h) {
         if (h->stage_ev[k]) hipEventDestroy(h->stage_ev[k]);
     }
     hipFree(h->rank); hipFree(h->start); hipFree(h->tiles);
-    hipFree(h->src); hipFree(h->best); hipFree(h->rec); hipFree(h->rmass); hipFree(h->inst);
+    hipFree(h->src); hipFree(h->best); hipFree(h->perm); hipFree(h->rec); hipFree(h->rmass); hipFree(h->inst);
     hipFree(h->blk); hipFree(h->chunks); hipFree(h->bkey); hipFree(h->cpart); hipFree(h->gpart); hipFree(h->shift); hipFree(h->pair_count); hipFree(h->status);
 }
 
@@ -733,6 +747,7 @@ int tpkmc_create(const tpkmc_config* cfg, tpkmc_handle** out) {
     bad |= dalloc(&h->tiles, tiles);
     bad |= dalloc(&h->src, h->max_n);
     bad |= dalloc(&h->best, h->max_n);
+    bad |= dalloc(&h->perm, h->max_n);
     bad |= hipMalloc(&h->rec, rs * 8 * (size_t)std::max<int64_t>(h->max_n, 1)) != hipSuccess;
     bad |= hipMalloc(&h->rmass, rs * (size_t)std::max<int64_t>(h->max_n, 1)) != hipSuccess;
     bad |= hipMalloc(&h->inst, inst_sz * (size_t)h->max_inst) != hipSuccess;

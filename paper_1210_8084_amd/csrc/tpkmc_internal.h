@@ -40,6 +40,7 @@ struct Inst {
     real dt, D2, mass;
     double mass_d, dt_d;      // dt_d: this step's time step (set on the device with ADAPTIVE_DT)
     double dt_cap, dx_d;      // caller's dt; smallest c-bin width over axes with > 1 c-bin (0: none)
+    double sigma_d, cellvol_d; // cross section; c-bin volume (area in the plane), for random partners
 };
 
 // Bit of Inst::flags, set by the host (outside the public flag bits): the
@@ -78,6 +79,7 @@ struct StepArgs {
     real* rmass;              // masses in record order (with mass only)
     int32_t* src;             // record -> caller index
     int32_t* best;            // record -> partner record or -1 (FP64 search)
+    int32_t* perm;            // random partners: c-bin-local order -> record
     unsigned long long* bkey; // record -> (d_min^2 bits, partner record) (FP32 search)
     double* gpart;            // [nblk][kGPart]
     double* shift;            // per-o-bin velocity shift (3 per o-bin)
@@ -94,5 +96,6 @@ template <typename real> void launch_scatter(const StepArgs<real>& a, hipStream_
 template <typename real> void launch_adapt_dt(Inst<real>* inst, const double* gpart, int n_inst, hipStream_t s);
 template <typename real> void launch_search(const StepArgs<real>& a, int block, int group, hipStream_t s);
 template <typename real> void launch_move(const StepArgs<real>& a, hipStream_t s);
+template <typename real> void launch_random_pairs(const StepArgs<real>& a, hipStream_t s);
 
 }  // namespace tpkmc

@@ -190,12 +190,13 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32
 
 // Isotropic unit vector of the pair (idA < idB) from a point (x1, x2) drawn
 // uniformly in the unit disk by rejection, two 53-bit uniforms per Philox
-// draw; computed in double in both precisions.  In space: Marsaglia's map
+// draw (at most 255 draws: the counter ending in 255 is kept for the random
+// partners' draws); computed in double in both precisions.  In space: Marsaglia's map
 // (2 x1 q, 2 x2 q, 1 - 2 s), q = sqrt(1 - s).  In the plane: the doubled
 // angle ((x1^2 - x2^2) / s, 2 x1 x2 / s, 0), which needs s > 0.
 __device__ __forceinline__ void pair_direction(uint32_t k0, uint32_t k1, uint32_t step, uint32_t instance,
                                                uint32_t idA, uint32_t idB, bool planar, double n[3]) {
-    for (uint32_t attempt = 0; attempt < 256u; ++attempt) {
+    for (uint32_t attempt = 0; attempt < 255u; ++attempt) {
         uint32_t c[4] = {step, idA, idB, (instance << 8) | attempt};
         philox4x32_10(c, k0, k1);
         const double u1 = ((double)(c[0] >> 5) * 67108864.0 + (double)(c[1] >> 6)) * (1.0 / 9007199254740992.0);
@@ -790,6 +791,7 @@ k_search(StepArgs<real> a) {
     const int entry = lb / sub;
     const Blk bt = a.blk[entry];
     const Inst<real>& I = a.inst[bt.inst];
+    if (I.flags & TPKMC_PAIR_RANDOM) return;  // partners from k_rp_* instead
     const int64_t i0 = (int64_t)bt.first + ((int64_t)(lb % sub) * blockDim.x + threadIdx.x) * G;
     const int64_t base = I.off - a.start[I.cell_off];
     const int64_t live_end = base + a.start[I.cell_off + I.C];
@@ -850,6 +852,138 @@ k_search(StepArgs<real> a) {
             unsafeAtomicAdd(gp + GP_CAND, c);
         }
     }
+}
+
+// ---------------------------------------------------------------- 4b. random partners
+// Random partners inside each c-bin (TPKMC_PAIR_RANDOM, the usual DSMC rule
+// of Sec. 2.3) in place of the search: every live record gets a Philox key,
+// the records of a c-bin are ranked by (key, id), and ranks (0, 1), (2, 3),
+// ... pair up.  Three passes (launch boundaries order them): the keys; the
+// rank of every record among its c-bin's (a loop over the c-bin, O(n_c^2)
+// per c-bin like the neighbourhood search) with the c-bin-local order in
+// perm; the partners.  The rank goes through `best` (free until the last
+// pass writes the FP64 partner there) and the keys through `rank` (free
+// after the scatter).
+
+__device__ __forceinline__ uint32_t random_key(const uint32_t k0, const uint32_t k1, uint32_t step,
+                                               uint32_t instance, uint32_t id) {
+    uint32_t c[4] = {step, id, id, (instance << 8) | 255u};
+    philox4x32_10(c, k0, k1);
+    return c[0];
+}
+
+template <typename real> __device__ __forceinline__ uint32_t record_id(const real* rec, int64_t i);
+template <> __device__ __forceinline__ uint32_t record_id<float>(const float* rec, int64_t i) {
+    return reinterpret_cast<const uint32_t*>(rec)[8 * i + 3];
+}
+template <> __device__ __forceinline__ uint32_t record_id<double>(const double* rec, int64_t i) {
+    return (uint32_t)reinterpret_cast<const unsigned long long*>(rec)[8 * i + 3];
+}
+
+// Global c-bin of a record, from its position (the key kernel's arithmetic).
+template <typename real>
+__device__ __forceinline__ int64_t record_cbin(const Inst<real>& I, real x, real y, real z) {
+    const int cx = axis_bin(x, I.lo[0], I.inv_w[0], I.n[0]);
+    const int cy = axis_bin(y, I.lo[1], I.inv_w[1], I.n[1]);
+    const int cz = axis_bin(z, I.lo[2], I.inv_w[2], I.n[2]);
+    return I.cell_off + cx + (int64_t)I.n[0] * row_of(I, cy, cz);
+}
+
+template <typename real>
+__global__ void __launch_bounds__(kBlock) k_rp_key(StepArgs<real> a) {
+    const Blk bt = a.blk[blockIdx.x];
+    const Inst<real>& I = a.inst[bt.inst];
+    if (!(I.flags & TPKMC_PAIR_RANDOM)) return;
+    const int64_t base = I.off - a.start[I.cell_off];
+    const int64_t live_end = base + a.start[I.cell_off + I.C];
+    const int64_t i = (int64_t)bt.first + threadIdx.x;
+    if (i < live_end && i < I.off + I.cnt)
+        reinterpret_cast<uint32_t*>(a.rank)[i] =
+            random_key(I.seed_lo, I.seed_hi, I.step_lo, I.instance, record_id<real>(a.rec, i));
+}
+
+template <typename real>
+__global__ void __launch_bounds__(kBlock) k_rp_rank(StepArgs<real> a) {
+    const Blk bt = a.blk[blockIdx.x];
+    const Inst<real>& I = a.inst[bt.inst];
+    if (!(I.flags & TPKMC_PAIR_RANDOM)) return;
+    const int64_t base = I.off - a.start[I.cell_off];
+    const int64_t live_end = base + a.start[I.cell_off + I.C];
+    const int64_t i = (int64_t)bt.first + threadIdx.x;
+    if (!(i < live_end && i < I.off + I.cnt)) return;
+    real x, y, z, vx, vy, vz;
+    uint32_t id, fl;
+    Rec<real>::load(a.rec, i, x, y, z, id, vx, vy, vz, fl);
+    const int64_t k = record_cbin(I, x, y, z);
+    const int64_t lo = base + a.start[k], hi = base + a.start[k + 1];
+    const uint32_t* key = reinterpret_cast<const uint32_t*>(a.rank);
+    const uint32_t mine = key[i];
+    int32_t r = 0;
+    for (int64_t j = lo; j < hi; ++j) {
+        const uint32_t kj = key[j];
+        r += (kj < mine || (kj == mine && record_id<real>(a.rec, j) < id)) ? 1 : 0;
+    }
+    a.perm[lo + r] = (int32_t)i;
+    a.best[i] = r;
+}
+
+template <typename real>
+__global__ void __launch_bounds__(kBlock) k_rp_partner(StepArgs<real> a) {
+    __shared__ double lds[16];
+    const Blk bt = a.blk[blockIdx.x];
+    const Inst<real>& I = a.inst[bt.inst];
+    if (!(I.flags & TPKMC_PAIR_RANDOM)) return;
+    const int64_t base = I.off - a.start[I.cell_off];
+    const int64_t live_end = base + a.start[I.cell_off + I.C];
+    const int64_t i = (int64_t)bt.first + threadIdx.x;
+    double formed = 0.0, paired = 0.0;
+    if (i < I.off + I.cnt) {
+        int32_t partner = -1;
+        if (i < live_end) {
+            real x, y, z, vx, vy, vz;
+            uint32_t id, fl;
+            Rec<real>::load(a.rec, i, x, y, z, id, vx, vy, vz, fl);
+            const int64_t k = record_cbin(I, x, y, z);
+            const int64_t lo = base + a.start[k], nc = base + a.start[k + 1] - lo;
+            const int32_t r = a.best[i], q = r ^ 1;
+            if (q < nc) {
+                partner = a.perm[lo + q];
+                paired = 1.0;
+                formed = (r & 1) == 0 ? 1.0 : 0.0;
+            }
+        }
+        if constexpr (std::is_same<real, double>::value) a.best[i] = partner;
+        else a.bkey[i] = partner >= 0 ? (unsigned long long)(uint32_t)partner : ~0ull;
+    }
+    const double f = block_sum(formed, lds);
+    const double c = block_sum(paired, lds);
+    if (threadIdx.x == 0 && (f != 0.0 || c != 0.0)) {
+        double* gp = a.gpart + (int64_t)blockIdx.x * kGPart;
+        unsafeAtomicAdd(gp + GP_TESTS2, 2.0 * f);
+        unsafeAtomicAdd(gp + GP_CAND, c);
+    }
+}
+
+// Whether the random pair of record i (position x, y, z) and its partner
+// collides: u < (((n_c - 1) sigma) g) dt / V_c in double, with the pair's own
+// Philox draw; both records of the pair take the same decision.
+template <typename real>
+__device__ __forceinline__ bool random_pair_collides(const StepArgs<real>& a, const Inst<real>& I, real x, real y,
+                                                     real z, uint32_t idi, real vxi, real vyi, real vzi,
+                                                     uint32_t idj, real vxj, real vyj, real vzj) {
+#pragma clang fp contract(off)
+    const bool iA = idi < idj;
+    const double ux = iA ? (double)vxi - (double)vxj : (double)vxj - (double)vxi;
+    const double uy = iA ? (double)vyi - (double)vyj : (double)vyj - (double)vyi;
+    const double uz = iA ? (double)vzi - (double)vzj : (double)vzj - (double)vzi;
+    const double g = sqrt((ux * ux + uy * uy) + uz * uz);
+    const int64_t k = record_cbin(I, x, y, z);
+    const int64_t nc = (int64_t)a.start[k + 1] - a.start[k];
+    const double prob = ((((double)(nc - 1) * I.sigma_d) * g) * I.dt_d) / I.cellvol_d;
+    uint32_t c[4] = {I.step_lo, iA ? idi : idj, iA ? idj : idi, (I.instance << 8) | 255u};
+    philox4x32_10(c, I.seed_lo, I.seed_hi);
+    const double u = ((double)(c[0] >> 5) * 67108864.0 + (double)(c[1] >> 6)) * (1.0 / 9007199254740992.0);
+    return u < prob;
 }
 
 // ---------------------------------------------------------------- 5. move
@@ -965,14 +1099,19 @@ __global__ void __launch_bounds__(kMoveLanes) k_move(StepArgs<real> a) {
                 const real dt = I.dt;
                 const real mi = has_mass ? a.rmass[i] : I.mass;
                 const int32_t j = j_pre;
-                const bool mutual = j >= 0 && partner_of<real>(a, j) == (int32_t)i;
+                bool mutual = j >= 0 && partner_of<real>(a, j) == (int32_t)i;
                 ghave += j >= 0 ? 1.0 : 0.0;
                 real nx = x, ny = y, nz = z, nvx = vx, nvy = vy, nvz = vz;
                 double virx = 0, viry = 0, virz = 0;
+                const bool random_pairs = (I.flags & TPKMC_PAIR_RANDOM) != 0;
+                real xj = 0, yj = 0, zj = 0, vxj = 0, vyj = 0, vzj = 0;
+                uint32_t idj = 0, flj = 0;
                 if (mutual) {
-                    real xj, yj, zj, vxj, vyj, vzj;
-                    uint32_t idj, flj;
                     Rec<real>::load(a.rec, j, xj, yj, zj, idj, vxj, vyj, vzj, flj);
+                    if (random_pairs)
+                        mutual = random_pair_collides(a, I, x, y, z, idi, vx, vy, vz, idj, vxj, vyj, vzj);
+                }
+                if (mutual) {
                     const bool isA = idi < idj;
                     // Pair quantities with A = lower id, B = higher id.
                     const real xA = isA ? x : xj, yA = isA ? y : yj, zA = isA ? z : zj;
@@ -986,7 +1125,8 @@ __global__ void __launch_bounds__(kMoveLanes) k_move(StepArgs<real> a) {
                     const real ux = vxA - vxB, uy = vyA - vyB, uz = vzA - vzB;
                     const real s0 = (rx * ux + ry * uy) + rz * uz;
                     const real vv = (ux * ux + uy * uy) + uz * uz;
-                    const real tp = -s0 / vv;
+                    // Random partners collide at the start of the step.
+                    const real tp = random_pairs ? real(0) : -s0 / vv;
                     double nh[3];
                     pair_direction(I.seed_lo, I.seed_hi, I.step_lo, I.instance, isA ? idi : idj, isA ? idj : idi,
                                    (I.flags & TPKMC_PLANAR) != 0, nh);
@@ -1217,6 +1357,12 @@ void launch_search(const StepArgs<real>& a, int block, int group, hipStream_t s)
     if (group == 4) hipLaunchKernelGGL((k_search<real, half, 4>), dim3(grid), dim3(bs), 0, s, a);
     else if (group == 2) hipLaunchKernelGGL((k_search<real, half, 2>), dim3(grid), dim3(bs), 0, s, a);
     else hipLaunchKernelGGL((k_search<real, half, 1>), dim3(grid), dim3(bs), 0, s, a);
+}
+template <typename real>
+void launch_random_pairs(const StepArgs<real>& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_rp_key<real>, dim3(a.nblk), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_rp_rank<real>, dim3(a.nblk), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_rp_partner<real>, dim3(a.nblk), dim3(kBlock), 0, s, a);
 }
 template <typename real>
 void launch_move(const StepArgs<real>& a, hipStream_t s) {

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(HERE, "libtpkmc.so")
 
 FP64, FP32 = 0, 1
 REFLECT, PERIODIC, ABSORB = 0, 1, 2
-EMIT_PAIRS, ALLOW_REORDER, ADAPTIVE_DT, PLANAR, RANK_TIME = 1, 2, 4, 8, 16
+EMIT_PAIRS, ALLOW_REORDER, ADAPTIVE_DT, PLANAR, RANK_TIME, PAIR_RANDOM = 1, 2, 4, 8, 16, 32
 STATUS_PAIR_OVERFLOW, STATUS_NONFINITE, STATUS_FAST = 1, 2, 4
 CNT = dict(alive=0, pairs=1, tests=2, cand=3, fast=4, nonfinite=5, absorbed=6, have_best=7)
 GLB = dict(px=0, py=1, pz=2, ekin=3, vmax2=4, virial=5, mass=6, dt=7)
@@ -135,6 +135,8 @@ def make_params(p, flags=0) -> Params:
         P.flags |= PLANAR
     if p.get("rank_time"):
         P.flags |= RANK_TIME
+    if p.get("pair_random"):
+        P.flags |= PAIR_RANDOM
     return P
 
 
