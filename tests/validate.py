@@ -30,13 +30,14 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 
-def _run(w, precision, steps, progress=None, rank_time=False):
+def _run(w, precision, steps, progress=None, rank_time=False, pair_random=False):
     """Advance workload w by `steps` steps on the GPU; returns host state,
     the last step's moments and per-step globals/counters.  rank_time:
-    criterion 3 by earliest contact instead of closest approach."""
+    criterion 3 by earliest contact instead of closest approach; pair_random:
+    random partners inside each c-bin (the DSMC rule) instead of criteria 1-3."""
     import torch
     from paper_1210_8084_amd import tpkmc as T
-    g, p = w.grid, dict(w.params, rank_time=rank_time)
+    g, p = w.grid, dict(w.params, rank_time=rank_time, pair_random=pair_random)
     eng = T.Engine(max_particles=w.n, max_cells=T.ncells(g) + 1, max_obins=T.nobins(g), precision=precision)
     dst = T.to_device(w.state, precision)
     out = T.make_outputs(1, T.nobins(g))
@@ -90,7 +91,7 @@ def _tanh_width(x, n, x_s, lo, hi):
     return float(2.0 * math.atanh(0.8) * abs(d)), float(c)
 
 
-def sod(precision, n=4_000_000, steps=500, kn=1e-3, planar=False, seed=1, rank_time=False):
+def sod(precision, n=4_000_000, steps=500, kn=1e-3, planar=False, seed=1, rank_time=False, pair_random=False):
     from oracle import analytic as A
     from paper_1210_8084_amd import workloads as W
     if planar:
@@ -98,7 +99,7 @@ def sod(precision, n=4_000_000, steps=500, kn=1e-3, planar=False, seed=1, rank_t
     else:
         w = W.sod(n=n, ncell=1000, nobin=200, dt=1.134e-4, kn=kn, seed=seed)
     f = 2 if planar else 3
-    r = _run(w, precision, steps, progress=100, rank_time=rank_time)
+    r = _run(w, precision, steps, progress=100, rank_time=rank_time, pair_random=pair_random)
     t = steps * w.params["dt"]
     M = r["moments"]
     nob = w.grid["nobin"][0]
@@ -130,7 +131,7 @@ def sod(precision, n=4_000_000, steps=500, kn=1e-3, planar=False, seed=1, rank_t
     fn = fc / ((fe[1] - fe[0]) * (w.info["side"] if planar else 0.05 * 0.05))
     width, x_fit = _tanh_width(0.5 * (fe[1:] + fe[:-1]), fn, x_s, nr, n2)
     return dict(workload=f"{w.name} n={n} kn={kn}", steps=steps, t=t, wall_s=r["wall"],
-                rank="contact time" if rank_time else "closest approach",
+                rank="random partners" if pair_random else "contact time" if rank_time else "closest approach",
                 shock_x_exact=x_s, shock_x_fit=x_fit, shock_width=width, shock_width_mfp=width / lam,
                 l1_density=float(np.mean(np.abs(n_ - rho)) / nl),
                 l1_pressure_kinetic=float(np.mean(np.abs(p_kin - p)) / (nl * tl)),
@@ -204,11 +205,11 @@ def noh3d(precision, n=8_000_000, steps=160, seed=1):
                 **_conservation(w, r))
 
 
-def sedov(precision, n=16_000_000, steps=600, planar=False, seed=1, rank_time=False):
+def sedov(precision, n=16_000_000, steps=600, planar=False, seed=1, rank_time=False, pair_random=False):
     from oracle import analytic as A
     from paper_1210_8084_amd import workloads as W
     w = (W.sedov2d if planar else W.sedov)(n=n, steps=steps, seed=seed)
-    r = _run(w, precision, steps, progress=200, rank_time=rank_time)
+    r = _run(w, precision, steps, progress=200, rank_time=rank_time, pair_random=pair_random)
     t = steps * w.params["dt"]
     st = r["state"]
     j = 2 if planar else 3
@@ -241,7 +242,7 @@ def sedov(precision, n=16_000_000, steps=600, planar=False, seed=1, rank_time=Fa
     width = float(outer_cross(1.0 + 0.1 * (top - 1.0)) - outer_cross(1.0 + 0.9 * (top - 1.0)))
     lam = w.info.get("lam", 1e-3)
     return dict(workload=f"{w.name} n={n}", steps=steps, t=t, wall_s=r["wall"], r_shock_analytic=R,
-                rank="contact time" if rank_time else "closest approach",
+                rank="random partners" if pair_random else "contact time" if rank_time else "closest approach",
                 front_width=width, front_width_mfp=width / lam,
                 r_density_peak=float(rc[peak]), peak_density=float(rho[peak]),
                 l1_density=float(np.mean(np.abs(rho - ra))),
@@ -270,8 +271,9 @@ def main():
     ap.add_argument("--seeds", default="1", help="comma-separated workload seeds; with several, the "
                     "report adds the mean and spread of L1 and of the FP32 - FP64 difference")
     ap.add_argument("--rank-compare", action="store_true",
-                    help="criterion 3 by closest approach against by earliest contact (FP32): collided "
-                    "fraction, L1 density and shock width of the Sod tube and the Sedov blast")
+                    help="partners by closest approach against by earliest contact and against random "
+                    "partners inside each c-bin (FP32): collided fraction, L1 density and shock width of the "
+                    "Sod tube and the Sedov blast")
     args = ap.parse_args()
     from paper_1210_8084_amd import tpkmc as T
     seeds = [int(v) for v in args.seeds.split(",")]
@@ -280,15 +282,15 @@ def main():
         keys = ("rank", "collided_fraction", "l1_density", "shock_width_mfp", "front_width_mfp", "peak_density",
                 "energy_rel_drift")
         for name in ("sod", "sedov"):
-            for rank_time in (False, True):
-                print(f"== {name} rank_time={rank_time}", flush=True)
+            for rule in ("distance", "time", "random"):
+                kw = dict(rank_time=rule == "time", pair_random=rule == "random")
+                print(f"== {name} {rule}", flush=True)
                 if name == "sod":
-                    res = sod(T.FP32, n=400_000 if args.quick else 4_000_000, steps=100 if args.quick else 500,
-                              rank_time=rank_time)
+                    res = sod(T.FP32, n=400_000 if args.quick else 4_000_000, steps=100 if args.quick else 500, **kw)
                 else:
                     res = sedov(T.FP32, n=2_000_000 if args.quick else 16_000_000, steps=150 if args.quick else 600,
-                                rank_time=rank_time)
-                report[f"{name}_{'time' if rank_time else 'distance'}"] = res
+                                **kw)
+                report[f"{name}_{rule}"] = res
                 print(json.dumps({k: res[k] for k in keys if k in res}), flush=True)
         if args.out:
             with open(args.out, "w") as f:
