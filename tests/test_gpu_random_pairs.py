@@ -167,3 +167,46 @@ def test_random_partners_refuse_contact_ranking(T):
     with pytest.raises(T.TpkmcError):
         eng.step(dst, w.grid, dict(w.params, pair_random=True, rank_time=True), out)
     eng.close()
+
+
+def test_fp64_random_partners_dense_bins_and_tube(T, oracle):
+    """The Sod tube with a few hundred particles per c-bin (the in-bin rank
+    loop at its longest): two steps bit-identical to the oracle."""
+    w = W.sod(n=200_000, seed=111, ncell=50, nobin=10, dt=1e-4)
+    w.params = dict(w.params, pair_random=True)
+    _say("random partners fp64 sod 200k, 50 c-bins")
+    got, gouts = _gpu(T, w, T.FP64, 2, flags=T.EMIT_PAIRS | T.ALLOW_REORDER)
+    want, routs = _oracle(oracle, w, 2)
+    # reordered arrays: compare particle by particle
+    a, b = np.argsort(got["id"]), np.argsort(want["id"])
+    for k in ("x", "y", "z", "vx", "vy", "vz"):
+        assert np.array_equal(got[k][a], want[k][b]), k
+    for go, ro in zip(gouts, routs):
+        assert go["counters"][0].tolist() == ro["counters"].tolist()
+        assert _pairset(go["pairs"]) == _pairset(ro["pairs"])
+    assert routs[0]["counters"][oracle.CNT["pairs"]] > 1000
+
+
+def test_graph_run_random_partners(T, oracle):
+    """tpkmc_run replays the step with the step counter advanced on the
+    device: the random keys follow it, as in plain steps and the oracle."""
+    w = W.random_box(n=4000, seed=112, ncell=(8, 6, 5), bc=(R, R, P), d_over_w=0.15, dt_over=0.1)
+    w.params = dict(w.params, pair_random=True, step=3)
+    g = w.grid
+    kw = dict(max_particles=w.n, max_cells=T.ncells(g) + 1, max_obins=T.nobins(g), precision=T.FP64)
+    K = 4
+    e1 = T.Engine(**kw)
+    d1 = T.to_device(w.state, T.FP64)
+    o1 = T.make_outputs(1, T.nobins(g))
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        e1.run(d1, [(0, w.n, g, w.params)], K, o1, stream=stream)
+    stream.synchronize()
+    got = T.to_host(d1)
+    e1.close()
+    ref = W.copy_state(w.state)
+    for s in range(K):
+        ro = oracle.step(ref, g, dict(w.params, step=3 + s))
+    for k in ("x", "y", "z", "vx", "vy", "vz"):
+        assert np.array_equal(got[k], ref[k]), k
+    assert o1.host()["counters"][0].tolist() == ro["counters"].tolist()
