@@ -241,8 +241,8 @@ def main():
                     help="after the run, copy a 1 GiB device buffer 3 times (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the collision step is not sharded across GPUs in this "
-              "build (see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs the collision step on a single GPU and "
+              "does not shard it across GPUs; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "batched64":
