@@ -65,7 +65,7 @@ enum {
     TPKMC_ENOMEM = -2,       /* device allocation failed (tpkmc_create)      */
     TPKMC_EHIP = -3,         /* a HIP runtime call failed                    */
     TPKMC_ECAPACITY = -4,    /* input exceeds the capacities of the handle   */
-    TPKMC_EUNSUPPORTED = -5  /* valid but not supported by this build        */
+    TPKMC_EUNSUPPORTED = -5  /* valid but not supported by the library       */
 };
 
 enum { TPKMC_FP64 = 0, TPKMC_FP32 = 1 };
