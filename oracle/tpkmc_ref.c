@@ -65,7 +65,7 @@ static double unit_double(uint32_t a, uint32_t b)
     return (hi * 67108864.0 + lo) * (1.0 / 9007199254740992.0);
 }
 
-/* Outgoing directions are "random and opposite" (Sec. 3); the random unit
+/* The outgoing directions are random and opposite (Sec. 3); the random unit
  * vector is drawn with Marsaglia's 1972 rejection method, which needs only a
  * square root.  The counter names the pair and the draw. */
 int ref_direction(uint64_t seed, uint64_t step, uint32_t instance,
