@@ -120,6 +120,47 @@ __device__ __forceinline__ uint64_t lanes_le(int lane) {
     return lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
 }
 
+// Cross-lane moves of a double through the VALU's data-parallel primitives
+// (DPP) instead of the LDS permute unit; every lane of the wave must be
+// active.  Quad permutations: lane q of each group of four reads lane P[q]
+// of its group, encoded P[0] | P[1] << 2 | P[2] << 4 | P[3] << 6.  Row
+// shifts (0x100 + n): lane r of each row of 16 lanes reads lane r + n of
+// the row (lanes past the row's end read nothing defined and must not use
+// the value).  Row rotations (0x120 + n) rotate each row by n.
+constexpr int kQuadXor1 = 1 | 0 << 2 | 3 << 4 | 2 << 6;
+constexpr int kQuadXor2 = 2 | 3 << 2 | 0 << 4 | 1 << 6;
+constexpr int kRowShl1 = 0x101;
+constexpr int kRowShl2 = 0x102;
+constexpr int kRowShl4 = 0x104;
+constexpr int kRowShl8 = 0x108;
+constexpr int kRowRor4 = 0x124;
+constexpr int kRowRor8 = 0x128;
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double lane_value(double v, int lane) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
+                            __builtin_amdgcn_readlane(__double2loint(v), lane));
+}
+
+// Sum (or maximum) of a double over the 64 lanes, in a fixed order: pairs,
+// quads and rows through DPP, then the four row totals.  Every lane must be
+// active; the result is returned in every lane.
+template <bool MAX>
+__device__ __forceinline__ double wave_reduce(double v) {
+    auto op = [](double x, double y) { return MAX ? fmax(x, y) : x + y; };
+    v = op(v, dpp_move<kQuadXor1>(v));
+    v = op(v, dpp_move<kQuadXor2>(v));
+    v = op(v, dpp_move<kRowRor4>(v));
+    v = op(v, dpp_move<kRowRor8>(v));
+    return op(op(lane_value(v, 0), lane_value(v, 16)), op(lane_value(v, 32), lane_value(v, 48)));
+}
+
 // Sum of an int over the work-group (blockDim.x <= 1024), result in all threads.
 __device__ __forceinline__ double block_sum(double v, double* lds) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -310,10 +351,8 @@ __global__ void __launch_bounds__(kWave) k_key(StepArgs<real> a) {
         const int b = __shfl(base[r], seg0[r] < 0 ? 0 : seg0[r]);
         if (p < end) a.rank[p] = b + (lane - seg0[r]);
     }
-    for (int o = 32; o > 0; o >>= 1) {
-        nonfin += __shfl_xor(nonfin, o);
-        v2 = fmax(v2, __shfl_xor(v2, o));
-    }
+    nonfin = wave_reduce<false>(nonfin);
+    v2 = wave_reduce<true>(v2);
     if (lane == 0) {
         double* gp = a.gpart + (int64_t)blockIdx.x * kGPart;
         gp[GP_NONFINITE] = nonfin;
@@ -997,6 +1036,15 @@ template <> __device__ __forceinline__ int32_t partner_of<float>(const StepArgs<
     return k == ~0ull ? -1 : (int32_t)(uint32_t)k;
 }
 
+// o-bin (with the instance's offset) of a position.
+template <typename real>
+__device__ __forceinline__ int obin_of(const Inst<real>& I, real x, real y, real z) {
+    const int bx = axis_bin(x, I.lo[0], I.inv_wo[0], I.no[0]);
+    const int by = axis_bin(y, I.lo[1], I.inv_wo[1], I.no[1]);
+    const int bz = axis_bin(z, I.lo[2], I.inv_wo[2], I.no[2]);
+    return (int)(I.obin_off + bx + (int64_t)I.no[0] * (by + (int64_t)I.no[1] * bz));
+}
+
 // Work-group table of o-bin sums, flushed with one atomic per value per bin.
 constexpr int kSlots = 64;
 struct MomentTable {
@@ -1029,13 +1077,22 @@ __device__ __forceinline__ int table_slot(MomentTable& T, int ob) {
 constexpr int kMoveRec = 2;
 constexpr int kMoveLanes = kBlock / kMoveRec;
 
+// The table and the global fallback are written on separate paths, so the
+// table's adds stay LDS atomics (one pointer for both would make every add a
+// generic-address atomic).
 template <typename real>
 __device__ __forceinline__ void moment_flush(MomentTable& tab, const StepArgs<real>& a, int ob, const double* mv) {
     const int slot = table_slot(tab, ob);
-    double* dst = slot >= 0 ? tab.val[slot] : a.moments + (int64_t)ob * TPKMC_MOMENT_STRIDE;
+    if (slot >= 0) {
 #pragma unroll
-    for (int k = 0; k < TPKMC_MOMENT_STRIDE; ++k)
-        if (k < 7 || k == 11 || mv[k] != 0.0) unsafeAtomicAdd(dst + k, mv[k]);
+        for (int k = 0; k < TPKMC_MOMENT_STRIDE; ++k)
+            if (k < 7 || k == 11 || mv[k] != 0.0) unsafeAtomicAdd(&tab.val[slot][k], mv[k]);
+    } else {
+        double* dst = a.moments + (int64_t)ob * TPKMC_MOMENT_STRIDE;
+#pragma unroll
+        for (int k = 0; k < TPKMC_MOMENT_STRIDE; ++k)
+            if (k < 7 || k == 11 || mv[k] != 0.0) unsafeAtomicAdd(dst + k, mv[k]);
+    }
 }
 
 template <typename real>
@@ -1214,15 +1271,12 @@ __global__ void __launch_bounds__(kMoveLanes) k_move(StepArgs<real> a) {
                     gm += m;
                     galive += 1.0;
                     if (a.moments) {
-                        const int bx = axis_bin(nx, I.lo[0], I.inv_wo[0], I.no[0]);
-                        const int by = axis_bin(ny, I.lo[1], I.inv_wo[1], I.no[1]);
-                        const int bz = axis_bin(nz, I.lo[2], I.inv_wo[2], I.no[2]);
-                        const int ob = (int)(I.obin_off + bx + (int64_t)I.no[0] * (by + (int64_t)I.no[1] * bz));
+                        const int ob = obin_of(I, nx, ny, nz);
                         if (ob != mob) {
                             if (mob >= 0) moment_flush(tab, a, mob, mv);
-                            mob = ob;
                             const double* S = a.shift + (int64_t)ob * 3;
                             shx = S[0]; shy = S[1]; shz = S[2];
+                            mob = ob;
 #pragma unroll
                             for (int k = 0; k < TPKMC_MOMENT_STRIDE; ++k) mv[k] = 0.0;
                         }
@@ -1255,30 +1309,33 @@ __global__ void __launch_bounds__(kMoveLanes) k_move(StepArgs<real> a) {
     }
     if (a.moments) {
         // Consecutive lanes hold consecutive records, so their last runs come
-        // in runs of one o-bin across the wave.  Within each such run of lanes,
-        // every group of four is first summed into its first lane (two steps
-        // of a segmented reduction), which alone goes through the table: a
-        // quarter of the conflicting LDS atomics.  Measured against one to six
-        // steps, two are best on the 16M Sedov blast (runs of ~7 lanes) and
-        // close to best on the Noh implosion (longer runs).
+        // in runs of one o-bin across the wave.  Within each row of 16 lanes,
+        // the lanes of one run are first summed into the run's first lane of
+        // the row (a segmented suffix sum by doubling, DPP row shifts of 1, 2,
+        // 4 and 8 lanes), which alone goes through the table.
         const int prev_mob = __shfl_up(mob, 1);
         const bool head = lane == 0 || prev_mob != mob;
         const uint64_t heads = __ballot(head);
         const uint64_t after = heads & ~lanes_le(lane);
-        const int seg0 = 63 - __clzll((long long)(heads & lanes_le(lane)));
         const int seg1 = after ? __ffsll((long long)after) - 1 : 64;
+        const int rl = lane & 15;
+        const int lim = min(seg1, lane - rl + 16) - lane;  // lanes of my run in my row, from me on
         const bool coll = __ballot(mv[7] != 0.0 || mv[8] != 0.0 || mv[9] != 0.0 || mv[10] != 0.0) != 0;
 #pragma unroll
         for (int k = 0; k < TPKMC_MOMENT_STRIDE; ++k) {
-            if (k >= 7 && k <= 10 && !coll) continue;
+            if (k >= 7 && k <= 10 && !coll) continue;  // wave-uniform
             double v = mv[k];
-            for (int d = 1; d < 4; d <<= 1) {
-                const double u = __shfl_down(v, d);
-                if (lane + d < seg1) v += u;
-            }
+            double u = dpp_move<kRowShl1>(v);
+            if (1 < lim) v += u;
+            u = dpp_move<kRowShl2>(v);
+            if (2 < lim) v += u;
+            u = dpp_move<kRowShl4>(v);
+            if (4 < lim) v += u;
+            u = dpp_move<kRowShl8>(v);
+            if (8 < lim) v += u;
             mv[k] = v;
         }
-        if (((lane - seg0) & 3) == 0 && mob >= 0) moment_flush(tab, a, mob, mv);
+        if ((head || rl == 0) && mob >= 0) moment_flush(tab, a, mob, mv);
         __syncthreads();
         for (int t = tid; t < kSlots; t += kMoveLanes) {
             const int ob = tab.key[t];
@@ -1290,11 +1347,7 @@ __global__ void __launch_bounds__(kMoveLanes) k_move(StepArgs<real> a) {
     }
     double v[11] = {gpx, gpy, gpz, gek, gvm, gvir, gm, galive, gpairs, gabs, ghave};
 #pragma unroll
-    for (int k = 0; k < 11; ++k)
-        for (int o = 32; o > 0; o >>= 1) {
-            const double u = __shfl_xor(v[k], o);
-            v[k] = k == 4 ? fmax(v[k], u) : v[k] + u;
-        }
+    for (int k = 0; k < 11; ++k) v[k] = k == 4 ? wave_reduce<true>(v[k]) : wave_reduce<false>(v[k]);
     if (kMoveLanes > 64) {
         if (lane == 0)
 #pragma unroll
