@@ -119,24 +119,37 @@ struct NSum {
 
 // Per-instance reduction of the work-group partials, in a fixed order:
 // first each chunk of <= kChunk work-groups, then each instance's chunks.
-// Thread k < kGPart owns slot k; Neumaier sums for the FP slots, max for
-// max|v|^2, plain sums for the (integer-valued) counts.
+// Sixteen threads per slot (work-groups of 256 threads): thread t of slot k
+// folds rows t, t + 16, t + 32, ... (Neumaier sums for the FP slots, max for
+// max|v|^2, plain sums for the integer-valued counts), then a butterfly over
+// the sixteen lanes combines their partials with a commutative step, so all
+// sixteen end with the same total.
+constexpr int kSlotLanes = 256 / kGPart;
+static_assert(kSlotLanes * kGPart == 256 && (kSlotLanes & (kSlotLanes - 1)) == 0, "slot lanes");
+
 __device__ __forceinline__ void reduce_slots(const double* rows, int nrows, double* out) {
-    const int k = threadIdx.x;
-    if (k >= kGPart) return;
+    const int k = threadIdx.x / kSlotLanes, t = threadIdx.x % kSlotLanes;
+    double s = 0.0, c = 0.0;
     if (k == GP_VMAX2) {
-        double m = 0.0;
-        for (int r = 0; r < nrows; ++r) m = fmax(m, rows[(int64_t)r * kGPart + k]);
-        out[k] = m;
+        for (int r = t; r < nrows; r += kSlotLanes) s = fmax(s, rows[(int64_t)r * kGPart + k]);
+        for (int o = 1; o < kSlotLanes; o <<= 1) s = fmax(s, __shfl_xor(s, o));
     } else if (k < GP_ALIVE) {
-        NSum s;
-        for (int r = 0; r < nrows; ++r) s.add(rows[(int64_t)r * kGPart + k]);
-        out[k] = s.value();
+        NSum a;
+        for (int r = t; r < nrows; r += kSlotLanes) a.add(rows[(int64_t)r * kGPart + k]);
+        s = a.s;
+        c = a.c;
+        for (int o = 1; o < kSlotLanes; o <<= 1) {
+            const double s2 = __shfl_xor(s, o), c2 = __shfl_xor(c, o);
+            const double sum = s + s2;
+            const double err = fabs(s) >= fabs(s2) ? (s - sum) + s2 : (s2 - sum) + s;
+            c = (c + c2) + err;
+            s = sum;
+        }
     } else {
-        double t = 0.0;
-        for (int r = 0; r < nrows; ++r) t += rows[(int64_t)r * kGPart + k];
-        out[k] = t;
+        for (int r = t; r < nrows; r += kSlotLanes) s += rows[(int64_t)r * kGPart + k];
+        for (int o = 1; o < kSlotLanes; o <<= 1) s += __shfl_xor(s, o);
     }
+    if (t == 0) out[k] = s + c;
 }
 
 __global__ void __launch_bounds__(256) k_reduce_chunks(const Chunk* chunks, const double* gpart, double* cpart) {
@@ -212,25 +225,39 @@ __global__ void __launch_bounds__(256) k_finalize(Inst<real>* inst, const double
 
 // Shifted o-bin sums -> momentum and central second moments; the bin mean
 // becomes the shift of the next step, so the sums stay small next time.
+// Each work-group (256 threads) stages the rows of its 256 o-bins through
+// LDS, so the loads and stores are coalesced.
 template <typename real>
-__global__ void k_moments_final(const Inst<real>* inst, double* moments, double* shift) {
+__global__ void __launch_bounds__(256) k_moments_final(const Inst<real>* inst, double* moments, double* shift) {
+    constexpr int kRows = 256;
+    __shared__ double rows[kRows * TPKMC_MOMENT_STRIDE];
     const Inst<real>& I = inst[blockIdx.y];
     const int64_t nb = (int64_t)I.no[0] * I.no[1] * I.no[2];
-    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nb) return;
-    const int64_t ob = I.obin_off + b;
-    double* M = moments + ob * TPKMC_MOMENT_STRIDE;
-    double* S = shift + ob * 3;
-    const double cnt = M[0];
-    if (cnt > 0.0) {
-        const double mass = M[11];
-        for (int a = 0; a < 3; ++a) {
-            const double s1 = M[1 + a], s2 = M[4 + a];
-            const double mean_off = s1 / mass;
-            M[1 + a] = s1 + mass * S[a];
-            M[4 + a] = fmax(s2 - s1 * mean_off, 0.0);
-            S[a] = S[a] + mean_off;
+    const int64_t b0 = (int64_t)blockIdx.x * kRows;
+    if (b0 >= nb) return;  // whole work-group
+    const int nloc = (int)min<int64_t>(kRows, nb - b0);
+    double* M0 = moments + (I.obin_off + b0) * TPKMC_MOMENT_STRIDE;
+    for (int t = threadIdx.x; t < nloc * TPKMC_MOMENT_STRIDE; t += kRows) rows[t] = M0[t];
+    __syncthreads();
+    if ((int)threadIdx.x < nloc) {
+        double* M = rows + threadIdx.x * TPKMC_MOMENT_STRIDE;
+        double* S = shift + (I.obin_off + b0 + threadIdx.x) * 3;
+        const double cnt = M[0];
+        if (cnt > 0.0) {
+            const double mass = M[11];
+            for (int a = 0; a < 3; ++a) {
+                const double s1 = M[1 + a], s2 = M[4 + a];
+                const double mean_off = s1 / mass;
+                M[1 + a] = s1 + mass * S[a];
+                M[4 + a] = fmax(s2 - s1 * mean_off, 0.0);
+                S[a] = S[a] + mean_off;
+            }
         }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < nloc * TPKMC_MOMENT_STRIDE; t += kRows) {
+        const int k = t % TPKMC_MOMENT_STRIDE;
+        if (k >= 1 && k <= 6) M0[t] = rows[t];
     }
 }
 
