@@ -244,7 +244,9 @@ __global__ void __launch_bounds__(256) k_moments_final(const Inst<real>* inst, d
         double* S = shift + (I.obin_off + b0 + threadIdx.x) * 3;
         const double cnt = M[0];
         if (cnt > 0.0) {
-            const double mass = M[11];
+            // Without per-particle masses the move leaves the mass sum out.
+            const double mass = (I.flags & kHasMass) ? M[11] : cnt * I.mass_d;
+            M[11] = mass;
             for (int a = 0; a < 3; ++a) {
                 const double s1 = M[1 + a], s2 = M[4 + a];
                 const double mean_off = s1 / mass;
@@ -257,7 +259,7 @@ __global__ void __launch_bounds__(256) k_moments_final(const Inst<real>* inst, d
     __syncthreads();
     for (int t = threadIdx.x; t < nloc * TPKMC_MOMENT_STRIDE; t += kRows) {
         const int k = t % TPKMC_MOMENT_STRIDE;
-        if (k >= 1 && k <= 6) M0[t] = rows[t];
+        if ((k >= 1 && k <= 6) || k == 11) M0[t] = rows[t];
     }
 }
 

@@ -1079,19 +1079,21 @@ constexpr int kMoveLanes = kBlock / kMoveRec;
 
 // The table and the global fallback are written on separate paths, so the
 // table's adds stay LDS atomics (one pointer for both would make every add a
-// generic-address atomic).
+// generic-address atomic).  Zero values are skipped: the virial and collider
+// count outside collisions, the mass sum without per-particle masses (the
+// finalisation takes count x mass), the z terms in the plane.
 template <typename real>
 __device__ __forceinline__ void moment_flush(MomentTable& tab, const StepArgs<real>& a, int ob, const double* mv) {
     const int slot = table_slot(tab, ob);
     if (slot >= 0) {
 #pragma unroll
         for (int k = 0; k < TPKMC_MOMENT_STRIDE; ++k)
-            if (k < 7 || k == 11 || mv[k] != 0.0) unsafeAtomicAdd(&tab.val[slot][k], mv[k]);
+            if (mv[k] != 0.0) unsafeAtomicAdd(&tab.val[slot][k], mv[k]);
     } else {
         double* dst = a.moments + (int64_t)ob * TPKMC_MOMENT_STRIDE;
 #pragma unroll
         for (int k = 0; k < TPKMC_MOMENT_STRIDE; ++k)
-            if (k < 7 || k == 11 || mv[k] != 0.0) unsafeAtomicAdd(dst + k, mv[k]);
+            if (mv[k] != 0.0) unsafeAtomicAdd(dst + k, mv[k]);
     }
 }
 
@@ -1284,7 +1286,7 @@ __global__ void __launch_bounds__(kMoveLanes) k_move(StepArgs<real> a) {
                         mv[0] += 1.0; mv[1] += m * ex; mv[2] += m * ey; mv[3] += m * ez;
                         mv[4] += m * ex * ex; mv[5] += m * ey * ey; mv[6] += m * ez * ez;
                         mv[7] += virx; mv[8] += viry; mv[9] += virz; mv[10] += mutual ? 1.0 : 0.0;
-                        mv[11] += m;
+                        if (has_mass) mv[11] += m;
                     }
                 }
             }
@@ -1323,7 +1325,7 @@ __global__ void __launch_bounds__(kMoveLanes) k_move(StepArgs<real> a) {
         const bool coll = __ballot(mv[7] != 0.0 || mv[8] != 0.0 || mv[9] != 0.0 || mv[10] != 0.0) != 0;
 #pragma unroll
         for (int k = 0; k < TPKMC_MOMENT_STRIDE; ++k) {
-            if (k >= 7 && k <= 10 && !coll) continue;  // wave-uniform
+            if ((k >= 7 && k <= 10 && !coll) || (k == 11 && !has_mass)) continue;  // wave-uniform
             double v = mv[k];
             double u = dpp_move<kRowShl1>(v);
             if (1 < lim) v += u;
@@ -1342,7 +1344,7 @@ __global__ void __launch_bounds__(kMoveLanes) k_move(StepArgs<real> a) {
             if (ob < 0) continue;
             double* M = a.moments + (int64_t)ob * TPKMC_MOMENT_STRIDE;
             for (int k = 0; k < TPKMC_MOMENT_STRIDE; ++k)
-                if (k < 7 || k == 11 || tab.val[t][k] != 0.0) unsafeAtomicAdd(M + k, tab.val[t][k]);
+                if (tab.val[t][k] != 0.0) unsafeAtomicAdd(M + k, tab.val[t][k]);
         }
     }
     double v[11] = {gpx, gpy, gpz, gek, gvm, gvir, gm, galive, gpairs, gabs, ghave};
