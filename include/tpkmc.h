@@ -163,7 +163,8 @@ enum { TPKMC_G_PX = 0, TPKMC_G_EKIN = 3, TPKMC_G_VMAX2 = 4, TPKMC_G_VIRIAL = 5, 
  *  0 count; 1..3 sum m v_a; 4..6 sum m (v_a - vbar_a)^2 with vbar the bin's
  *  mass-weighted mean velocity; 7..9 sum over colliders of (1/2) s_a dp_a /
  *  dt with s the separation from the partner at closest approach and dp the
- *  momentum change; 10 number of colliders; 11 sum m.  Pressure of a bin of
+ *  momentum change; 10 number of colliders; 11 sum m (count x mass for a
+ *  scalar mass, rounded once).  Pressure of a bin of
  *  volume V: p = (sum_a [4+a] + sum_a [7+a]) / (3 V); temperature
  *  T = sum_a [4+a] / (3 count). */
 #define TPKMC_MOMENT_STRIDE 12
@@ -227,8 +228,8 @@ typedef struct {
  * pairs: uint32[2 * pair_cap], rows (id_A, id_B) with id_A < id_B in
  * unspecified order; pairs beyond pair_cap are counted, not written, and
  * set TPKMC_STATUS_PAIR_OVERFLOW.  counters: uint64[8 * n_inst];
- * globals: double[8 * n_inst]; moments: double[11 * sum of o-bins], the
- * instances' o-bin blocks concatenated in instance order. */
+ * globals: double[8 * n_inst]; moments: double[TPKMC_MOMENT_STRIDE * sum of
+ * o-bins], the instances' o-bin blocks concatenated in instance order. */
 typedef struct {
     uint32_t* pairs;
     int64_t pair_cap;
