@@ -36,6 +36,10 @@ HBM_PEAK = 8.0e12
 MOMENT_VALUES = 12  # doubles per o-bin
 
 
+WORKLOAD_NAMES = {"sedov16M": "16M-particle Sedov", "sod4M": "4M-particle Sod", "sod4M_kn0.1": "4M-particle Sod at Kn 0.1",
+                  "noh8M": "8M-particle Noh", "sod100k": "100k-particle Sod"}
+
+
 def make_workload(name):
     from paper_1210_8084_amd import workloads as W
     if name == "sedov16M":
@@ -343,7 +347,8 @@ def main():
                "sample": sample}
 
     line = {
-        "metric": "particle-steps/s (collision step, 16M-particle Sedov, FP32 state)",
+        "metric": f"particle-steps/s (collision step, {WORKLOAD_NAMES[args.workload]}, "
+                  f"{args.precision.upper()} state)",
         "value": value,
         "unit": "particle-steps/s",
         "n_gpus": 1,
