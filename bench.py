@@ -18,6 +18,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -69,6 +70,14 @@ def phase_bytes(rs, n, ncell_tot, nobin, reorder):
     }
 
 
+def kernel_code_sha256(path):
+    """SHA-256 of a kernel source with its comments and blank lines removed:
+    the counter summaries stay valid across comment edits, not code edits."""
+    text = re.sub(r"/\*.*?\*/", "", open(path).read(), flags=re.S)
+    lines = (re.sub(r"//.*$", "", line).rstrip() for line in text.splitlines())
+    return hashlib.sha256("\n".join(line for line in lines if line.strip()).encode()).hexdigest()
+
+
 def read_traffic(workload, precision, shape):
     """HBM bytes per search launch from the committed rocprofv3 counter
     summary, if it was taken on the current kernel source and in the launch
@@ -82,8 +91,7 @@ def read_traffic(workload, precision, shape):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
     src = os.path.join(ROOT, "paper_1210_8084_amd", "csrc", "tpkmc_kernels.h")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if vals.get("kernel_source_sha256") != sha:
+    if vals.get("kernel_code_sha256") != kernel_code_sha256(src):
         return None
     if vals.get("search_shape") != f"{shape[0]},{shape[1]}":
         return None

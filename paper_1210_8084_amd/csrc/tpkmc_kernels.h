@@ -161,7 +161,7 @@ __device__ __forceinline__ double wave_reduce(double v) {
     return op(op(lane_value(v, 0), lane_value(v, 16)), op(lane_value(v, 32), lane_value(v, 48)));
 }
 
-// Sum of an int over the work-group (blockDim.x <= 1024), result in all threads.
+// Sum of a double over the work-group (blockDim.x <= 1024), result in all threads.
 __device__ __forceinline__ double block_sum(double v, double* lds) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
