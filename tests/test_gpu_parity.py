@@ -660,3 +660,50 @@ def test_fp32_mixture_conserves(T, oracle):
     assert gouts[-1]["globals"][0][6] == pytest.approx(m.sum(), rel=1e-12)
     ro = oracle.step(W.copy_state(f32), w.grid, w.params)
     assert gouts[0]["counters"][0][1] == pytest.approx(ro["counters"][1], rel=0.02)
+
+
+def _boundary_pairs(n_pairs, seed, D, dt):
+    """Pairs placed on the edges of criteria 1 and 2 (closest approach just
+    before or after the end of the step, closest distance just below or above
+    D), one pair per c-bin of a lattice of bins much wider than their reach:
+    separations at the reach bound |r|^2 = D^2 + |u|^2 dt^2 of the search's
+    screen."""
+    rng = np.random.default_rng(seed)
+    nb = int(np.ceil(n_pairs ** (1.0 / 3.0)))
+    wb = 0.01
+    k = np.arange(n_pairs)
+    c = np.stack([(k % nb + 0.5) * wb, (k // nb % nb + 0.5) * wb, (k // (nb * nb) + 0.5) * wb])
+    u = rng.normal(size=(3, n_pairs))
+    u *= rng.uniform(0.3, 2.0, n_pairs) / np.sqrt((u * u).sum(axis=0))
+    q = rng.normal(size=(3, n_pairs))
+    q -= u * (q * u).sum(axis=0) / (u * u).sum(axis=0)
+    q /= np.sqrt((q * q).sum(axis=0))
+    e1 = rng.choice([-1.0, 1.0], n_pairs) * 10 ** rng.uniform(-13, -6, n_pairs)
+    e2 = rng.choice([-1.0, 1.0], n_pairs) * 10 ** rng.uniform(-13, -6, n_pairs)
+    r = -u * dt * (1.0 - e1) + q * D * (1.0 - e2)
+    va = 0.05 * rng.normal(size=(3, n_pairs))
+    pa, pb = c + 0.5 * r, c - 0.5 * r
+    vb = va - u
+    st = W.make_state(*np.concatenate([pa, pb], axis=1), *np.concatenate([va, vb], axis=1))
+    g = W.grid((0, 0, 0), (nb * wb,) * 3, (nb,) * 3, (P, P, P))
+    p = W.params(sigma=math.pi * D * D, dt=dt, seed=seed)
+
+    class Wl:
+        pass
+    w = Wl()
+    w.state, w.grid, w.params, w.n = st, g, p, 2 * n_pairs
+    return w
+
+
+def test_fp64_pairs_at_the_reach_bound(T, oracle):
+    """Pairs on the edges of both criteria, so at the search's reach screen:
+    the accepted pairs and the state stay bit-identical to the oracle's, and
+    both outcomes occur."""
+    w = _boundary_pairs(4000, seed=61, D=1e-3, dt=1e-3)
+    got, gouts, _ = gpu_steps(T, w, T.FP64)
+    want, routs = oracle_steps(oracle, w)
+    assert_state_equal(got, want)
+    assert pairset(gouts[0]["pairs"]) == pairset(routs[0]["pairs"])
+    assert gouts[0]["counters"][0].tolist() == routs[0]["counters"].tolist()
+    accepted = routs[0]["counters"][oracle.CNT["pairs"]]
+    assert 0.1 * 4000 < accepted < 0.9 * 4000
