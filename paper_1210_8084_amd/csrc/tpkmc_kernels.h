@@ -773,15 +773,37 @@ __device__ __forceinline__ void search_group(const StepArgs<real>& a, const Inst
             }
             int32_t u0 = own ? (UNIFORM ? wave_first : i0) + 1 : (int32_t)(base + a.start[row + ua]);
             int32_t u1 = (int32_t)(base + a.start[row + ub + 1]);
+            int32_t jm = u0;  // from jm on, the range masks need no test
+            bool split = false;
             if constexpr (UNIFORM) {
                 u0 = __builtin_amdgcn_readfirstlane(u0);
                 u1 = __builtin_amdgcn_readfirstlane(u1);
+                // When every non-empty range ends at u1, all of them are open
+                // from the largest lower end on, which the last lane holds
+                // (records are in c-bin order); checked for every lane.
+                int32_t lo_last = lo[0];
+#pragma unroll
+                for (int k = 1; k < G; ++k)
+                    if (k < nrec) lo_last = lo[k];
+                const int last = 63 - __clzll((long long)__ballot(true));
+                jm = __builtin_amdgcn_readlane(lo_last, last);
+                bool open = true;
+#pragma unroll
+                for (int k = 0; k < G; ++k) open &= hi[k] <= lo[k] || (hi[k] == u1 && lo[k] <= jm);
+                split = __ballot(!open) == 0 && jm >= u0 && jm <= u1;
             }
-            for (int32_t j = u0; j < u1; ++j) {
+            const int32_t um = split ? jm : u1;
+            for (int32_t j = u0; j < um; ++j) {
                 bool take[G];
 #pragma unroll
                 for (int k = 0; k < G; ++k) take[k] = (uint32_t)(j - lo[k]) < (uint32_t)(hi[k] - lo[k]);
                 visit(j, take);
+            }
+            if (split) {  // wave-uniform
+                bool take[G];
+#pragma unroll
+                for (int k = 0; k < G; ++k) take[k] = hi[k] > lo[k];
+                for (int32_t j = jm; j < u1; ++j) visit(j, take);
             }
         }
     } else {
