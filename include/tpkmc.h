@@ -45,8 +45,10 @@
  *     rule of Sec. 3 (dt = c-bin width / v_max), evaluated on the device.
  *   - Precision is fixed per handle: TPKMC_FP64 takes double particle
  *     arrays and reproduces the CPU oracle's pair decisions bit for bit;
- *     TPKMC_FP32 takes float arrays.  Moments and global sums are FP64 in
- *     both modes.
+ *     TPKMC_FP32 takes float arrays; its runs are not bit-reproducible
+ *     (exact FP32 ties of the closest distance go to the lower record, and
+ *     the record order inside a c-bin follows atomic ordering).  Moments and
+ *     global sums are FP64 in both modes.
  */
 #ifndef TPKMC_H
 #define TPKMC_H
