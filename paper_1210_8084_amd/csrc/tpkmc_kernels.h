@@ -301,8 +301,8 @@ __device__ __forceinline__ int cbin_key(const StepArgs<real>& a, const Inst<real
 constexpr int kKeyRec = kBlock / kWave;
 
 // c-bin count of every caller-order particle and its rank inside the c-bin.
-// Lanes holding the same c-bin in a run (the common case for sorted input)
-// take one atomic for the whole run.
+// Consecutive particles of the same c-bin (the common case for sorted input)
+// take one atomic for the whole run, also across the wave's rounds.
 template <typename real>
 __global__ void __launch_bounds__(kWave) k_key(StepArgs<real> a) {
     const Blk bt = a.blk[blockIdx.x];
@@ -323,8 +323,14 @@ __global__ void __launch_bounds__(kWave) k_key(StepArgs<real> a) {
             vx[r] = a.vx[p]; vy[r] = a.vy[p]; vz[r] = a.vz[p];
         }
     }
-    int key[kKeyRec], base[kKeyRec], seg0[kKeyRec];
+    // The wave's kKeyRec * 64 particles in caller order, q = r * 64 + lane,
+    // fall into runs of one c-bin (in c-bin order after the first step, one
+    // run per c-bin and wave); a run may span rounds.  Its first particle
+    // takes one atomic for the whole run.
+    int key[kKeyRec], base[kKeyRec];
+    uint64_t heads[kKeyRec];
     double nonfin = 0.0, v2 = 0.0;
+    int carry = -1;  // key of the previous round's last lane (keys are >= 0)
 #pragma unroll
     for (int r = 0; r < kKeyRec; ++r) {
         const int64_t p = (int64_t)bt.first + r * kWave + lane;
@@ -336,20 +342,43 @@ __global__ void __launch_bounds__(kWave) k_key(StepArgs<real> a) {
         } else if (in) {
             nonfin += (alive[r] && !fin) ? 1.0 : 0.0;
         }
-        const uint64_t active = __ballot(in);
-        const int prev = __shfl_up(key[r], 1);
-        const bool head = in && (lane == 0 || prev != key[r]);
-        const uint64_t heads = __ballot(head);
-        seg0[r] = 63 - __clzll((long long)(heads & lanes_le(lane)));
-        const uint64_t above = heads & ~lanes_le(lane);
-        const int seg1 = above ? (__ffsll((long long)above) - 1) : __popcll(active);
-        base[r] = head ? atomicAdd(&a.start[key[r]], seg1 - seg0[r]) : 0;
+        int prev = __shfl_up(key[r], 1);
+        if (lane == 0) prev = carry;
+        heads[r] = __ballot(in && prev != key[r]);
+        carry = __builtin_amdgcn_readlane(key[r], kWave - 1);
+    }
+    const int nvalid = (int)min<int64_t>(end - (int64_t)bt.first, (int64_t)kKeyRec * kWave);
+    int hq[kKeyRec];  // linear index of the run head of each of the lane's particles
+#pragma unroll
+    for (int r = 0; r < kKeyRec; ++r) {
+        const int q = r * kWave + lane;
+        const uint64_t below = heads[r] & lanes_le(lane);
+        int h = below ? r * kWave + 63 - __clzll((long long)below) : 0;
+        if (!below)
+            for (int rr = r - 1; rr >= 0; --rr)
+                if (heads[rr]) { h = rr * kWave + 63 - __clzll((long long)heads[rr]); break; }
+        hq[r] = h;
+        base[r] = 0;
+        if (q < nvalid && h == q) {
+            const uint64_t above = heads[r] & ~lanes_le(lane);
+            int nq = above ? r * kWave + __ffsll((long long)above) - 1 : nvalid;
+            if (!above)
+                for (int rr = r + 1; rr < kKeyRec; ++rr)
+                    if (heads[rr]) { nq = min(nvalid, rr * kWave + __ffsll((long long)heads[rr]) - 1); break; }
+            base[r] = atomicAdd(&a.start[key[r]], nq - q);
+        }
     }
 #pragma unroll
     for (int r = 0; r < kKeyRec; ++r) {
-        const int64_t p = (int64_t)bt.first + r * kWave + lane;
-        const int b = __shfl(base[r], seg0[r] < 0 ? 0 : seg0[r]);
-        if (p < end) a.rank[p] = b + (lane - seg0[r]);
+        const int q = r * kWave + lane;
+        const int hr = hq[r] / kWave, hl = hq[r] % kWave;
+        int b = 0;
+#pragma unroll
+        for (int rr = 0; rr <= r; ++rr) {
+            const int t = __shfl(base[rr], hl);
+            if (rr == hr) b = t;
+        }
+        if (q < nvalid) a.rank[(int64_t)bt.first + q] = b + (q - hq[r]);
     }
     nonfin = wave_reduce<false>(nonfin);
     v2 = wave_reduce<true>(v2);
