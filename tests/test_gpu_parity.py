@@ -665,9 +665,8 @@ def test_fp32_mixture_conserves(T, oracle):
 def _boundary_pairs(n_pairs, seed, D, dt):
     """Pairs placed on the edges of criteria 1 and 2 (closest approach just
     before or after the end of the step, closest distance just below or above
-    D), one pair per c-bin of a lattice of bins much wider than their reach:
-    separations at the reach bound |r|^2 = D^2 + |u|^2 dt^2 of the search's
-    screen."""
+    D), one pair per c-bin of a lattice of bins much wider than their reach,
+    so their separations lie at |r|^2 = D^2 + |u|^2 dt^2."""
     rng = np.random.default_rng(seed)
     nb = int(np.ceil(n_pairs ** (1.0 / 3.0)))
     wb = 0.01
@@ -695,10 +694,9 @@ def _boundary_pairs(n_pairs, seed, D, dt):
     return w
 
 
-def test_fp64_pairs_at_the_reach_bound(T, oracle):
-    """Pairs on the edges of both criteria, so at the search's reach screen:
-    the accepted pairs and the state stay bit-identical to the oracle's, and
-    both outcomes occur."""
+def test_fp64_pairs_on_the_edges_of_both_criteria(T, oracle):
+    """Pairs on the edges of both criteria: the accepted pairs and the state
+    stay bit-identical to the oracle's, and both outcomes occur."""
     w = _boundary_pairs(4000, seed=61, D=1e-3, dt=1e-3)
     got, gouts, _ = gpu_steps(T, w, T.FP64)
     want, routs = oracle_steps(oracle, w)
