@@ -232,3 +232,49 @@ def test_direction_depends_on_every_key_field(oracle):
     for args in [(2, 2, 3, 4, 5), (1, 3, 3, 4, 5), (1, 2, 4, 4, 5), (1, 2, 3, 5, 5), (1, 2, 3, 4, 6)]:
         assert not np.array_equal(oracle.direction(*args)[0], base)
     assert np.array_equal(oracle.direction(1, 2, 3, 4, 5)[0], base)
+
+
+# The oracle's Philox4x32-10 against an independent implementation: rocRAND's
+# (its header ships with ROCm), compiled here for the host at test time, so
+# that no third-party answer is stored in this repository.
+_ROCRAND_PROBE = r"""
+#include <cstdio>
+#include <rocrand/rocrand_philox4x32_10.h>
+struct open_engine : rocrand_device::philox4x32_10_engine {
+    using rocrand_device::philox4x32_10_engine::ten_rounds;
+};
+int main() {
+    open_engine e;
+    unsigned c0, c1, c2, c3, k0, k1;
+    while (std::scanf("%u %u %u %u %u %u", &c0, &c1, &c2, &c3, &k0, &k1) == 6) {
+        uint4 r = e.ten_rounds(uint4{c0, c1, c2, c3}, uint2{k0, k1});
+        std::printf("%u %u %u %u\n", r.x, r.y, r.z, r.w);
+    }
+    return 0;
+}
+"""
+
+
+def test_philox_matches_rocrand(oracle, tmp_path):
+    import os
+    import shutil
+    import subprocess
+    hipcc = os.environ.get("HIPCC") or shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    header = "/opt/rocm/include/rocrand/rocrand_philox4x32_10.h"
+    if not (os.path.exists(hipcc) and os.path.exists(header)):
+        pytest.skip("hipcc or the rocRAND header is not installed")
+    src, exe = tmp_path / "philox.cpp", tmp_path / "philox"
+    src.write_text(_ROCRAND_PROBE)
+    subprocess.run([hipcc, "--cuda-host-only", "-O1", "-o", str(exe), str(src)], check=True, timeout=120,
+                   capture_output=True)
+    rng = np.random.default_rng(11)
+    rows = rng.integers(0, 2 ** 32, size=(3000, 6), dtype=np.uint64)
+    rows[:6] = [[0] * 6, [2 ** 32 - 1] * 6, [0, 0, 0, 0, 2 ** 32 - 1, 2 ** 32 - 1],
+                [2 ** 32 - 1] * 4 + [0, 0], [1, 2, 3, 4, 5, 6], [7, 0, 0, 255, 1, 0]]
+    text = "\n".join(" ".join(str(int(v)) for v in r) for r in rows) + "\n"
+    res = subprocess.run([str(exe)], input=text, capture_output=True, text=True, check=True, timeout=60)
+    theirs = np.array([[int(v) for v in line.split()] for line in res.stdout.splitlines()], dtype=np.uint64)
+    assert theirs.shape == (len(rows), 4)
+    ours = np.array([oracle.philox(r[:4].astype(np.uint32), r[4:].astype(np.uint32)) for r in rows],
+                    dtype=np.uint64)
+    assert np.array_equal(ours, theirs)
