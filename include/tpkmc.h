@@ -205,7 +205,8 @@ typedef struct {
     uint32_t instance;      /* instance number (< 2^24)                      */
     uint32_t flags;         /* TPKMC_EMIT_PAIRS | TPKMC_ALLOW_REORDER |
                                TPKMC_ADAPTIVE_DT | TPKMC_PLANAR |
-                               TPKMC_RANK_TIME                               */
+                               TPKMC_RANK_TIME | TPKMC_PAIR_RANDOM (not
+                               with TPKMC_RANK_TIME)                         */
 } tpkmc_params;
 
 /* Structure-of-arrays particle state, device pointers, n entries each.
@@ -288,6 +289,19 @@ int tpkmc_run(tpkmc_handle* h, const tpkmc_particles* s,
  * particle state is not modified.  Synchronises the stream. */
 int tpkmc_autotune(tpkmc_handle* h, const tpkmc_particles* s,
                    const tpkmc_instance* inst, int32_t n_inst, void* hip_stream);
+
+/* Diagnostic: the arithmetic mix of the partner search on a state, for the
+ * roofline of the search.  counts (host, uint64[3]) receives, summed over
+ * the instances, the algorithmic unordered pair tests (TPKMC_CNT_TESTS),
+ * those with s0 = r.u < 0 (approaching) and those with s0 < 0 < s1 =
+ * s0 + |u|^2 dt (criterion 1 of Sec. 2.4).  A pair test costs 11 FLOP to
+ * decide s0 (r, u, r.u), 7 more for |u|^2 and s1 when s0 < 0, and 12 more
+ * for t_poca, the separation there and d_min^2 when both hold.  Bins the
+ * state and runs a counting build of the search (never the one tpkmc_step
+ * runs); the state and all outputs are left as they were.  Synchronises the
+ * stream. */
+int tpkmc_search_mix(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* inst, int32_t n_inst,
+                     uint64_t* counts, void* hip_stream);
 
 /* Launch shape of the partner search: one lane per `group` consecutive
  * c-bin-ordered records (1, 2 or 4) and `block` lanes per work-group (64,

@@ -93,6 +93,8 @@ def lib():
         L.ref_step.argtypes = ([_P, _P, ctypes.c_int64] + [_P] * 9 +
                                [ctypes.c_int, ctypes.c_int, _P, ctypes.c_int64, _P, _P, _P])
         L.ref_step.restype = ctypes.c_int
+        L.ref_last_phase_ms.argtypes = [_P]
+        L.ref_last_phase_ms.restype = None
         _lib = L
     return _lib
 
@@ -280,3 +282,13 @@ def step(state, grid, params, mode=MODE_BINNED, nthreads=0, pair_cap=None, momen
         raise ValueError(f"ref_step failed ({rc})")
     k = min(int(counters[CNT["pairs"]]), cap)
     return dict(pairs=pairs[:k].copy(), counters=counters, globals=glob, moments=mom)
+
+
+PHASES = ("bin", "search", "pair", "scatter", "move", "moments")
+
+
+def last_phase_ms():
+    """Wall time (ms) of each phase of the last :func:`step` in this process."""
+    out = np.zeros(len(PHASES))
+    lib().ref_last_phase_ms(_ptr(out))
+    return dict(zip(PHASES, out.tolist()))

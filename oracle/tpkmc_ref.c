@@ -24,6 +24,7 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#include <time.h>
 #ifdef _OPENMP
 #include <omp.h>
 #endif
@@ -813,6 +814,24 @@ static void nadd(nsum* a, double v)
 static double nval(const nsum* a) { return a->s + a->c; }
 
 /* ------------------------------------------------------------------------ */
+/* Wall time of the phases of the last ref_step (for the CPU baseline of the */
+/* benchmark; instrumentation only).                                         */
+/* ------------------------------------------------------------------------ */
+static double phase_ms[REF_NPHASES];
+
+static double now_ms(void)
+{
+    struct timespec t;
+    clock_gettime(CLOCK_MONOTONIC, &t);
+    return 1e3 * (double)t.tv_sec + 1e-6 * (double)t.tv_nsec;
+}
+
+void ref_last_phase_ms(double out[REF_NPHASES])
+{
+    for (int k = 0; k < REF_NPHASES; ++k) out[k] = phase_ms[k];
+}
+
+/* ------------------------------------------------------------------------ */
 /* One step                                                                  */
 /* ------------------------------------------------------------------------ */
 int ref_step(const ref_grid* g, const ref_params* p, int64_t n,
@@ -834,6 +853,9 @@ int ref_step(const ref_grid* g, const ref_params* p, int64_t n,
     p = &q;
     const double dt = p->dt;
     uint64_t cnt[8] = { 0 };
+    for (int k = 0; k < REF_NPHASES; ++k) phase_ms[k] = 0.0;
+    double t_mark = now_ms(), t_now;
+#define REF_PHASE_END(k) (t_now = now_ms(), phase_ms[k] += t_now - t_mark, t_mark = t_now)
 
     size_t nn = (size_t)(n > 0 ? n : 1);
     int64_t* best = (int64_t*)malloc(sizeof(int64_t) * nn);
@@ -856,6 +878,7 @@ int ref_step(const ref_grid* g, const ref_params* p, int64_t n,
 
     /* 1. Sort into c-bins. */
     if (make_bins(&G, g, &V, &Bn)) { rc = -2; goto done; }
+    REF_PHASE_END(REF_PHASE_BIN);
     if (G.pair_random) {
         /* 2'-3'. Random partners inside each c-bin, each pair its own
          * acceptance draw (REF_PAIR_RANDOM). */
@@ -873,6 +896,7 @@ int ref_step(const ref_grid* g, const ref_params* p, int64_t n,
                 partner[j] = i;
             }
         }
+        REF_PHASE_END(REF_PHASE_SEARCH);
         goto scatter;
     }
     for (int64_t c = 0; c < G.C; ++c) {
@@ -886,6 +910,7 @@ int ref_step(const ref_grid* g, const ref_params* p, int64_t n,
 
     /* 2. Closest candidate of every particle. */
     cnt[REF_CNT_CAND] = search_all(&G, dt, &V, &Bn, mode, nthreads, best, best_d2);
+    REF_PHASE_END(REF_PHASE_SEARCH);
     for (int64_t i = 0; i < n; ++i)
         if (best[i] >= 0) cnt[REF_CNT_HAVE_BEST]++;
 
@@ -894,6 +919,8 @@ int ref_step(const ref_grid* g, const ref_params* p, int64_t n,
         int64_t j = best[i];
         partner[i] = (j >= 0 && best[j] == i) ? j : -1;
     }
+
+    REF_PHASE_END(REF_PHASE_PAIR);
 
     /* 4. Scattering of every accepted pair, visited once from its lower id. */
 scatter:;
@@ -911,6 +938,8 @@ scatter:;
     }
     cnt[REF_CNT_PAIRS] = (uint64_t)npairs;
 
+    REF_PHASE_END(REF_PHASE_SCATTER);
+
     /* 5. Positions: split at t_poca for colliders, free streaming otherwise;
      * then the walls. */
     for (int64_t i = 0; i < n; ++i) {
@@ -922,6 +951,8 @@ scatter:;
         vx[i] = v[0]; vy[i] = v[1]; vz[i] = v[2];
         if (gone) { alive[i] = 0; cnt[REF_CNT_ABSORBED]++; }
     }
+
+    REF_PHASE_END(REF_PHASE_MOVE);
 
     /* 6. Moments of the post-step state per o-bin, and global sums. */
     nsum gp[3] = { { 0, 0 }, { 0, 0 }, { 0, 0 } }, ge = { 0, 0 }, gv = { 0, 0 }, gm = { 0, 0 };
@@ -986,6 +1017,8 @@ scatter:;
         globals[REF_G_DT] = dt;
     }
     if (counters) memcpy(counters, cnt, sizeof(cnt));
+    REF_PHASE_END(REF_PHASE_MOMENTS);
+#undef REF_PHASE_END
 
 done:
     free_bins(&Bn);

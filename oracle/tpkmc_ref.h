@@ -102,6 +102,13 @@ enum { REF_RANK_TIME = 4 };
  * counter ending in 255 belongs to the key and acceptance draws alone. */
 enum { REF_PAIR_RANDOM = 8 };
 
+/* Phases of ref_step whose wall times ref_last_phase_ms reports, in ms, for
+ * the last ref_step of the process (instrumentation for the benchmark's CPU
+ * baseline; the random-partner mode books its pairing under SEARCH). */
+enum { REF_PHASE_BIN = 0, REF_PHASE_SEARCH, REF_PHASE_PAIR, REF_PHASE_SCATTER, REF_PHASE_MOVE,
+       REF_PHASE_MOMENTS, REF_NPHASES };
+void ref_last_phase_ms(double out[REF_NPHASES]);
+
 /* Counters written by ref_step (uint64[8]). */
 enum {
     REF_CNT_ALIVE = 0,      /* alive particles after the step                 */

@@ -266,6 +266,20 @@ __global__ void __launch_bounds__(256) k_moments_final(const Inst<real>* inst, d
 }  // namespace
 
 // ---------------------------------------------------------------- handle
+// Device scratch of one step: owned by a handle (tpkmc_create), or carved
+// out of the static scratch array by the allocation-free entry point.
+struct Buffers {
+    int32_t *rank, *start, *tiles, *src, *best, *perm;
+    void *rec, *rmass, *inst;
+    Blk* blk;
+    Chunk* chunks;
+    unsigned long long* bkey;
+    double *gpart, *cpart, *shift;
+    unsigned long long* pair_count;
+    uint32_t* status;
+    unsigned long long* mix;  // counters of tpkmc_search_mix (handles only)
+};
+
 struct ProfRec {
     int phase;
     hipEvent_t a, b;
@@ -275,19 +289,8 @@ struct tpkmc_handle {
     int device = 0, precision = TPKMC_FP64;
     int64_t max_n = 0, max_cells = 0, max_obins = 0, max_blk = 0;
     int32_t max_inst = 0;
-    int32_t *perm = nullptr, *rank = nullptr, *start = nullptr, *tiles = nullptr, *src = nullptr, *best = nullptr;
-    void* rec = nullptr;
-    void* rmass = nullptr;
-    void* inst = nullptr;
-    Blk* blk = nullptr;
-    Chunk* chunks = nullptr;
-    unsigned long long* bkey = nullptr;
-    double* gpart = nullptr;
-    double* cpart = nullptr;
     int64_t max_chunks = 0;
-    double* shift = nullptr;
-    unsigned long long* pair_count = nullptr;
-    uint32_t* status = nullptr;
+    Buffers b{};  // device scratch, allocated once in tpkmc_create
     hipStream_t last_stream = nullptr;
     hipStream_t own_stream = nullptr;
     int search_block = kWave;
@@ -329,15 +332,100 @@ struct Plan {
 
 bool bad_ptr(const void* p) { return p == nullptr; }
 
+bool bad_state(const tpkmc_particles* s) {
+    return s->n > 0 && (bad_ptr(s->x) || bad_ptr(s->y) || bad_ptr(s->z) || bad_ptr(s->vx) || bad_ptr(s->vy) ||
+                        bad_ptr(s->vz) || bad_ptr(s->id));
+}
+
+// Validates one instance and fills its device descriptor, except the
+// offsets into the c-bin, o-bin, block and chunk tables, which the caller
+// sets.  C and B: its c-bins and o-bins.
+template <typename real>
+int fill_inst(const tpkmc_particles* s, const tpkmc_instance& q, Inst<real>& d, int64_t& C, int64_t& B) {
+    const tpkmc_grid& g = q.grid;
+    const tpkmc_params& p = q.params;
+    if (q.offset < 0 || q.count < 0 || q.offset + q.count > s->n) return TPKMC_EINVAL;
+    if (!(std::isfinite(p.sigma) && p.sigma >= 0.0)) return TPKMC_EINVAL;
+    if (!(std::isfinite(p.mass) && p.mass > 0.0)) return TPKMC_EINVAL;
+    if (!(std::isfinite(p.dt) && p.dt > 0.0)) return TPKMC_EINVAL;
+    if (p.instance >= (1u << 24)) return TPKMC_EINVAL;
+    if (p.flags & ~(uint32_t)(TPKMC_EMIT_PAIRS | TPKMC_ALLOW_REORDER | TPKMC_ADAPTIVE_DT | TPKMC_PLANAR |
+                              TPKMC_RANK_TIME | TPKMC_PAIR_RANDOM))
+        return TPKMC_EINVAL;
+    if ((p.flags & TPKMC_RANK_TIME) && (p.flags & TPKMC_PAIR_RANDOM)) return TPKMC_EINVAL;
+    const bool planar = (p.flags & TPKMC_PLANAR) != 0;
+    if (planar && g.ncell[2] != 1) return TPKMC_EINVAL;
+    std::memset(&d, 0, sizeof(d));
+    C = 1;
+    B = 1;
+    double dx = 0.0, wd[3];
+    for (int a = 0; a < 3; ++a) {
+        if (g.ncell[a] < 1 || g.nobin[a] < 1) return TPKMC_EINVAL;
+        if (g.ncell[a] > (1 << 24) || g.nobin[a] > (1 << 24)) return TPKMC_EINVAL;
+        if (!(std::isfinite(g.lo[a]) && std::isfinite(g.hi[a]) && g.hi[a] > g.lo[a])) return TPKMC_EINVAL;
+        if (g.bc[a] < TPKMC_BC_REFLECT || g.bc[a] > TPKMC_BC_ABSORB) return TPKMC_EINVAL;
+        if (g.bc[a] == TPKMC_BC_ABSORB && s->alive == nullptr) return TPKMC_EINVAL;
+        C *= g.ncell[a];
+        B *= g.nobin[a];
+        // Derived grid quantities, in double, in the order of the reference.
+        const double L = g.hi[a] - g.lo[a];
+        d.n[a] = g.ncell[a];
+        d.no[a] = g.nobin[a];
+        d.bc[a] = g.bc[a];
+        d.lo[a] = (real)g.lo[a];
+        d.hi[a] = (real)g.hi[a];
+        d.L[a] = (real)L;
+        d.halfL[a] = (real)(0.5 * L);
+        d.w[a] = (real)(L / (double)g.ncell[a]);
+        wd[a] = L / (double)g.ncell[a];
+        if (g.ncell[a] > 1 && (dx == 0.0 || L / (double)g.ncell[a] < dx)) dx = L / (double)g.ncell[a];
+        d.inv_w[a] = (real)((double)g.ncell[a] / L);
+        d.inv_wo[a] = (real)((double)g.nobin[a] / L);
+    }
+    if (C + 1 > (int64_t)1 << 30 || B > (int64_t)1 << 30) return TPKMC_EINVAL;
+    d.off = q.offset;
+    d.cnt = q.count;
+    d.C = (int32_t)C;
+    d.seed_lo = (uint32_t)p.seed;
+    d.seed_hi = (uint32_t)(p.seed >> 32);
+    d.step_lo = (uint32_t)p.step;
+    d.instance = p.instance;
+    d.flags = p.flags | (s->mass ? kHasMass : 0u);
+    d.dt = (real)p.dt;
+    // Largest accepted d_min^2: sigma = pi D^2 in space, sigma = 2 D in
+    // the plane (same expressions as the reference).
+    const double Dp = 0.5 * p.sigma;
+    d.D2 = planar ? (real)(Dp * Dp) : (real)(p.sigma / M_PI);
+    d.mass = (real)p.mass;
+    d.mass_d = p.mass;
+    d.dt_d = p.dt;
+    d.dt_cap = p.dt;
+    d.dx_d = dx;
+    // Random partners: the cross section and the c-bin volume (an area
+    // in the plane), in the reference's order.
+    d.sigma_d = p.sigma;
+    d.cellvol_d = planar ? wd[0] * wd[1] : (wd[0] * wd[1]) * wd[2];
+    // Band height of the c-bin order: the largest power of two of rows
+    // whose band plane (rows x n_x c-bins of records) stays within
+    // kBandBytes, so that one XCD's L2 holds the plane its neighbourhood
+    // walk reads twice.  Planar and one-row grids keep a single band.
+    d.band_log2 = 30;
+    if (g.ncell[2] > 1 && g.ncell[1] > 1 && q.count > 0) {
+        const double row_bytes = (double)g.ncell[0] * ((double)q.count / (double)C) * 8.0 * sizeof(real);
+        int h = 0;
+        while (h < 30 && (double)(2 << h) * row_bytes <= (double)kBandBytes) ++h;
+        if ((1 << h) < g.ncell[1]) d.band_log2 = h;
+    }
+    return TPKMC_OK;
+}
+
 template <typename real>
 int make_plan(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* in, int n_inst, Plan& P) {
     if (!s || !in || n_inst < 1) return TPKMC_EINVAL;
     if (n_inst > h->max_inst) return TPKMC_ECAPACITY;
     if (s->n < 0) return TPKMC_EINVAL;
     if (s->n > h->max_n) return TPKMC_ECAPACITY;
-    if (s->n > 0 && (bad_ptr(s->x) || bad_ptr(s->y) || bad_ptr(s->z) || bad_ptr(s->vx) || bad_ptr(s->vy) ||
-                     bad_ptr(s->vz) || bad_ptr(s->id)))
-        return TPKMC_EINVAL;
+    if (bad_state(s)) return TPKMC_EINVAL;
     std::vector<std::pair<int64_t, int64_t>> spans;
     std::vector<Inst<real>> I(n_inst);
     P.blk.clear();
@@ -351,89 +439,19 @@ int make_plan(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* i
     P.max_nob = 0;
     for (int k = 0; k < n_inst; ++k) {
         const tpkmc_instance& q = in[k];
-        const tpkmc_grid& g = q.grid;
-        const tpkmc_params& p = q.params;
-        if (q.offset < 0 || q.count < 0 || q.offset + q.count > s->n) return TPKMC_EINVAL;
-        spans.push_back({q.offset, q.count});
-        if (!(std::isfinite(p.sigma) && p.sigma >= 0.0)) return TPKMC_EINVAL;
-        if (!(std::isfinite(p.mass) && p.mass > 0.0)) return TPKMC_EINVAL;
-        if (!(std::isfinite(p.dt) && p.dt > 0.0)) return TPKMC_EINVAL;
-        if (p.instance >= (1u << 24)) return TPKMC_EINVAL;
-        if (p.flags & ~(uint32_t)(TPKMC_EMIT_PAIRS | TPKMC_ALLOW_REORDER | TPKMC_ADAPTIVE_DT | TPKMC_PLANAR |
-                                  TPKMC_RANK_TIME | TPKMC_PAIR_RANDOM))
-            return TPKMC_EINVAL;
-        if ((p.flags & TPKMC_RANK_TIME) && (p.flags & TPKMC_PAIR_RANDOM)) return TPKMC_EINVAL;
-        if (p.flags & TPKMC_PAIR_RANDOM) P.any_random = true;
-        else P.any_search = true;
-        const bool planar = (p.flags & TPKMC_PLANAR) != 0;
-        if (planar && g.ncell[2] != 1) return TPKMC_EINVAL;
         Inst<real>& d = I[k];
-        std::memset(&d, 0, sizeof(d));
-        int64_t C = 1, B = 1;
-        double dx = 0.0, wd[3];
-        for (int a = 0; a < 3; ++a) {
-            if (g.ncell[a] < 1 || g.nobin[a] < 1) return TPKMC_EINVAL;
-            if (g.ncell[a] > (1 << 24) || g.nobin[a] > (1 << 24)) return TPKMC_EINVAL;
-            if (!(std::isfinite(g.lo[a]) && std::isfinite(g.hi[a]) && g.hi[a] > g.lo[a])) return TPKMC_EINVAL;
-            if (g.bc[a] < TPKMC_BC_REFLECT || g.bc[a] > TPKMC_BC_ABSORB) return TPKMC_EINVAL;
-            if (g.bc[a] == TPKMC_BC_ABSORB && s->alive == nullptr) return TPKMC_EINVAL;
-            C *= g.ncell[a];
-            B *= g.nobin[a];
-            // Derived grid quantities, in double, in the order of the reference.
-            const double L = g.hi[a] - g.lo[a];
-            d.n[a] = g.ncell[a];
-            d.no[a] = g.nobin[a];
-            d.bc[a] = g.bc[a];
-            d.lo[a] = (real)g.lo[a];
-            d.hi[a] = (real)g.hi[a];
-            d.L[a] = (real)L;
-            d.halfL[a] = (real)(0.5 * L);
-            d.w[a] = (real)(L / (double)g.ncell[a]);
-            wd[a] = L / (double)g.ncell[a];
-            if (g.ncell[a] > 1 && (dx == 0.0 || L / (double)g.ncell[a] < dx)) dx = L / (double)g.ncell[a];
-            d.inv_w[a] = (real)((double)g.ncell[a] / L);
-            d.inv_wo[a] = (real)((double)g.nobin[a] / L);
-        }
-        if (C + 1 > (int64_t)1 << 30 || B > (int64_t)1 << 30) return TPKMC_EINVAL;
-        d.off = q.offset;
-        d.cnt = q.count;
-        d.C = (int32_t)C;
+        int64_t C, B;
+        const int rc = fill_inst<real>(s, q, d, C, B);
+        if (rc) return rc;
+        spans.push_back({q.offset, q.count});
+        if (q.params.flags & TPKMC_PAIR_RANDOM) P.any_random = true;
+        else P.any_search = true;
+        if (q.params.flags & TPKMC_ADAPTIVE_DT) P.adaptive = true;
         d.cell_off = P.ncell_tot;
         d.obin_off = P.nob_tot;
         P.ncell_tot += C + 1;
         P.nob_tot += B;
         P.max_nob = std::max(P.max_nob, B);
-        d.seed_lo = (uint32_t)p.seed;
-        d.seed_hi = (uint32_t)(p.seed >> 32);
-        d.step_lo = (uint32_t)p.step;
-        d.instance = p.instance;
-        d.flags = p.flags | (s->mass ? kHasMass : 0u);
-        d.dt = (real)p.dt;
-        // Largest accepted d_min^2: sigma = pi D^2 in space, sigma = 2 D in
-        // the plane (same expressions as the reference).
-        const double Dp = 0.5 * p.sigma;
-        d.D2 = planar ? (real)(Dp * Dp) : (real)(p.sigma / M_PI);
-        d.mass = (real)p.mass;
-        d.mass_d = p.mass;
-        d.dt_d = p.dt;
-        d.dt_cap = p.dt;
-        d.dx_d = dx;
-        // Random partners: the cross section and the c-bin volume (an area
-        // in the plane), in the reference's order.
-        d.sigma_d = p.sigma;
-        d.cellvol_d = planar ? wd[0] * wd[1] : (wd[0] * wd[1]) * wd[2];
-        // Band height of the c-bin order: the largest power of two of rows
-        // whose band plane (rows x n_x c-bins of records) stays within
-        // kBandBytes, so that one XCD's L2 holds the plane its neighbourhood
-        // walk reads twice.  Planar and one-row grids keep a single band.
-        d.band_log2 = 30;
-        if (g.ncell[2] > 1 && g.ncell[1] > 1 && q.count > 0) {
-            const double row_bytes = (double)g.ncell[0] * ((double)q.count / (double)C) * 8.0 * sizeof(real);
-            int h = 0;
-            while (h < 30 && (double)(2 << h) * row_bytes <= (double)kBandBytes) ++h;
-            if ((1 << h) < g.ncell[1]) d.band_log2 = h;
-        }
-        if (p.flags & TPKMC_ADAPTIVE_DT) P.adaptive = true;
         d.blk0 = (int32_t)P.blk.size();
         for (int64_t o = 0; o < q.count; o += kBlock) P.blk.push_back({k, (int32_t)(q.offset + o)});
         d.nblk = (int32_t)P.blk.size() - d.blk0;
@@ -489,60 +507,77 @@ struct PhaseScope {
 };
 
 template <typename real>
-StepArgs<real> make_args(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_outputs* o, const Plan& P) {
+StepArgs<real> make_args(const Buffers& B, const tpkmc_particles* s, const tpkmc_outputs* o, int nblk) {
     StepArgs<real> a{};
     a.x = (real*)s->x; a.y = (real*)s->y; a.z = (real*)s->z;
     a.vx = (real*)s->vx; a.vy = (real*)s->vy; a.vz = (real*)s->vz;
     a.id = s->id;
     a.alive = s->alive;
-    a.inst = (const Inst<real>*)h->inst;
-    a.blk = h->blk;
-    a.nblk = P.nblk;
-    a.rank = h->rank;
-    a.start = h->start;
-    a.rec = (real*)h->rec;
+    a.inst = (const Inst<real>*)B.inst;
+    a.blk = B.blk;
+    a.nblk = nblk;
+    a.rank = B.rank;
+    a.start = B.start;
+    a.rec = (real*)B.rec;
     a.mass = (real*)s->mass;
-    a.rmass = (real*)h->rmass;
-    a.src = h->src;
-    a.best = h->best;
-    a.perm = h->perm;
-    a.bkey = h->bkey;
-    a.gpart = h->gpart;
-    a.shift = h->shift;
+    a.rmass = (real*)B.rmass;
+    a.src = B.src;
+    a.best = B.best;
+    a.perm = B.perm;
+    a.bkey = B.bkey;
+    a.gpart = B.gpart;
+    a.shift = B.shift;
     a.pairs = o ? o->pairs : nullptr;
     a.pair_cap = (o && o->pairs) ? o->pair_cap : 0;
-    a.pair_count = h->pair_count;
+    a.pair_count = B.pair_count;
+    a.mix = B.mix;
     a.moments = o ? o->moments : nullptr;
     return a;
 }
 
-void enqueue_scan(tpkmc_handle* h, int64_t n, hipStream_t s) {
-    const int64_t tiles = (n + kScanTile - 1) / kScanTile;
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)tiles), dim3(kScanBlock), 0, s, h->start, n, h->tiles);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, h->tiles, tiles);
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)tiles), dim3(kScanBlock), 0, s, h->start, n, h->tiles);
+int64_t scan_tiles(int64_t n) { return (n + kScanTile - 1) / kScanTile; }
+
+void enqueue_scan(const Buffers& B, int64_t n, hipStream_t s) {
+    const int64_t tiles = scan_tiles(n);
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)tiles), dim3(kScanBlock), 0, s, B.start, n, B.tiles);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, B.tiles, tiles);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)tiles), dim3(kScanBlock), 0, s, B.start, n, B.tiles);
 }
 
-// Everything of one step after the tables are on the device.
+// Shape of one launch sequence: what enqueue_step needs of a Plan.
+struct Shape {
+    int n_inst, nblk, nchunk;
+    int64_t ncell_tot, nob_tot, max_nob;
+    bool adaptive, any_search, any_random;
+};
+
+Shape shape_of(const Plan& P) {
+    return Shape{P.n_inst, P.nblk, (int)P.chunks.size(), P.ncell_tot, P.nob_tot, P.max_nob,
+                 P.adaptive, P.any_search, P.any_random};
+}
+
+// Everything of one step after the tables are on the device.  `h` only
+// records phase timings (null: none).
 template <typename real>
-void enqueue_step(tpkmc_handle* h, const StepArgs<real>& a, const tpkmc_outputs* o, const Plan& P,
-                  hipStream_t s, bool prof, int advance_step) {
+void enqueue_step(tpkmc_handle* h, const Buffers& B, const StepArgs<real>& a, const tpkmc_outputs* o,
+                  const Shape& P, int search_block, int search_group, hipStream_t s, bool prof,
+                  int advance_step) {
     const int64_t nmom = (o && o->moments) ? P.nob_tot * TPKMC_MOMENT_STRIDE : 0;
     {
         PhaseScope ps(h, PH_CLEAR, s, prof);
         const int64_t work = std::max<int64_t>(P.ncell_tot + 1, nmom);
         const int64_t grid = std::min<int64_t>((work + 255) / 256, 4096);
-        hipLaunchKernelGGL(k_clear, dim3((unsigned)std::max<int64_t>(grid, 1)), dim3(256), 0, s, h->start,
-                           P.ncell_tot + 1, nmom ? o->moments : nullptr, nmom, h->pair_count);
+        hipLaunchKernelGGL(k_clear, dim3((unsigned)std::max<int64_t>(grid, 1)), dim3(256), 0, s, B.start,
+                           P.ncell_tot + 1, nmom ? o->moments : nullptr, nmom, B.pair_count);
     }
     if (P.nblk > 0) {
         PhaseScope ps(h, PH_KEY, s, prof);
         launch_key<real>(a, s);
-        if (P.adaptive) launch_adapt_dt<real>((Inst<real>*)h->inst, h->gpart, P.n_inst, s);
+        if (P.adaptive) launch_adapt_dt<real>((Inst<real>*)B.inst, B.gpart, P.n_inst, s);
     }
     {
         PhaseScope ps(h, PH_SCAN, s, prof);
-        enqueue_scan(h, P.ncell_tot + 1, s);
+        enqueue_scan(B, P.ncell_tot + 1, s);
     }
     if (P.nblk > 0) {
         {
@@ -551,7 +586,7 @@ void enqueue_step(tpkmc_handle* h, const StepArgs<real>& a, const tpkmc_outputs*
         }
         {
             PhaseScope ps(h, PH_SEARCH, s, prof);
-            if (P.any_search) launch_search<real>(a, h->search_block, h->search_group, s);
+            if (P.any_search) launch_search<real>(a, search_block, search_group, s);
             if (P.any_random) launch_random_pairs<real>(a, s);
         }
         {
@@ -561,16 +596,16 @@ void enqueue_step(tpkmc_handle* h, const StepArgs<real>& a, const tpkmc_outputs*
     }
     {
         PhaseScope ps(h, PH_FINAL, s, prof);
-        if (!P.chunks.empty())
-            hipLaunchKernelGGL(k_reduce_chunks, dim3((unsigned)P.chunks.size()), dim3(256), 0, s,
-                               (const Chunk*)h->chunks, (const double*)h->gpart, h->cpart);
-        hipLaunchKernelGGL(k_finalize<real>, dim3(P.n_inst), dim3(256), 0, s, (Inst<real>*)h->inst, h->cpart,
-                           o ? o->counters : nullptr, o ? o->globals : nullptr, h->status, h->pair_count,
+        if (P.nchunk > 0)
+            hipLaunchKernelGGL(k_reduce_chunks, dim3((unsigned)P.nchunk), dim3(256), 0, s,
+                               (const Chunk*)B.chunks, (const double*)B.gpart, B.cpart);
+        hipLaunchKernelGGL(k_finalize<real>, dim3(P.n_inst), dim3(256), 0, s, (Inst<real>*)B.inst, B.cpart,
+                           o ? o->counters : nullptr, o ? o->globals : nullptr, B.status, B.pair_count,
                            a.pair_cap, advance_step);
         if (nmom) {
             const unsigned gx = (unsigned)((P.max_nob + 255) / 256);
             hipLaunchKernelGGL(k_moments_final<real>, dim3(gx, P.n_inst), dim3(256), 0, s,
-                               (const Inst<real>*)h->inst, o->moments, h->shift);
+                               (const Inst<real>*)B.inst, o->moments, B.shift);
         }
     }
 }
@@ -584,10 +619,10 @@ int upload(tpkmc_handle* h, const Plan& P, hipStream_t s) {
     std::memcpy(h->stage[k], P.inst_bytes.data(), ib);
     if (bb) std::memcpy(h->stage[k] + ib, P.blk.data(), bb);
     if (cb) std::memcpy(h->stage[k] + ib + bb, P.chunks.data(), cb);
-    if (hipMemcpyAsync(h->inst, h->stage[k], ib, hipMemcpyHostToDevice, s) != hipSuccess) return TPKMC_EHIP;
-    if (bb && hipMemcpyAsync(h->blk, h->stage[k] + ib, bb, hipMemcpyHostToDevice, s) != hipSuccess)
+    if (hipMemcpyAsync(h->b.inst, h->stage[k], ib, hipMemcpyHostToDevice, s) != hipSuccess) return TPKMC_EHIP;
+    if (bb && hipMemcpyAsync(h->b.blk, h->stage[k] + ib, bb, hipMemcpyHostToDevice, s) != hipSuccess)
         return TPKMC_EHIP;
-    if (cb && hipMemcpyAsync(h->chunks, h->stage[k] + ib + bb, cb, hipMemcpyHostToDevice, s) != hipSuccess)
+    if (cb && hipMemcpyAsync(h->b.chunks, h->stage[k] + ib + bb, cb, hipMemcpyHostToDevice, s) != hipSuccess)
         return TPKMC_EHIP;
     if (hipEventRecord(h->stage_ev[k], s) != hipSuccess) return TPKMC_EHIP;
     h->stage_used[k] = true;
@@ -603,8 +638,8 @@ int step_impl(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* i
     if ((rc = check_outputs(o))) return rc;
     if (hipSetDevice(h->device) != hipSuccess) return TPKMC_EHIP;
     if ((rc = upload(h, P, st))) return rc;
-    StepArgs<real> a = make_args<real>(h, s, o, P);
-    enqueue_step<real>(h, a, o, P, st, h->profiling, 0);
+    StepArgs<real> a = make_args<real>(h->b, s, o, P.nblk);
+    enqueue_step<real>(h, h->b, a, o, shape_of(P), h->search_block, h->search_group, st, h->profiling, 0);
     h->last_stream = st;
     return hipGetLastError() == hipSuccess ? TPKMC_OK : TPKMC_EHIP;
 }
@@ -628,7 +663,7 @@ int run_impl(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* in
         hipStreamWaitEvent(st, ev, 0);
     }
     if ((rc = upload(h, P, st))) return rc;
-    StepArgs<real> a = make_args<real>(h, s, o, P);
+    StepArgs<real> a = make_args<real>(h->b, s, o, P.nblk);
     if (h->gexec) {
         hipStreamSynchronize(h->last_stream ? h->last_stream : st);
         hipGraphExecDestroy(h->gexec);
@@ -636,7 +671,7 @@ int run_impl(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* in
     }
     hipGraph_t graph = nullptr;
     if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return TPKMC_EHIP;
-    enqueue_step<real>(h, a, o, P, st, false, 1);
+    enqueue_step<real>(nullptr, h->b, a, o, shape_of(P), h->search_block, h->search_group, st, false, 1);
     if (hipStreamEndCapture(st, &graph) != hipSuccess || !graph) return TPKMC_EHIP;
     if (hipGraphInstantiate(&h->gexec, graph, nullptr, nullptr, 0) != hipSuccess) {
         hipGraphDestroy(graph);
@@ -663,13 +698,13 @@ int tune_impl(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* i
     if (hipSetDevice(h->device) != hipSuccess) return TPKMC_EHIP;
     if ((rc = upload(h, P, st))) return rc;
     tpkmc_outputs none{};
-    StepArgs<real> a = make_args<real>(h, s, &none, P);
+    StepArgs<real> a = make_args<real>(h->b, s, &none, P.nblk);
     // Bin once (clear, key, prefix, scatter); then time only the search.
-    hipLaunchKernelGGL(k_clear, dim3(1024), dim3(256), 0, st, h->start, P.ncell_tot + 1, (double*)nullptr,
-                       (int64_t)0, h->pair_count);
+    hipLaunchKernelGGL(k_clear, dim3(1024), dim3(256), 0, st, h->b.start, P.ncell_tot + 1, (double*)nullptr,
+                       (int64_t)0, h->b.pair_count);
     launch_key<real>(a, st);
-    if (P.adaptive) launch_adapt_dt<real>((Inst<real>*)h->inst, h->gpart, P.n_inst, st);
-    enqueue_scan(h, P.ncell_tot + 1, st);
+    if (P.adaptive) launch_adapt_dt<real>((Inst<real>*)h->b.inst, h->b.gpart, P.n_inst, st);
+    enqueue_scan(h->b, P.ncell_tot + 1, st);
     launch_scatter<real>(a, st);
     hipEvent_t e0, e1;
     hipEventCreate(&e0);
@@ -708,6 +743,37 @@ int tune_impl(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* i
     return hipGetLastError() == hipSuccess ? TPKMC_OK : TPKMC_EHIP;
 }
 
+// The search's arithmetic mix on a state: bins it (clear, key, prefix,
+// scatter) and runs the counting build of the search, which leaves the state
+// and the step's outputs untouched.
+template <typename real>
+int mix_impl(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* in, int n_inst, uint64_t* counts,
+             hipStream_t st) {
+    if (!counts) return TPKMC_EINVAL;
+    Plan P;
+    int rc = make_plan<real>(h, s, in, n_inst, P);
+    if (rc) return rc;
+    counts[0] = counts[1] = counts[2] = 0;
+    if (P.nblk == 0) return TPKMC_OK;
+    if (hipSetDevice(h->device) != hipSuccess) return TPKMC_EHIP;
+    if ((rc = upload(h, P, st))) return rc;
+    tpkmc_outputs none{};
+    StepArgs<real> a = make_args<real>(h->b, s, &none, P.nblk);
+    hipLaunchKernelGGL(k_clear, dim3(1024), dim3(256), 0, st, h->b.start, P.ncell_tot + 1, (double*)nullptr,
+                       (int64_t)0, h->b.pair_count);
+    launch_key<real>(a, st);
+    if (P.adaptive) launch_adapt_dt<real>((Inst<real>*)h->b.inst, h->b.gpart, P.n_inst, st);
+    enqueue_scan(h->b, P.ncell_tot + 1, st);
+    launch_scatter<real>(a, st);
+    if (hipMemsetAsync(h->b.mix, 0, 3 * sizeof(unsigned long long), st) != hipSuccess) return TPKMC_EHIP;
+    launch_search_mix<real>(a, h->search_block, st);
+    if (hipMemcpyAsync(counts, h->b.mix, 3 * sizeof(uint64_t), hipMemcpyDeviceToHost, st) != hipSuccess)
+        return TPKMC_EHIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return TPKMC_EHIP;
+    h->last_stream = st;
+    return hipGetLastError() == hipSuccess ? TPKMC_OK : TPKMC_EHIP;
+}
+
 template <typename T>
 int dalloc(T** p, int64_t count) {
     *p = nullptr;
@@ -720,9 +786,9 @@ void free_all(tpkmc_handle* h) {
         if (h->stage[k]) hipHostFree(h->stage[k]);
         if (h->stage_ev[k]) hipEventDestroy(h->stage_ev[k]);
     }
-    hipFree(h->rank); hipFree(h->start); hipFree(h->tiles);
-    hipFree(h->src); hipFree(h->best); hipFree(h->perm); hipFree(h->rec); hipFree(h->rmass); hipFree(h->inst);
-    hipFree(h->blk); hipFree(h->chunks); hipFree(h->bkey); hipFree(h->cpart); hipFree(h->gpart); hipFree(h->shift); hipFree(h->pair_count); hipFree(h->status);
+    hipFree(h->b.rank); hipFree(h->b.start); hipFree(h->b.tiles);
+    hipFree(h->b.src); hipFree(h->b.best); hipFree(h->b.perm); hipFree(h->b.rec); hipFree(h->b.rmass); hipFree(h->b.inst);
+    hipFree(h->b.blk); hipFree(h->b.chunks); hipFree(h->b.bkey); hipFree(h->b.cpart); hipFree(h->b.gpart); hipFree(h->b.shift); hipFree(h->b.pair_count); hipFree(h->b.status); hipFree(h->b.mix);
 }
 
 }  // namespace
@@ -771,23 +837,24 @@ int tpkmc_create(const tpkmc_config* cfg, tpkmc_handle** out) {
     const size_t inst_sz = cfg->precision == TPKMC_FP64 ? sizeof(Inst<double>) : sizeof(Inst<float>);
     const int64_t tiles = (cfg->max_cells + 1 + kScanTile - 1) / kScanTile + 1;
     int bad = 0;
-    bad |= dalloc(&h->rank, h->max_n);
-    bad |= dalloc(&h->start, h->max_cells + 1);
-    bad |= dalloc(&h->tiles, tiles);
-    bad |= dalloc(&h->src, h->max_n);
-    bad |= dalloc(&h->best, h->max_n);
-    bad |= dalloc(&h->perm, h->max_n);
-    bad |= hipMalloc(&h->rec, rs * 8 * (size_t)std::max<int64_t>(h->max_n, 1)) != hipSuccess;
-    bad |= hipMalloc(&h->rmass, rs * (size_t)std::max<int64_t>(h->max_n, 1)) != hipSuccess;
-    bad |= hipMalloc(&h->inst, inst_sz * (size_t)h->max_inst) != hipSuccess;
-    bad |= dalloc(&h->blk, h->max_blk);
-    bad |= dalloc(&h->gpart, h->max_blk * kGPart);
-    bad |= dalloc(&h->chunks, h->max_chunks);
-    bad |= dalloc(&h->cpart, h->max_chunks * kGPart);
-    if (cfg->precision == TPKMC_FP32) bad |= dalloc(&h->bkey, h->max_n);
-    bad |= dalloc(&h->shift, 3 * std::max<int64_t>(h->max_obins, 1));
-    bad |= dalloc(&h->pair_count, 1);
-    bad |= dalloc(&h->status, 1);
+    bad |= dalloc(&h->b.rank, h->max_n);
+    bad |= dalloc(&h->b.start, h->max_cells + 1);
+    bad |= dalloc(&h->b.tiles, tiles);
+    bad |= dalloc(&h->b.src, h->max_n);
+    bad |= dalloc(&h->b.best, h->max_n);
+    bad |= dalloc(&h->b.perm, h->max_n);
+    bad |= hipMalloc(&h->b.rec, rs * 8 * (size_t)std::max<int64_t>(h->max_n, 1)) != hipSuccess;
+    bad |= hipMalloc(&h->b.rmass, rs * (size_t)std::max<int64_t>(h->max_n, 1)) != hipSuccess;
+    bad |= hipMalloc(&h->b.inst, inst_sz * (size_t)h->max_inst) != hipSuccess;
+    bad |= dalloc(&h->b.blk, h->max_blk);
+    bad |= dalloc(&h->b.gpart, h->max_blk * kGPart);
+    bad |= dalloc(&h->b.chunks, h->max_chunks);
+    bad |= dalloc(&h->b.cpart, h->max_chunks * kGPart);
+    if (cfg->precision == TPKMC_FP32) bad |= dalloc(&h->b.bkey, h->max_n);
+    bad |= dalloc(&h->b.shift, 3 * std::max<int64_t>(h->max_obins, 1));
+    bad |= dalloc(&h->b.pair_count, 1);
+    bad |= dalloc(&h->b.mix, 3);
+    bad |= dalloc(&h->b.status, 1);
     h->stage_bytes = inst_sz * (size_t)h->max_inst + sizeof(Blk) * (size_t)h->max_blk +
                      sizeof(Chunk) * (size_t)h->max_chunks;
     for (int k = 0; k < tpkmc_handle::kRing && !bad; ++k) {
@@ -795,9 +862,9 @@ int tpkmc_create(const tpkmc_config* cfg, tpkmc_handle** out) {
         bad |= hipEventCreateWithFlags(&h->stage_ev[k], hipEventDisableTiming) != hipSuccess;
     }
     if (!bad) {
-        bad |= hipMemset(h->shift, 0, sizeof(double) * 3 * (size_t)std::max<int64_t>(h->max_obins, 1)) != hipSuccess;
-        bad |= hipMemset(h->status, 0, sizeof(uint32_t)) != hipSuccess;
-        bad |= hipMemset(h->gpart, 0, sizeof(double) * kGPart * (size_t)h->max_blk) != hipSuccess;
+        bad |= hipMemset(h->b.shift, 0, sizeof(double) * 3 * (size_t)std::max<int64_t>(h->max_obins, 1)) != hipSuccess;
+        bad |= hipMemset(h->b.status, 0, sizeof(uint32_t)) != hipSuccess;
+        bad |= hipMemset(h->b.gpart, 0, sizeof(double) * kGPart * (size_t)h->max_blk) != hipSuccess;
         bad |= hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking) != hipSuccess;
         bad |= hipDeviceSynchronize() != hipSuccess;
     }
@@ -859,6 +926,14 @@ int tpkmc_autotune(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instan
                                       : tune_impl<float>(h, s, inst, n_inst, st);
 }
 
+int tpkmc_search_mix(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* inst, int32_t n_inst,
+                     uint64_t* counts, void* stream) {
+    if (!h) return TPKMC_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    return h->precision == TPKMC_FP64 ? mix_impl<double>(h, s, inst, n_inst, counts, st)
+                                      : mix_impl<float>(h, s, inst, n_inst, counts, st);
+}
+
 int tpkmc_set_search(tpkmc_handle* h, int32_t group, int32_t block) {
     if (!h) return TPKMC_EINVAL;
     if (block != 64 && block != 128 && block != 256) return TPKMC_EINVAL;
@@ -881,8 +956,8 @@ int tpkmc_status(tpkmc_handle* h, int32_t* device_status) {
     if (hipSetDevice(h->device) != hipSuccess) return TPKMC_EHIP;
     if (hipStreamSynchronize(h->last_stream) != hipSuccess) return TPKMC_EHIP;
     uint32_t v = 0;
-    if (hipMemcpy(&v, h->status, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess) return TPKMC_EHIP;
-    if (hipMemset(h->status, 0, sizeof(v)) != hipSuccess) return TPKMC_EHIP;
+    if (hipMemcpy(&v, h->b.status, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess) return TPKMC_EHIP;
+    if (hipMemset(h->b.status, 0, sizeof(v)) != hipSuccess) return TPKMC_EHIP;
     *device_status = (int32_t)v;
     return TPKMC_OK;
 }

@@ -83,6 +83,7 @@ struct StepArgs {
     unsigned long long* bkey; // record -> (d_min^2 bits, partner record) (FP32 search)
     double* gpart;            // [nblk][kGPart]
     double* shift;            // per-o-bin velocity shift (3 per o-bin)
+    unsigned long long* mix;  // search mix counters (tests, s0 < 0, s0 < 0 < s1), or null
     // outputs
     uint32_t* pairs;
     int64_t pair_cap;
@@ -95,6 +96,7 @@ template <typename real> void launch_key(const StepArgs<real>& a, hipStream_t s)
 template <typename real> void launch_scatter(const StepArgs<real>& a, hipStream_t s);
 template <typename real> void launch_adapt_dt(Inst<real>* inst, const double* gpart, int n_inst, hipStream_t s);
 template <typename real> void launch_search(const StepArgs<real>& a, int block, int group, hipStream_t s);
+template <typename real> void launch_search_mix(const StepArgs<real>& a, int block, hipStream_t s);
 template <typename real> void launch_move(const StepArgs<real>& a, hipStream_t s);
 template <typename real> void launch_random_pairs(const StepArgs<real>& a, hipStream_t s);
 

@@ -664,10 +664,14 @@ __device__ __forceinline__ void for_neighbourhood(const int32_t* start, const In
 // Ordered (FP64): each record scans its whole neighbourhood and keeps the
 // smallest d_min^2, ties to the lower id, with the reference's arithmetic, so
 // the choice does not depend on the order of records inside a bin.
-template <typename real, bool HALF, bool PER, int G, bool UNIFORM>
+//
+// MIX (a diagnostic build, never the timed one) also counts the pairs the
+// step tests that approach (s0 < 0) and that meet criterion 1 (s0 < 0 < s1),
+// which fix the pair test's arithmetic per pair.
+template <typename real, bool HALF, bool PER, int G, bool UNIFORM, bool MIX = false>
 __device__ __forceinline__ void search_group(const StepArgs<real>& a, const Inst<real>& I, int64_t base,
                                              int32_t i0, int nrec, int32_t wave_first, int wave_ub,
-                                             double& tests, double& cand) {
+                                             double& tests, double& cand, uint32_t& n_s0, uint32_t& n_c1) {
     const Geo<real> G_(I);
     const int n[3] = {I.n[0], I.n[1], I.n[2]};
     real xi[G], yi[G], zi[G], vxi[G], vyi[G], vzi[G];
@@ -758,6 +762,10 @@ __device__ __forceinline__ void search_group(const StepArgs<real>& a, const Inst
             p1[k] = PairTest<real, PER>::stage1(G_, xi[k], yi[k], zi[k], vxi[k], vyi[k], vzi[k], xj, yj, zj, vxj,
                                                 vyj, vzj, S[k]) & take[k];
             any1 |= p1[k];
+            if constexpr (MIX) {
+                n_s0 += (take[k] && S[k].s0 < real(0)) ? 1u : 0u;
+                n_c1 += p1[k] ? 1u : 0u;
+            }
         }
         if (__builtin_amdgcn_ballot_w64(any1) == 0) return;
         bool p2[G];
@@ -871,7 +879,7 @@ __device__ __forceinline__ void search_group(const StepArgs<real>& a, const Inst
 // The FP32 two-records-per-lane shape (the usual autotuner choice) is held to
 // at most 72 VGPRs, 7 waves per SIMD instead of 6 at 78: the extra wave hides
 // more of the neighbour-load latency (measured 3-4% on the search).
-template <typename real, bool HALF, int G>
+template <typename real, bool HALF, int G, bool MIX = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((HALF && G == 2) ? 7 : 1, 8)))
 k_search(StepArgs<real> a) {
     __shared__ double lds[16];
@@ -917,14 +925,36 @@ k_search(StepArgs<real> a) {
               axis_bin(yf, I.lo[1], I.inv_w[1], I.n[1]) == axis_bin(yl, I.lo[1], I.inv_w[1], I.n[1]) &&
               axis_bin(zf, I.lo[2], I.inv_w[2], I.n[2]) == axis_bin(zl, I.lo[2], I.inv_w[2], I.n[2]);
     }
+    uint32_t n_s0 = 0, n_c1 = 0;
     if (uni) {
         if (nrec > 0) {
-            if (per) search_group<real, HALF, true, G, true>(a, I, base, (int32_t)i0, nrec, wfirst, wub, tests, cand);
-            else search_group<real, HALF, false, G, true>(a, I, base, (int32_t)i0, nrec, wfirst, wub, tests, cand);
+            if (per)
+                search_group<real, HALF, true, G, true, MIX>(a, I, base, (int32_t)i0, nrec, wfirst, wub, tests, cand,
+                                                             n_s0, n_c1);
+            else
+                search_group<real, HALF, false, G, true, MIX>(a, I, base, (int32_t)i0, nrec, wfirst, wub, tests, cand,
+                                                              n_s0, n_c1);
         }
     } else if (nrec > 0) {
-        if (per) search_group<real, HALF, true, G, false>(a, I, base, (int32_t)i0, nrec, 0, 0, tests, cand);
-        else search_group<real, HALF, false, G, false>(a, I, base, (int32_t)i0, nrec, 0, 0, tests, cand);
+        if (per)
+            search_group<real, HALF, true, G, false, MIX>(a, I, base, (int32_t)i0, nrec, 0, 0, tests, cand, n_s0,
+                                                          n_c1);
+        else
+            search_group<real, HALF, false, G, false, MIX>(a, I, base, (int32_t)i0, nrec, 0, 0, tests, cand, n_s0,
+                                                           n_c1);
+    }
+    if constexpr (MIX) {
+        // Ordered scans meet every unordered pair from both sides (s0 is
+        // symmetric in i and j bit for bit), so their counts are halved.
+        const double f = HALF ? 1.0 : 0.5;
+        const double t0 = block_sum(tests, lds), t1 = block_sum(f * (double)n_s0, lds),
+                     t2 = block_sum(f * (double)n_c1, lds);
+        if (threadIdx.x == 0) {
+            atomicAdd(a.mix + 0, (unsigned long long)t0);
+            atomicAdd(a.mix + 1, (unsigned long long)t1);
+            atomicAdd(a.mix + 2, (unsigned long long)t2);
+        }
+        return;
     }
     if (!HALF) {
         for (int k = nrec; k < G; ++k)
@@ -1463,6 +1493,14 @@ void launch_search(const StepArgs<real>& a, int block, int group, hipStream_t s)
     if (group == 4) hipLaunchKernelGGL((k_search<real, half, 4>), dim3(grid), dim3(bs), 0, s, a);
     else if (group == 2) hipLaunchKernelGGL((k_search<real, half, 2>), dim3(grid), dim3(bs), 0, s, a);
     else hipLaunchKernelGGL((k_search<real, half, 1>), dim3(grid), dim3(bs), 0, s, a);
+}
+template <typename real>
+void launch_search_mix(const StepArgs<real>& a, int block, hipStream_t s) {
+    constexpr bool half = std::is_same<real, float>::value;
+    const int lanes = kBlock / 2;
+    const int bs = block < lanes ? block : lanes;
+    const unsigned grid = (unsigned)a.nblk * (unsigned)(lanes / bs);
+    hipLaunchKernelGGL((k_search<real, half, 2, true>), dim3(grid), dim3(bs), 0, s, a);
 }
 template <typename real>
 void launch_random_pairs(const StepArgs<real>& a, hipStream_t s) {

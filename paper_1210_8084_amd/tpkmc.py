@@ -95,9 +95,10 @@ def lib():
         L.tpkmc_profile_read.argtypes = [_P, _P, _P, ctypes.c_int32]
         L.tpkmc_set_search.argtypes = [_P, ctypes.c_int32, ctypes.c_int32]
         L.tpkmc_get_search.argtypes = [_P, _P, _P]
+        L.tpkmc_search_mix.argtypes = [_P, _P, _P, ctypes.c_int32, _P, _P]
         for f in ("tpkmc_create", "tpkmc_destroy", "tpkmc_step", "tpkmc_step_batched", "tpkmc_run",
                   "tpkmc_autotune", "tpkmc_status", "tpkmc_profile_enable", "tpkmc_profile_read",
-                  "tpkmc_set_search", "tpkmc_get_search"):
+                  "tpkmc_set_search", "tpkmc_get_search", "tpkmc_search_mix"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -298,6 +299,16 @@ class Engine:
         S = particles(dstate)
         _check(lib().tpkmc_autotune(self.h, ctypes.byref(S), arr, len(specs), _P(_stream_ptr(stream))),
                "tpkmc_autotune")
+
+    def search_mix(self, dstate, specs, stream=None):
+        """(tests, approaching, meeting criterion 1) of the search on this
+        state; the state is not modified."""
+        arr = self.instances(specs)
+        S = particles(dstate)
+        counts = np.zeros(3, dtype=np.uint64)
+        _check(lib().tpkmc_search_mix(self.h, ctypes.byref(S), arr, len(specs), counts.ctypes.data_as(_P),
+                                      _P(_stream_ptr(stream))), "tpkmc_search_mix")
+        return tuple(int(v) for v in counts)
 
     def set_search(self, group, block):
         """Fix the partner-search launch shape: `group` records per lane (1, 2

@@ -1,0 +1,238 @@
+"""FP32 handle against the FP64 oracle, pair by pair, on the same
+FP32-rounded input.
+
+The FP32 search decides the three criteria of Sec. 2.4 / Sec. 3 in FP32,
+tests each unordered pair once and walks dense c-bins in its wave-uniform
+mode, so its pairs can differ from the oracle's only where FP32 rounding can
+change a decision: two candidates of one particle whose d_min^2 lie within
+FP32 rounding of each other (criterion 3), or a pair within rounding of the
+threshold of criterion 1 or 2.  For each case, one GPU step against the
+oracle's step on the same input:
+
+ - every GPU pair meets criteria 1 and 2, or lies within rounding of them;
+ - the GPU pairs form a matching;
+ - the two pair sets share at least 99% of their pairs, and every pair in
+   only one of them has an endpoint whose choice is ambiguous at FP32
+   precision (its FP64 best candidate near a threshold, or another candidate
+   within rounding of the best's d_min^2): nothing else is missing or extra;
+ - the algorithmic test count equals the oracle's (up to the FP32 binning of
+   positions within rounding of a c-bin face).
+
+The dense cases (hundreds to thousands of records per c-bin) run the
+wave-uniform walk with its split at the last lane's lower end; the sparse
+one runs the per-lane walk."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1210_8084_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+R, P, A = W.REFLECT, W.PERIODIC, W.ABSORB
+REL = 1e-5  # margin for FP32 rounding of s0, s1 and d_min^2 (about 80x eps32)
+
+
+@pytest.fixture(scope="module")
+def T():
+    from paper_1210_8084_amd import tpkmc
+    assert torch.cuda.is_available(), "GPU test without a visible GPU"
+    tpkmc.lib()
+    return tpkmc
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rounded32(state):
+    out = W.copy_state(state)
+    for k in ("x", "y", "z", "vx", "vy", "vz"):
+        out[k] = state[k].astype(np.float32).astype(np.float64)
+    return out
+
+
+class Neighbourhoods:
+    """c-bins of the particles (the oracle's binning) and their stencils."""
+
+    def __init__(self, oracle, st, grid):
+        self.oracle, self.grid = oracle, grid
+        lo, hi, n = np.array(grid["lo"]), np.array(grid["hi"]), np.array(grid["ncell"])
+        L = hi - lo
+        inv_w = n / L
+        c = []
+        self.near_face = np.zeros(len(st["x"]), dtype=bool)
+        for a, k in enumerate(("x", "y", "z")):
+            t = (st[k] - lo[a]) * inv_w[a]
+            c.append(np.where(t >= 0, np.minimum(np.floor(np.maximum(t, 0)), n[a] - 1), 0).astype(np.int64))
+            # FP32 binning of (x - lo) * inv_w can differ within a few
+            # roundings of a face (in c-bin units).
+            frac = t - np.floor(t)
+            tol = 8 * float(np.finfo(np.float32).eps) * (n[a] + 1)
+            self.near_face |= (frac < tol) | (frac > 1 - tol)
+        self.cell = c[0] + n[0] * (c[1] + n[1] * c[2])
+        self.order = np.argsort(self.cell, kind="stable")
+        C = int(np.prod(n))
+        self.first = np.searchsorted(self.cell[self.order], np.arange(C + 1))
+        self._stencil = {}
+
+    def stencil(self, i):
+        c = int(self.cell[i])
+        if c not in self._stencil:
+            self._stencil[c] = self.oracle.stencil(self.grid, c)
+        return self._stencil[c]
+
+    def of(self, i):
+        return np.concatenate([self.order[self.first[k]:self.first[k + 1]] for k in self.stencil(i)])
+
+    def adjacent(self, i, j):
+        return int(self.cell[j]) in self.stencil(i)
+
+
+def arrays(st):
+    if "_pos" not in st:
+        st["_pos"] = np.stack([st["x"], st["y"], st["z"]], axis=1)
+        st["_vel"] = np.stack([st["vx"], st["vy"], st["vz"]], axis=1)
+    return st["_pos"], st["_vel"]
+
+
+def classify(st, grid, params, i, J):
+    """FP64 criteria of the ordered pairs (i, j), j in J (i one index or an
+    array like J), with margins for FP32 rounding: d_min^2, |r|^2, `sure`
+    (a candidate at any rounding), `loose` (a candidate at some rounding)."""
+    pos, vel = arrays(st)
+    r = pos[i] - pos[J]
+    for a in range(3):
+        if grid["bc"][a] == P:
+            L = grid["hi"][a] - grid["lo"][a]
+            r[:, a] = np.where(r[:, a] > 0.5 * L, r[:, a] - L, np.where(r[:, a] < -0.5 * L, r[:, a] + L, r[:, a]))
+    u = vel[i] - vel[J]
+    dt = params["dt"]
+    D2 = params["sigma"] / math.pi
+    s0 = (r * u).sum(1)
+    vv = (u * u).sum(1)
+    s1 = s0 + vv * dt
+    mag = np.abs(r * u).sum(1)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        tp = np.where(vv > 0, -s0 / vv, 0.0)
+    p = r + tp[:, None] * u
+    d2 = (p * p).sum(1)
+    rr = (r * r).sum(1)
+    t0, t1, td = REL * mag, REL * (mag + vv * dt), REL * (D2 + rr)
+    sure = (s0 < -t0) & (s1 > t1) & (d2 <= D2 - td) & (J != i)
+    loose = (s0 < t0) & (s1 > -t1) & (d2 <= D2 + td) & (J != i)
+    return d2, rr, sure, loose
+
+
+def ambiguous(st, grid, params, nb, i, best_i):
+    """Whether FP32 rounding can change particle i's choice."""
+    if nb.near_face[i]:
+        return True
+    J = nb.of(i)
+    d2, rr, sure, loose = classify(st, grid, params, i, J)
+    if best_i < 0:
+        return bool(loose.any())
+    k = int(np.flatnonzero(J == best_i)[0])
+    if not sure[k]:
+        return True
+    tol = REL * (params["sigma"] / math.pi + rr[k] + rr)
+    rivals = loose & (J != best_i) & (d2 <= d2[k] + tol)
+    return bool(rivals.any())
+
+
+def run_case(T, oracle, w, flags=0):
+    st0 = rounded32(w.state)
+    g = w.grid
+    eng = T.Engine(max_particles=w.n, max_cells=T.ncells(g) + 1, max_obins=T.nobins(g), precision=T.FP32)
+    dst = T.to_device(st0, T.FP32)
+    out = T.make_outputs(1, T.nobins(g), pair_cap=w.n // 2 + 1)
+    eng.step(dst, g, w.params, out, flags=T.EMIT_PAIRS | flags)
+    torch.cuda.synchronize()
+    o = out.host()
+    eng.close()
+    gpu_pairs = o["pairs"].astype(np.int64)
+    want = W.copy_state(st0)
+    best, _ = oracle.best(st0, g, w.params)
+    r = oracle.step(want, g, w.params)
+    return st0, o, gpu_pairs, best, r
+
+
+def check_against_oracle(T, oracle, w, flags=0, min_pairs=100):
+    _say(f"fp32 pairs vs oracle: {w.name} n={w.n} ncell={w.grid['ncell']} bc={w.grid['bc']}")
+    st0, o, gpu_pairs, best, r = run_case(T, oracle, w, flags)
+    g, p = w.grid, w.params
+    idx = np.empty(int(st0["id"].max()) + 1, dtype=np.int64)
+    idx[st0["id"].astype(np.int64)] = np.arange(w.n)
+    # a matching
+    ends = gpu_pairs.ravel()
+    assert len(np.unique(ends)) == len(ends), "a particle appears in two GPU pairs"
+    assert np.all(gpu_pairs[:, 0] < gpu_pairs[:, 1])
+    # criteria 1 and 2 for every GPU pair (within rounding)
+    nb = Neighbourhoods(oracle, st0, g)
+    ia_all, ib_all = idx[gpu_pairs[:, 0]], idx[gpu_pairs[:, 1]]
+    _, _, _, loose = classify(st0, g, p, ia_all, ib_all)
+    assert loose.all(), f"{(~loose).sum()} GPU pairs fail the criteria beyond FP32 rounding"
+    for ia, ib in zip(ia_all, ib_all):
+        assert nb.adjacent(ia, ib) or nb.near_face[ia] or nb.near_face[ib], "GPU pair outside the neighbourhood"
+    # same pairs up to ambiguous choices, in both directions
+    gs = set(map(tuple, gpu_pairs.tolist()))
+    os_ = set(map(tuple, r["pairs"].astype(np.int64).tolist()))
+    assert len(os_) >= min_pairs
+    common = len(gs & os_)
+    assert common >= 0.99 * max(len(gs), len(os_)), (common, len(gs), len(os_))
+    unexplained = []
+    for a, b in (gs ^ os_):
+        ia, ib = idx[a], idx[b]
+        if not (ambiguous(st0, g, p, nb, ia, best[ia]) or ambiguous(st0, g, p, nb, ib, best[ib])):
+            unexplained.append((a, b, (a, b) in gs))
+    assert not unexplained, f"{len(unexplained)} differing pairs without an FP32-ambiguous endpoint: {unexplained[:5]}"
+    c = o["counters"][0]
+    rc = r["counters"]
+    assert abs(int(c[T.CNT["tests"]]) - int(rc[oracle.CNT["tests"]])) <= 1e-4 * rc[oracle.CNT["tests"]]
+    assert c[T.CNT["pairs"]] == len(gs)
+    assert c[T.CNT["alive"]] == w.n
+    _say(f"  pairs gpu {len(gs)} oracle {len(os_)} common {common} differing {len(gs ^ os_)}")
+    return len(gs ^ os_)
+
+
+def test_sparse_box_lane_walk(T, oracle):
+    """About 50 records per c-bin at most; per-lane walks."""
+    w = W.random_box(n=20000, seed=4, ncell=(10, 8, 6), bc=(R, P, P), d_over_w=0.7, dt_over=0.5)
+    check_against_oracle(T, oracle, w)
+
+
+def test_single_periodic_bin(T, oracle):
+    """One c-bin holds every particle (a 1x1x1 periodic box): every wave
+    walks the one bin in lock-step."""
+    w = W.random_box(n=4000, seed=21, ncell=(1, 1, 1), bc=(P, P, P), hi=(1.0, 0.8, 0.6), d_over_w=0.05,
+                     dt_over=0.05)
+    check_against_oracle(T, oracle, w)
+
+
+def test_dense_periodic_x_seam(T, oracle):
+    """Three periodic c-bins along x of 5000 records each: the wave-uniform
+    walk across the periodic x seam."""
+    w = W.random_box(n=15000, seed=22, ncell=(3, 1, 1), bc=(P, P, P), hi=(1.0, 0.1, 0.1), d_over_w=0.1,
+                     dt_over=0.2)
+    check_against_oracle(T, oracle, w)
+
+
+@pytest.mark.parametrize("reorder", [False, True], ids=["caller-order", "reorder"])
+def test_dense_reflecting_tube(T, oracle, reorder):
+    """A Sod tube of 200k particles on 100 c-bins (about 1800 records per
+    c-bin left of the diaphragm, 220 right), reflecting x walls, periodic
+    y and z: the configuration of the Sod runs at a quarter of their
+    density per c-bin."""
+    w = W.sod(n=200_000, ncell=100, nobin=100, seed=23)
+    check_against_oracle(T, oracle, w, flags=T.ALLOW_REORDER if reorder else 0, min_pairs=5000)
+
+
+def test_sedov_sparse_blast(T, oracle):
+    """A Sedov blast at 250k particles (7.6 per c-bin as at 16M): cold
+    background and a hot core."""
+    w = W.sedov(n=250_000, ncell=32, nobin=16, seed=24)
+    check_against_oracle(T, oracle, w, min_pairs=20)

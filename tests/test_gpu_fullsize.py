@@ -210,3 +210,53 @@ def test_fp32_sedov_16M_sampled(T, oracle):
     assert m[:, 0].sum() == w.n
     assert o["globals"][0][3] == pytest.approx(1.0 + 0.5 * (w.n - w.info["n_blast"]) / w.n *
                                                (1e-3 * w.info["v_blast"]) ** 2, rel=1e-4)
+
+
+@pytest.mark.parametrize("make", [
+    lambda: W.sod(n=4_000_000, ncell=1000, nobin=200, dt=1.134e-4),
+    lambda: W.noh(),
+], ids=["sod4M", "noh8M"])
+def test_fp64_fullsize_trajectory_sampled_bit_exact(T, oracle, make):
+    """Five FP64 steps of the dense full-size runs: every transition is
+    checked on the GPU's own state before the step, so the GPU FP64 path
+    follows the oracle's trajectory bit for bit on these configurations
+    (sampled particles and their partners, the test count, the time step).
+    This is what lets whole runs at these sizes use the GPU FP64 path in
+    place of the oracle, which is too slow for them."""
+    w = make()
+    g = w.grid
+    eng = T.Engine(max_particles=w.n, max_cells=T.ncells(g) + 1, max_obins=T.nobins(g), precision=T.FP64)
+    dst = T.to_device(w.state, T.FP64)
+    out = T.make_outputs(1, T.nobins(g), pair_cap=w.n // 2 + 1)
+    rng = np.random.default_rng(5)
+    for s in range(5):
+        p = dict(w.params, step=s)
+        before = T.to_host(dst)
+        _say(f"{w.name} n={w.n} FP64 step {s}")
+        eng.step(dst, g, p, out, flags=T.ALLOW_REORDER | T.EMIT_PAIRS)
+        torch.cuda.synchronize()
+        after = T.to_host(dst)
+        o = out.host()
+        # 1000 particles at random and 1000 of the GPU's colliders (the
+        # cold inflow of the implosion's first steps collides rarely).
+        inv0 = np.empty(w.n, dtype=np.int64)
+        inv0[before["id"].astype(np.int64)] = np.arange(w.n)
+        coll = inv0[o["pairs"].ravel().astype(np.int64)]
+        pick = rng.choice(coll, size=min(1000, len(coll)), replace=False) if len(coll) else coll
+        sample = np.unique(np.concatenate([rng.choice(w.n, size=1000, replace=False), pick]))
+        ref, partner, alive = oracle.step_sample(before, g, p, sample)
+        inv = np.empty(w.n, dtype=np.int64)
+        inv[after["id"].astype(np.int64)] = np.arange(w.n)
+        rows = inv[before["id"][sample].astype(np.int64)]
+        got = np.stack([after[k][rows] for k in ("x", "y", "z", "vx", "vy", "vz")], axis=1)
+        assert np.array_equal(got, ref), f"step {s}: {np.sum(np.any(got != ref, axis=1))} sampled particles differ"
+        c = o["counters"][0]
+        assert c[2] == oracle.count_tests(before, g)
+        assert c[0] == w.n
+        assert c[1] > 0
+        # every sampled GPU collider has the oracle's partner
+        assert (partner[np.isin(sample, pick)] >= 0).all()
+        _say(f"  {len(sample)} sampled, {int((partner >= 0).sum())} colliders, {int(c[1])} pairs")
+    eng.close()
+    del dst
+    torch.cuda.empty_cache()

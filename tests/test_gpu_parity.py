@@ -705,3 +705,59 @@ def test_fp64_pairs_on_the_edges_of_both_criteria(T, oracle):
     assert gouts[0]["counters"][0].tolist() == routs[0]["counters"].tolist()
     accepted = routs[0]["counters"][oracle.CNT["pairs"]]
     assert 0.1 * 4000 < accepted < 0.9 * 4000
+
+
+def _mix_by_enumeration(oracle, st, grid, params):
+    """(tests, s0 < 0, s0 < 0 < s1) over the unordered pairs of every c-bin's
+    neighbourhood, s0 and s1 in the order of the pair test (no FMA)."""
+    n = len(st["x"])
+    cells = np.array([oracle.cell_of(grid, st["x"][i], st["y"][i], st["z"][i])[0] for i in range(n)])
+    L = [grid["hi"][a] - grid["lo"][a] for a in range(3)]
+    tests = s0n = c1n = 0
+    for i in range(n):
+        nb = set(oracle.stencil(grid, int(cells[i])))
+        J = np.array([j for j in range(i + 1, n) if int(cells[j]) in nb], dtype=np.int64)
+        if len(J) == 0:
+            continue
+        r = [st[k][i] - st[k][J] for k in ("x", "y", "z")]
+        for a in range(3):
+            if grid["bc"][a] == P:
+                r[a] = np.where(r[a] > 0.5 * L[a], r[a] - L[a], np.where(r[a] < -(0.5 * L[a]), r[a] + L[a], r[a]))
+        u = [st[k][i] - st[k][J] for k in ("vx", "vy", "vz")]
+        s0 = (r[0] * u[0] + r[1] * u[1]) + r[2] * u[2]
+        vv = (u[0] * u[0] + u[1] * u[1]) + u[2] * u[2]
+        s1 = s0 + vv * params["dt"]
+        tests += len(J)
+        s0n += int((s0 < 0).sum())
+        c1n += int(((s0 < 0) & (s1 > 0)).sum())
+    return tests, s0n, c1n
+
+
+@pytest.mark.parametrize("case", CASES[:3], ids=lambda c: f"s{c['seed']}-{c['ncell']}-{c['bc']}")
+def test_search_mix_counts(T, oracle, case):
+    """tpkmc_search_mix counts the pair tests, the approaching pairs and those
+    meeting criterion 1: in FP64 exactly an enumeration of the neighbourhood
+    pairs; in FP32 the same up to rounding of s0 and s1.  The state is left
+    untouched."""
+    w = W.random_box(n=1500, seed=case["seed"], ncell=case["ncell"], bc=case["bc"], d_over_w=0.7, dt_over=0.6)
+    want = _mix_by_enumeration(oracle, w.state, w.grid, w.params)
+    assert want[0] == oracle.count_tests(w.state, w.grid)
+    st32 = W.copy_state(w.state)
+    for k in ("x", "y", "z", "vx", "vy", "vz"):
+        st32[k] = w.state[k].astype(np.float32).astype(np.float64)
+    want32 = _mix_by_enumeration(oracle, st32, w.grid, w.params)
+    for prec in (T.FP64, T.FP32):
+        eng = engine_for(T, w, prec)
+        dst = T.to_device(w.state, prec)
+        before = T.to_host(dst)
+        got = eng.search_mix(dst, [(0, w.n, w.grid, w.params)])
+        after = T.to_host(dst)
+        eng.close()
+        for k in ("x", "y", "z", "vx", "vy", "vz", "id"):
+            assert np.array_equal(before[k], after[k])
+        _say(f"mix {case} prec={prec}: gpu {got} enumeration {want}")
+        if prec == T.FP64:
+            assert got == want
+        else:
+            assert got[0] == want32[0]
+            assert abs(got[1] - want32[1]) <= 3 and abs(got[2] - want32[2]) <= 3
