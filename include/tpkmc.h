@@ -268,6 +268,34 @@ int tpkmc_destroy(tpkmc_handle* h);
 int tpkmc_step(tpkmc_handle* h, const tpkmc_grid* g, const tpkmc_params* p,
                const tpkmc_particles* s, const tpkmc_outputs* o, void* hip_stream);
 
+/* Size in bytes of the static device scratch of tpkmc_step_noalloc: one
+ * array per GPU the library runs on, held until the process ends. */
+#define TPKMC_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the step
+ * of tpkmc_step for one instance without a handle.  It calls no hipMalloc,
+ * hipFree, host-pinned allocation or other allocating routine; its scratch
+ * lives in a static device array of TPKMC_NOALLOC_SCRATCH_BYTES per GPU.
+ *   precision: TPKMC_FP64 (double particle arrays) or TPKMC_FP32 (float);
+ *   device:    HIP device ordinal (made current on the calling thread); the
+ *              stream must belong to it;
+ *   g, p, s, o, hip_stream: as for tpkmc_step; the search runs in the
+ *              default launch shape (2 records per lane, 64 lanes), so the
+ *              results equal those of tpkmc_step on a new handle.
+ * Returns TPKMC_ECAPACITY, before anything is launched, when the step's
+ * scratch exceeds the array: about 81 B per particle in FP64 (89 with
+ * per-particle masses), 57 B in FP32 (61), plus 4 B per c-bin and 24 B per
+ * o-bin, so at most about 0.8M particles in FP64 and 1.1M in FP32.
+ * Every call on a GPU uses that GPU's one array, and the array keeps the
+ * last call's contents (the call clears what must start at zero), so calls
+ * that overlap in time on one GPU race: order them on one stream.  There
+ * is no status word: the device conditions show in the counters
+ * (TPKMC_CNT_NONFINITE, TPKMC_CNT_FAST, and TPKMC_CNT_PAIRS > pair_cap for
+ * an overflowing pair list). */
+int tpkmc_step_noalloc(int32_t precision, int32_t device, const tpkmc_grid* g, const tpkmc_params* p,
+                       const tpkmc_particles* s, const tpkmc_outputs* o, void* hip_stream);
+
 /* One step of n_inst independent instances in a single set of launches;
  * s describes the concatenated arrays.  Outputs are per instance as above;
  * EMIT_PAIRS of any instance writes into the one shared pair list. */

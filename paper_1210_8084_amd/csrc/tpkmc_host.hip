@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "tpkmc_internal.h"
@@ -261,6 +262,27 @@ __global__ void __launch_bounds__(256) k_moments_final(const Inst<real>* inst, d
         const int k = t % TPKMC_MOMENT_STRIDE;
         if ((k >= 1 && k <= 6) || k == 11) M0[t] = rows[t];
     }
+}
+
+// Tables of the allocation-free entry point, written on the device so that
+// no host staging or copy is needed: its one instance descriptor (passed by
+// value as a kernel argument), the block and chunk tables, and the o-bin
+// velocity shifts and status word, cleared because the static scratch keeps
+// the previous call's contents.
+template <typename real>
+__global__ void __launch_bounds__(256) k_setup_one(Inst<real> one, Inst<real>* inst, Blk* blk, int nblk,
+                                                  Chunk* chunks, int nchunk, double* shift, int64_t nshift,
+                                                  uint32_t* status) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t0 == 0) {
+        *inst = one;
+        *status = 0u;
+    }
+    for (int64_t t = t0; t < nblk; t += stride) blk[t] = Blk{0, (int32_t)(one.off + t * kBlock)};
+    for (int64_t t = t0; t < nchunk; t += stride)
+        chunks[t] = Chunk{(int32_t)(t * kChunk), (int32_t)min<int64_t>(kChunk, nblk - t * kChunk)};
+    for (int64_t t = t0; t < nshift; t += stride) shift[t] = 0.0;
 }
 
 }  // namespace
@@ -791,6 +813,109 @@ void free_all(tpkmc_handle* h) {
     hipFree(h->b.blk); hipFree(h->b.chunks); hipFree(h->b.bkey); hipFree(h->b.cpart); hipFree(h->b.gpart); hipFree(h->b.shift); hipFree(h->b.pair_count); hipFree(h->b.status); hipFree(h->b.mix);
 }
 
+// ---------------------------------------------------------------- static scratch
+// Scratch of the allocation-free entry point: one array per GPU, held until
+// the process ends.  Host code never uses the name `scratch` as an address
+// (on the host it is only a stand-in); it uses the device address that
+// hipGetSymbolAddress returns, looked up once per device with that device
+// current and kept in scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[TPKMC_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+unsigned char* scratch_ptr[kMaxDevices] = {};
+
+int scratch_of(int device, unsigned char** out) {
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[device]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) return TPKMC_EHIP;
+        scratch_ptr[device] = (unsigned char*)p;
+    }
+    *out = scratch_ptr[device];
+    return TPKMC_OK;
+}
+
+// Carves the buffers of one instance out of the region starting at `base`
+// (256-byte aligned pieces) and returns the bytes they span; with base 0 it
+// only measures.
+template <typename real>
+size_t carve(uintptr_t base, int64_t n, int64_t ncell_tot, int64_t nob, int nblk, int nchunk, bool masses,
+             Buffers& B) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void* {
+        const uintptr_t p = base + off;
+        off += (std::max<size_t>(bytes, 1) + 255) & ~(size_t)255;
+        return (void*)p;
+    };
+    const size_t nn = (size_t)std::max<int64_t>(n, 1);
+    B.rank = (int32_t*)take(4 * nn);
+    B.src = (int32_t*)take(4 * nn);
+    B.best = (int32_t*)take(4 * nn);
+    B.perm = (int32_t*)take(4 * nn);
+    B.rec = take(8 * sizeof(real) * nn);
+    B.rmass = masses ? take(sizeof(real) * nn) : nullptr;
+    B.bkey = std::is_same<real, float>::value ? (unsigned long long*)take(8 * nn) : nullptr;
+    B.start = (int32_t*)take(4 * (size_t)(ncell_tot + 1));
+    B.tiles = (int32_t*)take(4 * (size_t)(scan_tiles(ncell_tot + 1) + 1));
+    B.inst = take(sizeof(Inst<real>));
+    B.blk = (Blk*)take(sizeof(Blk) * (size_t)nblk);
+    B.gpart = (double*)take(sizeof(double) * kGPart * (size_t)nblk);
+    B.chunks = (Chunk*)take(sizeof(Chunk) * (size_t)nchunk);
+    B.cpart = (double*)take(sizeof(double) * kGPart * (size_t)nchunk);
+    B.shift = (double*)take(sizeof(double) * 3 * (size_t)std::max<int64_t>(nob, 1));
+    B.pair_count = (unsigned long long*)take(sizeof(unsigned long long));
+    B.status = (uint32_t*)take(sizeof(uint32_t));
+    return off;
+}
+
+template <typename real>
+int step_noalloc_impl(int device, const tpkmc_grid* g, const tpkmc_params* p, const tpkmc_particles* s,
+                      const tpkmc_outputs* o, hipStream_t st) {
+    if (!g || !p || !s || s->n < 0 || bad_state(s)) return TPKMC_EINVAL;
+    int rc = check_outputs(o);
+    if (rc) return rc;
+    tpkmc_instance q;
+    q.offset = 0;
+    q.count = s->n;
+    q.grid = *g;
+    q.params = *p;
+    Inst<real> d;
+    int64_t C = 0, B = 0;
+    if ((rc = fill_inst<real>(s, q, d, C, B))) return rc;
+    // Records are addressed with 32-bit byte offsets in the FP32 search.
+    if (s->n >= ((int64_t)1 << 27)) return TPKMC_ECAPACITY;
+    const int nblk = (int)((s->n + kBlock - 1) / kBlock);
+    const int nchunk = (nblk + kChunk - 1) / kChunk;
+    const int64_t ncell_tot = C + 1;
+    d.cell_off = 0;
+    d.obin_off = 0;
+    d.blk0 = 0;
+    d.nblk = nblk;
+    d.chunk0 = 0;
+    d.nchunk = nchunk;
+    Buffers Bf{};
+    if (carve<real>(0, s->n, ncell_tot, B, nblk, nchunk, s->mass != nullptr, Bf) > TPKMC_NOALLOC_SCRATCH_BYTES)
+        return TPKMC_ECAPACITY;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess) return TPKMC_EHIP;
+    if (device < 0 || device >= ndev || device >= kMaxDevices) return TPKMC_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return TPKMC_EHIP;
+    unsigned char* base = nullptr;
+    if ((rc = scratch_of(device, &base))) return rc;
+    carve<real>((uintptr_t)base, s->n, ncell_tot, B, nblk, nchunk, s->mass != nullptr, Bf);
+    const int64_t nshift = 3 * std::max<int64_t>(B, 1);
+    const int64_t work = std::max<int64_t>(std::max<int64_t>(nblk, nchunk), nshift);
+    const unsigned sgrid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((work + 255) / 256, 1024));
+    hipLaunchKernelGGL(k_setup_one<real>, dim3(sgrid), dim3(256), 0, st, d, (Inst<real>*)Bf.inst, Bf.blk, nblk,
+                       Bf.chunks, nchunk, Bf.shift, nshift, Bf.status);
+    const bool random = (p->flags & TPKMC_PAIR_RANDOM) != 0;
+    const Shape P{1, nblk, nchunk, ncell_tot, B, B, (p->flags & TPKMC_ADAPTIVE_DT) != 0, !random, random};
+    StepArgs<real> a = make_args<real>(Bf, s, o, nblk);
+    enqueue_step<real>(nullptr, Bf, a, o, P, kWave, 2, st, false, 0);
+    return hipGetLastError() == hipSuccess ? TPKMC_OK : TPKMC_EHIP;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- C ABI
@@ -804,7 +929,7 @@ const char* tpkmc_strerror(int code) {
         case TPKMC_EINVAL: return "invalid argument";
         case TPKMC_ENOMEM: return "device allocation failed";
         case TPKMC_EHIP: return "HIP runtime error";
-        case TPKMC_ECAPACITY: return "input exceeds the handle's capacity";
+        case TPKMC_ECAPACITY: return "input exceeds the capacity of the handle or of the static scratch";
         case TPKMC_EUNSUPPORTED: return "unsupported";
         default: return "unknown error code";
     }
@@ -900,6 +1025,14 @@ int tpkmc_step(tpkmc_handle* h, const tpkmc_grid* g, const tpkmc_params* p, cons
     one.grid = *g;
     one.params = *p;
     return tpkmc_step_batched(h, s, &one, 1, o, stream);
+}
+
+int tpkmc_step_noalloc(int32_t precision, int32_t device, const tpkmc_grid* g, const tpkmc_params* p,
+                       const tpkmc_particles* s, const tpkmc_outputs* o, void* stream) {
+    hipStream_t st = (hipStream_t)stream;
+    if (precision == TPKMC_FP64) return step_noalloc_impl<double>(device, g, p, s, o, st);
+    if (precision == TPKMC_FP32) return step_noalloc_impl<float>(device, g, p, s, o, st);
+    return TPKMC_EINVAL;
 }
 
 int tpkmc_step_batched(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* inst, int32_t n_inst,

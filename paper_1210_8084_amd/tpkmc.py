@@ -95,10 +95,11 @@ def lib():
         L.tpkmc_profile_read.argtypes = [_P, _P, _P, ctypes.c_int32]
         L.tpkmc_set_search.argtypes = [_P, ctypes.c_int32, ctypes.c_int32]
         L.tpkmc_get_search.argtypes = [_P, _P, _P]
+        L.tpkmc_step_noalloc.argtypes = [ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P]
         L.tpkmc_search_mix.argtypes = [_P, _P, _P, ctypes.c_int32, _P, _P]
         for f in ("tpkmc_create", "tpkmc_destroy", "tpkmc_step", "tpkmc_step_batched", "tpkmc_run",
                   "tpkmc_autotune", "tpkmc_status", "tpkmc_profile_enable", "tpkmc_profile_read",
-                  "tpkmc_set_search", "tpkmc_get_search", "tpkmc_search_mix"):
+                  "tpkmc_set_search", "tpkmc_get_search", "tpkmc_step_noalloc", "tpkmc_search_mix"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -237,6 +238,21 @@ def _stream_ptr(stream):
     if stream is None:
         return _torch().cuda.current_stream().cuda_stream
     return getattr(stream, "cuda_stream", stream)
+
+
+NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024
+
+
+def step_noalloc(dstate, grid, params, out=None, flags=0, precision=FP64, device=0, stream=None, rc_only=False):
+    """One step through ``tpkmc_step_noalloc``: no handle, scratch in the
+    library's static device array (no device allocation)."""
+    G, P, S = make_grid(grid), make_params(params, flags), particles(dstate)
+    O = out.struct() if out is not None else Outputs()
+    rc = lib().tpkmc_step_noalloc(int(precision), int(device), ctypes.byref(G), ctypes.byref(P), ctypes.byref(S),
+                                  ctypes.byref(O), _P(_stream_ptr(stream)))
+    if rc_only:
+        return rc
+    _check(rc, "tpkmc_step_noalloc")
 
 
 class Engine:
