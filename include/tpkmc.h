@@ -305,8 +305,11 @@ int tpkmc_step_batched(tpkmc_handle* h, const tpkmc_particles* s,
 
 /* nsteps steps of a batch: the step is captured once as a HIP graph and
  * replayed nsteps times; each instance's step number advances on the device
- * from inst[k].params.step.  Outputs hold the last step's values.  Uses the
- * tuned launch shape (tpkmc_autotune) if one was recorded. */
+ * from inst[k].params.step.  Outputs hold the last step's values.  On the
+ * handle's first run without a launch shape chosen by tpkmc_autotune or
+ * tpkmc_set_search, it first tunes the search on this batch (as
+ * tpkmc_autotune, which synchronises the stream; every shape gives the same
+ * results). */
 int tpkmc_run(tpkmc_handle* h, const tpkmc_particles* s,
               const tpkmc_instance* inst, int32_t n_inst, int32_t nsteps,
               const tpkmc_outputs* o, void* hip_stream);

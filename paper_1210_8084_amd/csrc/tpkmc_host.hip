@@ -317,6 +317,7 @@ struct tpkmc_handle {
     hipStream_t own_stream = nullptr;
     int search_block = kWave;
     int search_group = 2;
+    bool shape_chosen = false;  // set by tpkmc_set_search or tpkmc_autotune
     bool profiling = false;
     std::vector<ProfRec> prof;
     std::vector<hipEvent_t> pool;
@@ -667,6 +668,9 @@ int step_impl(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* i
 }
 
 template <typename real>
+int tune_impl(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* in, int n_inst, hipStream_t st);
+
+template <typename real>
 int run_impl(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* in, int n_inst, int nsteps,
              const tpkmc_outputs* o, hipStream_t caller) {
     if (nsteps < 0) return TPKMC_EINVAL;
@@ -684,6 +688,9 @@ int run_impl(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* in
         hipEventRecord(ev, nullptr);
         hipStreamWaitEvent(st, ev, 0);
     }
+    // First use without a chosen launch shape: tune it on this batch (the
+    // state is not modified; every shape gives the same results).
+    if (!h->shape_chosen && (rc = tune_impl<real>(h, s, in, n_inst, st))) return rc;
     if ((rc = upload(h, P, st))) return rc;
     StepArgs<real> a = make_args<real>(h->b, s, o, P.nblk);
     if (h->gexec) {
@@ -761,6 +768,7 @@ int tune_impl(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* i
     if (rc) return rc;
     h->search_block = best_block;
     h->search_group = best_group;
+    h->shape_chosen = true;
     h->last_stream = st;
     return hipGetLastError() == hipSuccess ? TPKMC_OK : TPKMC_EHIP;
 }
@@ -792,6 +800,7 @@ int mix_impl(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* in
     if (hipMemcpyAsync(counts, h->b.mix, 3 * sizeof(uint64_t), hipMemcpyDeviceToHost, st) != hipSuccess)
         return TPKMC_EHIP;
     if (hipStreamSynchronize(st) != hipSuccess) return TPKMC_EHIP;
+    for (int k = 0; k < 3; ++k) counts[k] /= 2u;  // the device counts each unordered pair twice
     h->last_stream = st;
     return hipGetLastError() == hipSuccess ? TPKMC_OK : TPKMC_EHIP;
 }
@@ -1074,6 +1083,7 @@ int tpkmc_set_search(tpkmc_handle* h, int32_t group, int32_t block) {
     if (block > kBlock / group) return TPKMC_EINVAL;
     h->search_group = group;
     h->search_block = block;
+    h->shape_chosen = true;
     return TPKMC_OK;
 }
 

@@ -466,15 +466,19 @@ __device__ __forceinline__ real min_image(real r, real L, real halfL) {
 //    form, only discards pairs that are certainly not candidates; the rest go
 //    through the reference's own expressions (t_poca = -s0/|u|^2, PoCA
 //    separation r + t_poca u), so decisions and d_min^2 are bit-identical.
-template <typename real, bool PER>
+template <typename real, int PM>
 __device__ __forceinline__ void rel_vectors(const Geo<real>& G, real xi, real yi, real zi, real vxi, real vyi,
                                             real vzi, real xj, real yj, real zj, real vxj, real vyj, real vzj,
                                             real& rx, real& ry, real& rz, real& ux, real& uy, real& uz) {
     rx = xi - xj; ry = yi - yj; rz = zi - zj;
-    if (PER) {
+    if constexpr (PM < 0) {
         if (G.per[0]) rx = min_image(rx, G.L[0], G.halfL[0]);
         if (G.per[1]) ry = min_image(ry, G.L[1], G.halfL[1]);
         if (G.per[2]) rz = min_image(rz, G.L[2], G.halfL[2]);
+    } else {
+        if constexpr ((PM & 1) != 0) rx = min_image(rx, G.L[0], G.halfL[0]);
+        if constexpr ((PM & 2) != 0) ry = min_image(ry, G.L[1], G.halfL[1]);
+        if constexpr ((PM & 4) != 0) rz = min_image(rz, G.L[2], G.halfL[2]);
     }
     ux = vxi - vxj; uy = vyi - vyj; uz = vzi - vzj;
 }
@@ -488,18 +492,24 @@ template <typename real> struct Screen {
     real rx, ry, rz, ux, uy, uz, s0, vv;
 };
 
-template <typename real, bool PER> struct PairTest;
+// PM: the periodic axes as a mask known at compile time (bit a for axis a),
+// or -1 to read them from the instance at run time.
+template <typename real, int PM> struct PairTest;
 
-template <bool PER> struct PairTest<float, PER> {
+template <int PM> struct PairTest<float, PM> {
     static __device__ __forceinline__ bool stage1(const Geo<float>& G, float xi, float yi, float zi, float vxi,
                                                   float vyi, float vzi, float xj, float yj, float zj, float vxj,
                                                   float vyj, float vzj, Screen<float>& S) {
         float rx = xi - xj, ry = yi - yj, rz = zi - zj;
-        if (PER) {
-            // Nearest image: r - L rint(r / L) (ties at exactly L/2 keep r).
+        // Nearest image: r - L rint(r / L) (ties at exactly L/2 keep r).
+        if constexpr (PM < 0) {
             if (G.per[0]) rx = fmaf(-G.L[0], rintf(rx * G.invL[0]), rx);
             if (G.per[1]) ry = fmaf(-G.L[1], rintf(ry * G.invL[1]), ry);
             if (G.per[2]) rz = fmaf(-G.L[2], rintf(rz * G.invL[2]), rz);
+        } else {
+            if constexpr ((PM & 1) != 0) rx = fmaf(-G.L[0], rintf(rx * G.invL[0]), rx);
+            if constexpr ((PM & 2) != 0) ry = fmaf(-G.L[1], rintf(ry * G.invL[1]), ry);
+            if constexpr ((PM & 4) != 0) rz = fmaf(-G.L[2], rintf(rz * G.invL[2]), rz);
         }
         const float ux = vxi - vxj, uy = vyi - vyj, uz = vzi - vzj;
         const float s0 = fmaf(rz, uz, fmaf(ry, uy, rx * ux));
@@ -533,12 +543,12 @@ template <bool PER> struct PairTest<float, PER> {
     }
 };
 
-template <bool PER> struct PairTest<double, PER> {
+template <int PM> struct PairTest<double, PM> {
     static __device__ __forceinline__ bool stage1(const Geo<double>& G, double xi, double yi, double zi, double vxi,
                                                   double vyi, double vzi, double xj, double yj, double zj, double vxj,
                                                   double vyj, double vzj, Screen<double>& S) {
         double rx, ry, rz, ux, uy, uz;
-        rel_vectors<double, PER>(G, xi, yi, zi, vxi, vyi, vzi, xj, yj, zj, vxj, vyj, vzj, rx, ry, rz, ux, uy, uz);
+        rel_vectors<double, PM>(G, xi, yi, zi, vxi, vyi, vzi, xj, yj, zj, vxj, vyj, vzj, rx, ry, rz, ux, uy, uz);
         // Exactly the reference's s0 and s1 (no contraction in this unit).
         const double s0 = (rx * ux + ry * uy) + rz * uz;
         const double vv = (ux * ux + uy * uy) + uz * uz;
@@ -668,7 +678,7 @@ __device__ __forceinline__ void for_neighbourhood(const int32_t* start, const In
 // MIX (a diagnostic build, never the timed one) also counts the pairs the
 // step tests that approach (s0 < 0) and that meet criterion 1 (s0 < 0 < s1),
 // which fix the pair test's arithmetic per pair.
-template <typename real, bool HALF, bool PER, int G, bool UNIFORM, bool MIX = false>
+template <typename real, bool HALF, int PM, int G, bool UNIFORM, bool MIX = false>
 __device__ __forceinline__ void search_group(const StepArgs<real>& a, const Inst<real>& I, int64_t base,
                                              int32_t i0, int nrec, int32_t wave_first, int wave_ub,
                                              double& tests, double& cand, uint32_t& n_s0, uint32_t& n_c1) {
@@ -724,10 +734,10 @@ __device__ __forceinline__ void search_group(const StepArgs<real>& a, const Inst
     // first contact time.
     const bool by_time = (I.flags & TPKMC_RANK_TIME) != 0;
     auto hit = [&](int k, int32_t j, uint32_t idj, const Screen<real>& S) {
-        const real d2 = PairTest<real, PER>::finish(G_, S);
+        const real d2 = PairTest<real, PM>::finish(G_, S);
         if (d2 >= real(0)) {
             ++nc;
-            const real key = by_time ? PairTest<real, PER>::contact(G_, S) : d2;
+            const real key = by_time ? PairTest<real, PM>::contact(G_, S) : d2;
             if constexpr (HALF) {
                 const unsigned long long hi = (unsigned long long)sortable((float)key) << 32;
                 atomicMin(a.bkey + j, hi | (uint32_t)(i0 + k));
@@ -759,7 +769,7 @@ __device__ __forceinline__ void search_group(const StepArgs<real>& a, const Inst
 #pragma unroll
         for (int k = 0; k < G; ++k) {
             // Evaluated on every lane, masked afterwards: no branch.
-            p1[k] = PairTest<real, PER>::stage1(G_, xi[k], yi[k], zi[k], vxi[k], vyi[k], vzi[k], xj, yj, zj, vxj,
+            p1[k] = PairTest<real, PM>::stage1(G_, xi[k], yi[k], zi[k], vxi[k], vyi[k], vzi[k], xj, yj, zj, vxj,
                                                 vyj, vzj, S[k]) & take[k];
             any1 |= p1[k];
             if constexpr (MIX) {
@@ -772,7 +782,7 @@ __device__ __forceinline__ void search_group(const StepArgs<real>& a, const Inst
         bool any2 = false;
 #pragma unroll
         for (int k = 0; k < G; ++k) {
-            p2[k] = p1[k] && PairTest<real, PER>::stage2(G_, S[k]);
+            p2[k] = p1[k] && PairTest<real, PM>::stage2(G_, S[k]);
             any2 |= p2[k];
         }
         if (!any2) return;
@@ -874,6 +884,31 @@ __device__ __forceinline__ void search_group(const StepArgs<real>& a, const Inst
     cand = HALF ? 2.0 * (double)nc : (double)nc;
 }
 
+// search_group for the instance's periodic axes: FP32 has builds for the
+// masks of the usual boxes (none; z, as in the Noh implosions and the planar
+// gases; y and z, as in the Sod tubes; all three), which leave the other axes
+// out of the pair test; other masks, and FP64, read them at run time.
+template <typename real, bool HALF, int G, bool UNIFORM, bool MIX>
+__device__ __forceinline__ void search_for_axes(int pm, const StepArgs<real>& a, const Inst<real>& I, int64_t base,
+                                                int32_t i0, int nrec, int32_t wave_first, int wave_ub,
+                                                double& tests, double& cand, uint32_t& n_s0, uint32_t& n_c1) {
+#define TPKMC_SEARCH(PMV) \
+    search_group<real, HALF, PMV, G, UNIFORM, MIX>(a, I, base, i0, nrec, wave_first, wave_ub, tests, cand, n_s0, n_c1)
+    if constexpr (std::is_same<real, float>::value) {
+        switch (pm) {
+            case 0: TPKMC_SEARCH(0); break;
+            case 4: TPKMC_SEARCH(4); break;
+            case 6: TPKMC_SEARCH(6); break;
+            case 7: TPKMC_SEARCH(7); break;
+            default: TPKMC_SEARCH(-1); break;
+        }
+    } else {
+        if (pm == 0) TPKMC_SEARCH(0);
+        else TPKMC_SEARCH(-1);
+    }
+#undef TPKMC_SEARCH
+}
+
 // One table entry (kBlock records) is covered by kBlock / G lanes, split
 // into work-groups of blockDim.x lanes.
 // The FP32 two-records-per-lane shape (the usual autotuner choice) is held to
@@ -894,7 +929,8 @@ k_search(StepArgs<real> a) {
     const int64_t base = I.off - a.start[I.cell_off];
     const int64_t live_end = base + a.start[I.cell_off + I.C];
     const int64_t end = I.off + I.cnt;
-    const bool per = I.bc[0] == TPKMC_BC_PERIODIC || I.bc[1] == TPKMC_BC_PERIODIC || I.bc[2] == TPKMC_BC_PERIODIC;
+    const int pm = (I.bc[0] == TPKMC_BC_PERIODIC ? 1 : 0) | (I.bc[1] == TPKMC_BC_PERIODIC ? 2 : 0) |
+                   (I.bc[2] == TPKMC_BC_PERIODIC ? 4 : 0);
     double tests = 0.0, cand = 0.0;
     const int64_t live_stop = live_end < end ? live_end : end;
     const int nrec = i0 < live_stop ? (int)(live_stop - i0 < G ? live_stop - i0 : G) : 0;
@@ -927,27 +963,19 @@ k_search(StepArgs<real> a) {
     }
     uint32_t n_s0 = 0, n_c1 = 0;
     if (uni) {
-        if (nrec > 0) {
-            if (per)
-                search_group<real, HALF, true, G, true, MIX>(a, I, base, (int32_t)i0, nrec, wfirst, wub, tests, cand,
-                                                             n_s0, n_c1);
-            else
-                search_group<real, HALF, false, G, true, MIX>(a, I, base, (int32_t)i0, nrec, wfirst, wub, tests, cand,
-                                                              n_s0, n_c1);
-        }
+        if (nrec > 0)
+            search_for_axes<real, HALF, G, true, MIX>(pm, a, I, base, (int32_t)i0, nrec, wfirst, wub, tests, cand,
+                                                      n_s0, n_c1);
     } else if (nrec > 0) {
-        if (per)
-            search_group<real, HALF, true, G, false, MIX>(a, I, base, (int32_t)i0, nrec, 0, 0, tests, cand, n_s0,
-                                                          n_c1);
-        else
-            search_group<real, HALF, false, G, false, MIX>(a, I, base, (int32_t)i0, nrec, 0, 0, tests, cand, n_s0,
-                                                           n_c1);
+        search_for_axes<real, HALF, G, false, MIX>(pm, a, I, base, (int32_t)i0, nrec, 0, 0, tests, cand, n_s0, n_c1);
     }
     if constexpr (MIX) {
-        // Ordered scans meet every unordered pair from both sides (s0 is
-        // symmetric in i and j bit for bit), so their counts are halved.
-        const double f = HALF ? 1.0 : 0.5;
-        const double t0 = block_sum(tests, lds), t1 = block_sum(f * (double)n_s0, lds),
+        // Counted twice per unordered pair, so every work-group's share is an
+        // integer: ordered scans meet each pair from both sides (s0 is
+        // symmetric in i and j bit for bit), half scans once (doubled here).
+        // The host halves the totals.
+        const double f = HALF ? 2.0 : 1.0;
+        const double t0 = block_sum(2.0 * tests, lds), t1 = block_sum(f * (double)n_s0, lds),
                      t2 = block_sum(f * (double)n_c1, lds);
         if (threadIdx.x == 0) {
             atomicAdd(a.mix + 0, (unsigned long long)t0);
