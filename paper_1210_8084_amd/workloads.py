@@ -219,6 +219,28 @@ def equilibration(n=200_000, seed=1, lam_over_dx=1e-3, ncell=(32, 32, 32), box=4
     return Workload("equilibration", st, g, params(sigma, dt, seed=seed), steps, info)
 
 
+def equilibration2d(n=20_000_000, seed=1, lam_over_dx=1e-3, ncell=1000, box=4.0, speed=10.0,
+                    dt_over_dx=1.0 / 60.0, steps=400):
+    """Maxwell-Boltzmann equilibration of a two-dimensional gas (Sec. 4.1, the
+    paper's own setup): N particles uniform in the periodic square
+    [0, box]^2 of the plane z = 0 on ncell^2 c-bins, every one at the same
+    speed in a random in-plane direction, dt = dt_over_dx * dx.  sigma is a
+    length, 1 / (n lambda) with n the number per area and lambda =
+    lam_over_dx * dx."""
+    rng = np.random.default_rng(seed)
+    pos = rng.uniform(0.0, box, size=(2, n))
+    th = rng.uniform(0.0, 2.0 * math.pi, n)
+    dx = box / ncell
+    lam = lam_over_dx * dx
+    sigma = 1.0 / ((n / (box * box)) * lam)
+    dt = dt_over_dx * dx
+    g = grid((0, 0, -0.5), (box, box, 0.5), (ncell, ncell, 1), (PERIODIC,) * 3)
+    z, vz = _in_plane(n)
+    st = make_state(pos[0], pos[1], z, speed * np.cos(th), speed * np.sin(th), vz)
+    info = dict(lam=lam, dx=dx, speed=speed, lam_over_dx=lam_over_dx, f=2)
+    return Workload("equilibration2d", st, g, dict(params(sigma, dt, seed=seed), planar=True), steps, info)
+
+
 def mean_speed_2d(temperature: float, mass: float = 1.0) -> float:
     """Mean speed of a 2D Maxwellian, sqrt(pi T / (2 m))."""
     return math.sqrt(math.pi * temperature / (2.0 * mass))

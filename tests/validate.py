@@ -91,13 +91,17 @@ def _tanh_width(x, n, x_s, lo, hi):
     return float(2.0 * math.atanh(0.8) * abs(d)), float(c)
 
 
-def sod(precision, n=4_000_000, steps=500, kn=1e-3, planar=False, seed=1, rank_time=False, pair_random=False):
+def sod(precision, n=4_000_000, steps=500, kn=1e-3, planar=False, seed=1, rank_time=False, pair_random=False,
+        free=False):
+    """free: no collisions (sigma = 0), the free-streaming limit of Sec. 5."""
     from oracle import analytic as A
     from paper_1210_8084_amd import workloads as W
     if planar:
         w = W.sod2d(n=n, ncell=1000, nobin=200, dt=1.134e-4, kn=kn, seed=seed)
     else:
         w = W.sod(n=n, ncell=1000, nobin=200, dt=1.134e-4, kn=kn, seed=seed)
+    if free:
+        w.params["sigma"] = 0.0
     f = 2 if planar else 3
     r = _run(w, precision, steps, progress=100, rank_time=rank_time, pair_random=pair_random)
     t = steps * w.params["dt"]
@@ -126,13 +130,16 @@ def sod(precision, n=4_000_000, steps=500, kn=1e-3, planar=False, seed=1, rank_t
     q = ps / (nr * tr)
     n2 = nr * (q + (g_ - 1.0) / (g_ + 1.0)) / ((g_ - 1.0) / (g_ + 1.0) * q + 1.0)
     lam = w.info.get("lam", kn)
-    fe = np.arange(x_s - 0.02, x_s + 0.02 + 1e-12, 0.5 * lam)
-    fc, _ = np.histogram(r["state"]["x"], bins=fe)
-    fn = fc / ((fe[1] - fe[0]) * (w.info["side"] if planar else 0.05 * 0.05))
-    width, x_fit = _tanh_width(0.5 * (fe[1:] + fe[:-1]), fn, x_s, nr, n2)
+    width = x_fit = None
+    if not free and lam <= 4e-3:  # at least ten bins in the window; no front to fit without collisions
+        fe = np.arange(x_s - 0.02, x_s + 0.02 + 1e-12, 0.5 * lam)
+        fc, _ = np.histogram(r["state"]["x"], bins=fe)
+        fn = fc / ((fe[1] - fe[0]) * (w.info["side"] if planar else 0.05 * 0.05))
+        width, x_fit = _tanh_width(0.5 * (fe[1:] + fe[:-1]), fn, x_s, nr, n2)
     return dict(workload=f"{w.name} n={n} kn={kn}", steps=steps, t=t, wall_s=r["wall"],
                 rank="random partners" if pair_random else "contact time" if rank_time else "closest approach",
-                shock_x_exact=x_s, shock_x_fit=x_fit, shock_width=width, shock_width_mfp=width / lam,
+                shock_x_exact=x_s, shock_x_fit=x_fit, shock_width=width,
+                shock_width_mfp=None if width is None else width / lam,
                 l1_density=float(np.mean(np.abs(n_ - rho)) / nl),
                 l1_pressure_kinetic=float(np.mean(np.abs(p_kin - p)) / (nl * tl)),
                 l1_pressure_with_virial=float(np.mean(np.abs(p_tot - p)) / (nl * tl)),
@@ -140,10 +147,15 @@ def sod(precision, n=4_000_000, steps=500, kn=1e-3, planar=False, seed=1, rank_t
                 **_conservation(w, r))
 
 
-def noh(precision, n=8_000_000, steps=800, planar=False, seed=1):
+def noh(precision, n=8_000_000, steps=800, planar=False, seed=1, kn=1e-3, ncell=256, free=False):
+    """ncell below 256 keeps the particles per c-bin of the 8M run at
+    n = 8M (ncell / 256)^2, with dt scaled to move the inflow the same
+    fraction of a c-bin."""
     from oracle import analytic as A
     from paper_1210_8084_amd import workloads as W
-    w = (W.noh2d if planar else W.noh)(n=n, steps=steps, seed=seed)
+    w = (W.noh2d if planar else W.noh)(n=n, steps=steps, seed=seed, kn=kn, ncell=ncell, dt=7.5e-4 * 256 / ncell)
+    if free:
+        w.params["sigma"] = 0.0
     f = 2 if planar else 3
     r = _run(w, precision, steps, progress=200)
     t = steps * w.params["dt"]
@@ -205,10 +217,13 @@ def noh3d(precision, n=8_000_000, steps=160, seed=1):
                 **_conservation(w, r))
 
 
-def sedov(precision, n=16_000_000, steps=600, planar=False, seed=1, rank_time=False, pair_random=False):
+def sedov(precision, n=16_000_000, steps=600, planar=False, seed=1, rank_time=False, pair_random=False,
+          kn=1e-3, free=False):
     from oracle import analytic as A
     from paper_1210_8084_amd import workloads as W
-    w = (W.sedov2d if planar else W.sedov)(n=n, steps=steps, seed=seed)
+    w = (W.sedov2d if planar else W.sedov)(n=n, steps=steps, seed=seed, kn=kn)
+    if free:
+        w.params["sigma"] = 0.0
     r = _run(w, precision, steps, progress=200, rank_time=rank_time, pair_random=pair_random)
     t = steps * w.params["dt"]
     st = r["state"]
@@ -243,6 +258,7 @@ def sedov(precision, n=16_000_000, steps=600, planar=False, seed=1, rank_time=Fa
     lam = w.info.get("lam", 1e-3)
     return dict(workload=f"{w.name} n={n}", steps=steps, t=t, wall_s=r["wall"], r_shock_analytic=R,
                 rank="random partners" if pair_random else "contact time" if rank_time else "closest approach",
+                central_density=float(rho[rc < 0.05].mean()),
                 front_width=width, front_width_mfp=width / lam,
                 r_density_peak=float(rc[peak]), peak_density=float(rho[peak]),
                 l1_density=float(np.mean(np.abs(rho - ra))),
@@ -250,11 +266,95 @@ def sedov(precision, n=16_000_000, steps=600, planar=False, seed=1, rank_time=Fa
                 **_conservation(w, r))
 
 
+# ---------------------------------------------------------------- Sec. 5, Sec. 4.1
+MFP_OVER_DX = (1e-3, 1.0, 10.0, 30.0, 100.0, float("inf"))  # inf: free streaming (sigma = 0)
+
+
+def mfp_sweep(precision, quick=False, problems=("sod2d", "noh2d", "sedov2d")):
+    """The mean-free-path study of Sec. 5: the 2D Sod, Noh and Sedov problems
+    with lambda = 1e-3 (continuum), 1, 10, 30 and 100 c-bin widths and
+    without collisions (free streaming).  Sizes: Sod 1M particles on 1000
+    c-bins (dx = 1e-3), Noh 2M on 128^2 (dx = 1/64, the particles per c-bin
+    of the 8M run), Sedov 4M on 800^2 (dx = 1.25e-3)."""
+    out = {}
+    for name in problems:
+        for m in MFP_OVER_DX:
+            free = m == float("inf")
+            tag = f"{name}_mfp_{'free' if free else f'{m:g}dx'}"
+            print(f"== {tag}", flush=True)
+            if name == "sod2d":
+                kn = (m if not free else 1.0) * 1e-3
+                res = sod(precision, n=250_000 if quick else 1_000_000, steps=500, kn=kn, planar=True, free=free)
+            elif name == "noh2d":
+                kn = (m if not free else 1.0) * 2.0 / 128
+                res = noh(precision, n=500_000 if quick else 2_000_000, steps=400, planar=True, kn=kn, ncell=128,
+                          free=free)
+            else:
+                kn = (m if not free else 1.0) * 1.25e-3
+                res = sedov(precision, n=1_000_000 if quick else 4_000_000, steps=600, planar=True, kn=kn,
+                            free=free)
+            res["lambda_over_dx"] = None if free else m
+            brief = {k: v for k, v in res.items() if not k.startswith(("profile", "analytic_density"))}
+            print(json.dumps(brief), flush=True)
+            out[tag] = res
+    return out
+
+
+def equilibration2d(precision, lam_over_dx, n=20_000_000, ncell=1000, steps=400, sample=200_000, every=2):
+    """Sec. 4.1 in its own setup: N particles of speed 10 in random in-plane
+    directions, periodic [0,4]^2 on ncell^2 c-bins, dt = dx / 60.  Per step:
+    the fraction of particles that collide; every `every` steps, the
+    Kolmogorov-Smirnov distance between the speeds of a fixed subsample and
+    the 2D Maxwell-Boltzmann (Rayleigh) law of the same mean energy,
+    F(v) = 1 - exp(-v^2 / <v^2>)."""
+    import torch
+    from paper_1210_8084_amd import tpkmc as T
+    from paper_1210_8084_amd import workloads as W
+    w = W.equilibration2d(n=n, lam_over_dx=lam_over_dx, ncell=ncell, steps=steps)
+    g, p = w.grid, w.params
+    eng = T.Engine(max_particles=w.n, max_cells=T.ncells(g) + 1, max_obins=T.nobins(g), precision=precision)
+    dst = T.to_device(w.state, precision)
+    cnt = torch.zeros((steps, 8), dtype=torch.int64, device="cuda")
+    idx = torch.arange(0, w.n, max(1, w.n // sample), device="cuda")
+    v2mean = float(np.mean(w.state["vx"] ** 2 + w.state["vy"] ** 2))
+    ks = []
+    t0 = time.perf_counter()
+    for s in range(steps):
+        o = T.DeviceOutputs(counters=cnt[s:s + 1], globals=None, moments=None, pairs=None, pair_cap=0)
+        eng.step(dst, g, dict(p, step=s), o)  # caller order kept: the subsample is the same particles
+        if (s + 1) % every == 0 or s == 0:
+            vx = dst["vx"].index_select(0, idx).double()
+            vy = dst["vy"].index_select(0, idx).double()
+            v = torch.sqrt(vx * vx + vy * vy).cpu().numpy()
+            v.sort()
+            F = 1.0 - np.exp(-v * v / v2mean)
+            emp_hi = np.arange(1, len(v) + 1) / len(v)
+            emp_lo = np.arange(0, len(v)) / len(v)
+            ks.append((s + 1, float(max(np.max(np.abs(emp_hi - F)), np.max(np.abs(emp_lo - F))))))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    c = cnt.cpu().numpy().view(np.uint64)
+    eng.close()
+    frac = 2.0 * c[:, 1].astype(np.float64) / w.n
+    noise = 1.63 / math.sqrt(len(idx))  # KS critical value at the 1% level
+    settled = next((st for st, d in ks if d < 2.0 * noise), None)
+    return dict(workload=f"equilibration2d n={n} ncell={ncell}^2 lambda={lam_over_dx:g}dx", steps=steps,
+                wall_s=wall, collided_fraction_first=float(frac[0]),
+                collided_fraction_mean=float(frac[min(10, steps - 1):].mean()),
+                collided_fraction_last=float(frac[-1]), ks_threshold=2.0 * noise,
+                steps_to_maxwell_boltzmann=settled, ks=[(st, round(d, 4)) for st, d in ks[::5]],
+                particles_conserved=bool(np.all(c[:, 0] == w.n)))
+
+
+KN = None  # Knudsen number of the 3D Sod tube (--kn)
+
+
 def _one(name, prec, quick, seed):
     planar = name.endswith("2d")
     base = name[:-2] if name.endswith(("2d", "3d")) else name
     if base == "sod":
-        return sod(prec, n=400_000 if quick else 4_000_000, steps=100 if quick else 500, planar=planar, seed=seed)
+        return sod(prec, n=400_000 if quick else 4_000_000, steps=100 if quick else 500, planar=planar, seed=seed,
+                   kn=KN if KN is not None else 1e-3)
     if base == "noh" and name.endswith("3d"):
         return noh3d(prec, n=800_000 if quick else 8_000_000, steps=160, seed=seed)
     if base == "noh":
@@ -274,10 +374,30 @@ def main():
                     help="partners by closest approach against by earliest contact and against random "
                     "partners inside each c-bin (FP32): collided fraction, L1 density and shock width of the "
                     "Sod tube and the Sedov blast")
+    ap.add_argument("--mfp-sweep", action="store_true",
+                    help="Sec. 5: 2D Sod, Noh and Sedov at lambda = 1e-3, 1, 10, 30, 100 c-bin widths and "
+                         "free streaming (FP32)")
+    ap.add_argument("--equilibration", action="store_true",
+                    help="Sec. 4.1: 2D equilibration at lambda = 1e-3, 1 and 10 c-bin widths (FP32)")
+    ap.add_argument("--kn", type=float, default=None, help="Knudsen number of the 3D Sod tube (--only sod)")
     args = ap.parse_args()
     from paper_1210_8084_amd import tpkmc as T
     seeds = [int(v) for v in args.seeds.split(",")]
     report = {}
+    if args.mfp_sweep or args.equilibration:
+        if args.equilibration:
+            for m in (1e-3, 1.0, 10.0):
+                print(f"== equilibration2d lambda={m:g}dx", flush=True)
+                res = equilibration2d(T.FP32, m, n=2_000_000 if args.quick else 20_000_000,
+                                      ncell=316 if args.quick else 1000)
+                report[f"equilibration2d_{m:g}dx"] = res
+                print(json.dumps(res), flush=True)
+        if args.mfp_sweep:
+            report.update(mfp_sweep(T.FP32, quick=args.quick))
+        if args.out:
+            with open(args.out, "w") as f:
+                json.dump(report, f, indent=1)
+        return
     if args.rank_compare:
         keys = ("rank", "collided_fraction", "l1_density", "shock_width_mfp", "front_width_mfp", "peak_density",
                 "energy_rel_drift")
@@ -296,6 +416,8 @@ def main():
             with open(args.out, "w") as f:
                 json.dump(report, f, indent=1)
         return
+    global KN
+    KN = args.kn
     for name in args.only.split(","):
         diffs, l1 = [], {"fp32": [], "fp64": []}
         for seed in seeds:
