@@ -168,7 +168,15 @@ enum { TPKMC_G_PX = 0, TPKMC_G_EKIN = 3, TPKMC_G_VMAX2 = 4, TPKMC_G_VIRIAL = 5, 
  *  momentum change; 10 number of colliders; 11 sum m (count x mass for a
  *  scalar mass, rounded once).  Pressure of a bin of
  *  volume V: p = (sum_a [4+a] + sum_a [7+a]) / (3 V); temperature
- *  T = sum_a [4+a] / (3 count). */
+ *  T = sum_a [4+a] / (3 count).
+ *  The sums are exact and independent of the order of the particles: each
+ *  term is rounded once to an integer multiple of 2^-50 times the power of
+ *  two just above the largest term of its kind in that o-bin and step, the
+ *  integers are added exactly, and the total is rounded to double; equal
+ *  inputs give bit-identical moments whatever the launch shape, batch or
+ *  particle order.  Velocities enter relative to a per-o-bin shift (the
+ *  bin's previous mean), so the spread is not the difference of large
+ *  sums. */
 #define TPKMC_MOMENT_STRIDE 12
 
 typedef struct tpkmc_handle tpkmc_handle;
@@ -257,8 +265,8 @@ int tpkmc_version(void);
 const char* tpkmc_strerror(int code);
 
 /* Allocates a handle and all its device scratch on cfg->device (memory is
- * sized from the capacities: about 60 B per particle in FP32, 88 B in FP64,
- * 8 B per c-bin, 24 B per o-bin).  *out is NULL on failure. */
+ * sized from the capacities: about 73 B per particle in FP32, 113 B in FP64,
+ * 8 B per c-bin, 216 B per o-bin).  *out is NULL on failure. */
 int tpkmc_create(const tpkmc_config* cfg, tpkmc_handle** out);
 
 /* Waits for the handle's work, frees everything.  NULL is a no-op. */
@@ -284,9 +292,9 @@ int tpkmc_step(tpkmc_handle* h, const tpkmc_grid* g, const tpkmc_params* p,
  *              default launch shape (2 records per lane, 64 lanes), so the
  *              results equal those of tpkmc_step on a new handle.
  * Returns TPKMC_ECAPACITY, before anything is launched, when the step's
- * scratch exceeds the array: about 81 B per particle in FP64 (89 with
- * per-particle masses), 57 B in FP32 (61), plus 4 B per c-bin and 24 B per
- * o-bin, so at most about 0.8M particles in FP64 and 1.1M in FP32.
+ * scratch exceeds the array: about 105 B per particle in FP64 (113 with
+ * per-particle masses), 69 B in FP32 (73), plus 4 B per c-bin and 216 B per
+ * o-bin, so at most about 0.6M particles in FP64 and 0.9M in FP32.
  * Every call on a GPU uses that GPU's one array, and the array keeps the
  * last call's contents (the call clears what must start at zero), so calls
  * that overlap in time on one GPU race: order them on one stream.  There

@@ -23,13 +23,13 @@ constexpr int kPhases = 8;
 enum Phase { PH_CLEAR = 0, PH_KEY, PH_SCAN, PH_SCATTER, PH_SEARCH, PH_MOVE, PH_FINAL };
 
 // ---------------------------------------------------------------- kernels
-__global__ void k_clear(int32_t* start, int64_t ncell, double* moments, int64_t nmom,
+__global__ void k_clear(int32_t* start, int64_t ncell, unsigned long long* macc, int64_t nwords,
                         unsigned long long* pair_count) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (int64_t t = t0; t < ncell; t += stride) start[t] = 0;
-    if (moments)
-        for (int64_t t = t0; t < nmom; t += stride) moments[t] = 0.0;
+    if (macc)
+        for (int64_t t = t0; t < nwords; t += stride) macc[t] = 0ull;
     if (t0 == 0) *pair_count = 0ull;
 }
 
@@ -224,12 +224,30 @@ __global__ void __launch_bounds__(256) k_finalize(Inst<real>* inst, const double
     if (advance_step) I.step_lo += 1u;
 }
 
-// Shifted o-bin sums -> momentum and central second moments; the bin mean
-// becomes the shift of the next step, so the sums stay small next time.
-// Each work-group (256 threads) stages the rows of its 256 o-bins through
-// LDS, so the loads and stores are coalesced.
+// Exact shifted o-bin sums -> the moments of the output: momentum and central
+// second moments; the bin mean becomes the shift of the next step, so the
+// sums stay small next time.  Each sum is converted to double by an
+// error-free sum of its top parts plus the rest (the result is within an
+// ulp of the exact sum, and a function of it only).
+// Each work-group (256 threads) stages its 256 o-bins' output rows through
+// LDS, so the stores are coalesced; every output value is written.
+__device__ __forceinline__ double fx_to_double(unsigned long long lo, long long hi, double inv_scale) {
+    // The exact value hi 2^32 + lo as hh 2^64 + (hl + lh) 2^32 + ll, three
+    // exactly representable parts.
+    const long long hh = hi >> 32;
+    const unsigned long long mid = (unsigned long long)(uint32_t)hi + (lo >> 32);
+    const double a = (double)hh * 0x1p64;
+    const double b = (double)mid * 0x1p32;
+    const double c = (double)(uint32_t)lo;
+    const double s = a + b;  // and its rounding error, exactly
+    const double bp = s - a;
+    const double e = (a - (s - bp)) + (b - bp);
+    return (s + (e + c)) * inv_scale;
+}
+
 template <typename real>
-__global__ void __launch_bounds__(256) k_moments_final(const Inst<real>* inst, double* moments, double* shift) {
+__global__ void __launch_bounds__(256) k_moments_final(const Inst<real>* inst, const ObAcc* macc, double* moments,
+                                                       double* shift) {
     constexpr int kRows = 256;
     __shared__ double rows[kRows * TPKMC_MOMENT_STRIDE];
     const Inst<real>& I = inst[blockIdx.y];
@@ -237,31 +255,39 @@ __global__ void __launch_bounds__(256) k_moments_final(const Inst<real>* inst, d
     const int64_t b0 = (int64_t)blockIdx.x * kRows;
     if (b0 >= nb) return;  // whole work-group
     const int nloc = (int)min<int64_t>(kRows, nb - b0);
-    double* M0 = moments + (I.obin_off + b0) * TPKMC_MOMENT_STRIDE;
-    for (int t = threadIdx.x; t < nloc * TPKMC_MOMENT_STRIDE; t += kRows) rows[t] = M0[t];
-    __syncthreads();
     if ((int)threadIdx.x < nloc) {
+        const int64_t ob = I.obin_off + b0 + threadIdx.x;
+        const ObAcc& A = macc[ob];
         double* M = rows + threadIdx.x * TPKMC_MOMENT_STRIDE;
-        double* S = shift + (I.obin_off + b0 + threadIdx.x) * 3;
-        const double cnt = M[0];
-        if (cnt > 0.0) {
-            // Without per-particle masses the move leaves the mass sum out.
-            const double mass = (I.flags & kHasMass) ? M[11] : cnt * I.mass_d;
-            M[11] = mass;
-            for (int a = 0; a < 3; ++a) {
-                const double s1 = M[1 + a], s2 = M[4 + a];
-                const double mean_off = s1 / mass;
-                M[1 + a] = s1 + mass * S[a];
-                M[4 + a] = fmax(s2 - s1 * mean_off, 0.0);
-                S[a] = S[a] + mean_off;
+        double* S = shift + ob * 3;
+        const unsigned long long cnt = A.cnt;
+        for (int k = 0; k < TPKMC_MOMENT_STRIDE; ++k) M[k] = 0.0;
+        if (cnt > 0) {
+            double inv[4];  // quanta 2^(E-50) of the four kinds (as in the moment pass)
+            for (int k = 0; k < 4; ++k) {
+                const int e = A.e[k] > 0 ? A.e[k] - kExpBias : 0;
+                inv[k] = ldexp(1.0, max(e, -969) - 50);
             }
+            double v[kAccVals];
+            for (int k = 0; k < kAccVals; ++k) v[k] = fx_to_double(A.lo[k], A.hi[k], inv[acc_kind(k)]);
+            // Without per-particle masses the moment pass leaves the mass sum out.
+            const double mass = (I.flags & kHasMass) ? v[9] : (double)cnt * I.mass_d;
+            M[0] = (double)cnt;
+            for (int ax = 0; ax < 3; ++ax) {
+                const double s1 = v[ax], s2 = v[3 + ax];
+                const double mean_off = s1 / mass;
+                M[1 + ax] = s1 + mass * S[ax];
+                M[4 + ax] = fmax(s2 - s1 * mean_off, 0.0);
+                M[7 + ax] = v[6 + ax];
+                S[ax] = S[ax] + mean_off;
+            }
+            M[10] = (double)A.coll;
+            M[11] = mass;
         }
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < nloc * TPKMC_MOMENT_STRIDE; t += kRows) {
-        const int k = t % TPKMC_MOMENT_STRIDE;
-        if ((k >= 1 && k <= 6) || k == 11) M0[t] = rows[t];
-    }
+    double* M0 = moments + (I.obin_off + b0) * TPKMC_MOMENT_STRIDE;
+    for (int t = threadIdx.x; t < nloc * TPKMC_MOMENT_STRIDE; t += kRows) M0[t] = rows[t];
 }
 
 // Tables of the allocation-free entry point, written on the device so that
@@ -297,6 +323,9 @@ struct Buffers {
     Chunk* chunks;
     unsigned long long* bkey;
     double *gpart, *cpart, *shift;
+    ObAcc* macc;      // exact o-bin sums, 192 B per o-bin
+    void* vir;        // colliders' virial terms, 3 reals per particle
+    uint8_t* coll;    // collided flags, 1 B per particle
     unsigned long long* pair_count;
     uint32_t* status;
     unsigned long long* mix;  // counters of tpkmc_search_mix (handles only)
@@ -550,6 +579,9 @@ StepArgs<real> make_args(const Buffers& B, const tpkmc_particles* s, const tpkmc
     a.bkey = B.bkey;
     a.gpart = B.gpart;
     a.shift = B.shift;
+    a.macc = (o && o->moments) ? B.macc : nullptr;
+    a.vir = (real*)B.vir;
+    a.coll = B.coll;
     a.pairs = o ? o->pairs : nullptr;
     a.pair_cap = (o && o->pairs) ? o->pair_cap : 0;
     a.pair_count = B.pair_count;
@@ -585,18 +617,19 @@ template <typename real>
 void enqueue_step(tpkmc_handle* h, const Buffers& B, const StepArgs<real>& a, const tpkmc_outputs* o,
                   const Shape& P, int search_block, int search_group, hipStream_t s, bool prof,
                   int advance_step) {
-    const int64_t nmom = (o && o->moments) ? P.nob_tot * TPKMC_MOMENT_STRIDE : 0;
+    const bool mom = o && o->moments;
+    const int64_t nwords = mom ? P.nob_tot * (int64_t)(sizeof(ObAcc) / 8) : 0;
     {
         PhaseScope ps(h, PH_CLEAR, s, prof);
-        const int64_t work = std::max<int64_t>(P.ncell_tot + 1, nmom);
+        const int64_t work = std::max<int64_t>(P.ncell_tot + 1, nwords);
         const int64_t grid = std::min<int64_t>((work + 255) / 256, 4096);
         hipLaunchKernelGGL(k_clear, dim3((unsigned)std::max<int64_t>(grid, 1)), dim3(256), 0, s, B.start,
-                           P.ncell_tot + 1, nmom ? o->moments : nullptr, nmom, B.pair_count);
+                           P.ncell_tot + 1, mom ? (unsigned long long*)B.macc : nullptr, nwords, B.pair_count);
     }
     if (P.nblk > 0) {
         PhaseScope ps(h, PH_KEY, s, prof);
         launch_key<real>(a, s);
-        if (P.adaptive) launch_adapt_dt<real>((Inst<real>*)B.inst, B.gpart, P.n_inst, s);
+        if (P.adaptive) launch_prep<real>((Inst<real>*)B.inst, B.gpart, P.n_inst, P.nblk, s);
     }
     {
         PhaseScope ps(h, PH_SCAN, s, prof);
@@ -615,6 +648,7 @@ void enqueue_step(tpkmc_handle* h, const Buffers& B, const StepArgs<real>& a, co
         {
             PhaseScope ps(h, PH_MOVE, s, prof);
             launch_move<real>(a, s);
+            if (mom) launch_moments<real>(a, s);
         }
     }
     {
@@ -625,10 +659,10 @@ void enqueue_step(tpkmc_handle* h, const Buffers& B, const StepArgs<real>& a, co
         hipLaunchKernelGGL(k_finalize<real>, dim3(P.n_inst), dim3(256), 0, s, (Inst<real>*)B.inst, B.cpart,
                            o ? o->counters : nullptr, o ? o->globals : nullptr, B.status, B.pair_count,
                            a.pair_cap, advance_step);
-        if (nmom) {
+        if (mom && P.max_nob > 0) {
             const unsigned gx = (unsigned)((P.max_nob + 255) / 256);
             hipLaunchKernelGGL(k_moments_final<real>, dim3(gx, P.n_inst), dim3(256), 0, s,
-                               (const Inst<real>*)B.inst, o->moments, B.shift);
+                               (const Inst<real>*)B.inst, (const ObAcc*)B.macc, o->moments, B.shift);
         }
     }
 }
@@ -729,10 +763,10 @@ int tune_impl(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* i
     tpkmc_outputs none{};
     StepArgs<real> a = make_args<real>(h->b, s, &none, P.nblk);
     // Bin once (clear, key, prefix, scatter); then time only the search.
-    hipLaunchKernelGGL(k_clear, dim3(1024), dim3(256), 0, st, h->b.start, P.ncell_tot + 1, (double*)nullptr,
-                       (int64_t)0, h->b.pair_count);
+    hipLaunchKernelGGL(k_clear, dim3(1024), dim3(256), 0, st, h->b.start, P.ncell_tot + 1,
+                       (unsigned long long*)nullptr, (int64_t)0, h->b.pair_count);
     launch_key<real>(a, st);
-    if (P.adaptive) launch_adapt_dt<real>((Inst<real>*)h->b.inst, h->b.gpart, P.n_inst, st);
+    if (P.adaptive) launch_prep<real>((Inst<real>*)h->b.inst, h->b.gpart, P.n_inst, P.nblk, st);
     enqueue_scan(h->b, P.ncell_tot + 1, st);
     launch_scatter<real>(a, st);
     hipEvent_t e0, e1;
@@ -789,10 +823,10 @@ int mix_impl(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* in
     if ((rc = upload(h, P, st))) return rc;
     tpkmc_outputs none{};
     StepArgs<real> a = make_args<real>(h->b, s, &none, P.nblk);
-    hipLaunchKernelGGL(k_clear, dim3(1024), dim3(256), 0, st, h->b.start, P.ncell_tot + 1, (double*)nullptr,
-                       (int64_t)0, h->b.pair_count);
+    hipLaunchKernelGGL(k_clear, dim3(1024), dim3(256), 0, st, h->b.start, P.ncell_tot + 1,
+                       (unsigned long long*)nullptr, (int64_t)0, h->b.pair_count);
     launch_key<real>(a, st);
-    if (P.adaptive) launch_adapt_dt<real>((Inst<real>*)h->b.inst, h->b.gpart, P.n_inst, st);
+    if (P.adaptive) launch_prep<real>((Inst<real>*)h->b.inst, h->b.gpart, P.n_inst, P.nblk, st);
     enqueue_scan(h->b, P.ncell_tot + 1, st);
     launch_scatter<real>(a, st);
     if (hipMemsetAsync(h->b.mix, 0, 3 * sizeof(unsigned long long), st) != hipSuccess) return TPKMC_EHIP;
@@ -819,7 +853,7 @@ void free_all(tpkmc_handle* h) {
     }
     hipFree(h->b.rank); hipFree(h->b.start); hipFree(h->b.tiles);
     hipFree(h->b.src); hipFree(h->b.best); hipFree(h->b.perm); hipFree(h->b.rec); hipFree(h->b.rmass); hipFree(h->b.inst);
-    hipFree(h->b.blk); hipFree(h->b.chunks); hipFree(h->b.bkey); hipFree(h->b.cpart); hipFree(h->b.gpart); hipFree(h->b.shift); hipFree(h->b.pair_count); hipFree(h->b.status); hipFree(h->b.mix);
+    hipFree(h->b.blk); hipFree(h->b.chunks); hipFree(h->b.bkey); hipFree(h->b.cpart); hipFree(h->b.gpart); hipFree(h->b.shift); hipFree(h->b.macc); hipFree(h->b.vir); hipFree(h->b.coll); hipFree(h->b.pair_count); hipFree(h->b.status); hipFree(h->b.mix);
 }
 
 // ---------------------------------------------------------------- static scratch
@@ -873,6 +907,9 @@ size_t carve(uintptr_t base, int64_t n, int64_t ncell_tot, int64_t nob, int nblk
     B.chunks = (Chunk*)take(sizeof(Chunk) * (size_t)nchunk);
     B.cpart = (double*)take(sizeof(double) * kGPart * (size_t)nchunk);
     B.shift = (double*)take(sizeof(double) * 3 * (size_t)std::max<int64_t>(nob, 1));
+    B.macc = (ObAcc*)take(sizeof(ObAcc) * (size_t)std::max<int64_t>(nob, 1));
+    B.vir = take(3 * sizeof(real) * nn);
+    B.coll = (uint8_t*)take(nn);
     B.pair_count = (unsigned long long*)take(sizeof(unsigned long long));
     B.status = (uint32_t*)take(sizeof(uint32_t));
     return off;
@@ -986,6 +1023,9 @@ int tpkmc_create(const tpkmc_config* cfg, tpkmc_handle** out) {
     bad |= dalloc(&h->b.cpart, h->max_chunks * kGPart);
     if (cfg->precision == TPKMC_FP32) bad |= dalloc(&h->b.bkey, h->max_n);
     bad |= dalloc(&h->b.shift, 3 * std::max<int64_t>(h->max_obins, 1));
+    bad |= dalloc(&h->b.macc, std::max<int64_t>(h->max_obins, 1));
+    bad |= hipMalloc(&h->b.vir, rs * 3 * (size_t)std::max<int64_t>(h->max_n, 1)) != hipSuccess;
+    bad |= dalloc(&h->b.coll, std::max<int64_t>(h->max_n, 1));
     bad |= dalloc(&h->b.pair_count, 1);
     bad |= dalloc(&h->b.mix, 3);
     bad |= dalloc(&h->b.status, 1);

@@ -21,6 +21,31 @@ enum GPart {
     GP_FAST, GP_NONFINITE, GP_VMAX0, kGPart
 };
 
+// Exact o-bin sums, in two passes over the particles.  The move records,
+// per o-bin and kind of term, the exponent E of a power of two above every
+// term (|x| < 2^E, an integer maximum, so the order does not matter).  The
+// moment pass then rounds each term once to an integer q, a multiple of
+// 2^(E-50) (|q| < 2^50): a work-group sums its at most 2048 terms per o-bin
+// in one int64 per value, and the global sums split each work-group sum S
+// into its low 32-bit digit (S mod 2^32) and the signed rest S >> 32,
+// summed in separate 64-bit words: 2^32 work-group sums fit, no carry
+// passes between the words, and integer sums do not depend on the order of
+// the terms.  Kinds: 0 m (v - shift) per axis, 1 m (v - shift)^2 per axis,
+// 2 virial terms, 3 mass.  Per o-bin: values 0..2 momentum, 3..5 spread,
+// 6..8 virial, 9 mass (per-particle masses only), the particle and
+// collider counts, and the four exponents (biased by kExpBias; 0: no
+// nonzero term).
+constexpr int kAccVals = 10;
+constexpr int kExpBias = 1100;
+struct ObAcc {
+    unsigned long long lo[kAccVals];  // sums of the low digits
+    long long hi[kAccVals];           // sums of the high parts
+    unsigned long long cnt, coll;
+    int32_t e[4];
+};
+static_assert(sizeof(ObAcc) == 192, "one o-bin accumulator is 192 B");
+__host__ __device__ constexpr int acc_kind(int k) { return k < 3 ? 0 : k < 6 ? 1 : k < 9 ? 2 : 3; }
+
 // Instance descriptor on the device.  Derived grid quantities are computed
 // on the host in double, exactly like the CPU oracle, then cast to `real`.
 template <typename real>
@@ -41,6 +66,11 @@ struct Inst {
     double mass_d, dt_d;      // dt_d: this step's time step (set on the device with ADAPTIVE_DT)
     double dt_cap, dx_d;      // caller's dt; smallest c-bin width over axes with > 1 c-bin (0: none)
     double sigma_d, cellvol_d; // cross section; c-bin volume (area in the plane), for random partners
+    // Adaptive time step: running maximum of |v|^2 (bit pattern of a
+    // non-negative double) and the count of prep work-groups done; the last
+    // one to finish resets both.
+    unsigned long long run_v2;
+    uint32_t prep_done;
 };
 
 // Bit of Inst::flags, set by the host (outside the public flag bits): the
@@ -83,6 +113,9 @@ struct StepArgs {
     unsigned long long* bkey; // record -> (d_min^2 bits, partner record) (FP32 search)
     double* gpart;            // [nblk][kGPart]
     double* shift;            // per-o-bin velocity shift (3 per o-bin)
+    ObAcc* macc;              // per-o-bin exact sums, or null (no moments)
+    real* vir;                // virial terms of each collider (3 per particle, caller index)
+    uint8_t* coll;            // 1 if the particle collided this step (caller index)
     unsigned long long* mix;  // search mix counters (tests, s0 < 0, s0 < 0 < s1), or null
     // outputs
     uint32_t* pairs;
@@ -94,10 +127,12 @@ struct StepArgs {
 // Launchers implemented per precision (tpkmc_f32.hip / tpkmc_f64.hip).
 template <typename real> void launch_key(const StepArgs<real>& a, hipStream_t s);
 template <typename real> void launch_scatter(const StepArgs<real>& a, hipStream_t s);
-template <typename real> void launch_adapt_dt(Inst<real>* inst, const double* gpart, int n_inst, hipStream_t s);
+template <typename real> void launch_prep(Inst<real>* inst, const double* gpart, int n_inst, int max_nblk,
+                                         hipStream_t s);
 template <typename real> void launch_search(const StepArgs<real>& a, int block, int group, hipStream_t s);
 template <typename real> void launch_search_mix(const StepArgs<real>& a, int block, hipStream_t s);
 template <typename real> void launch_move(const StepArgs<real>& a, hipStream_t s);
+template <typename real> void launch_moments(const StepArgs<real>& a, hipStream_t s);
 template <typename real> void launch_random_pairs(const StepArgs<real>& a, hipStream_t s);
 
 }  // namespace tpkmc

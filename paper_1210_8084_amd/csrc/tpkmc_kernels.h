@@ -1154,17 +1154,81 @@ __device__ __forceinline__ int obin_of(const Inst<real>& I, real x, real y, real
     return (int)(I.obin_off + bx + (int64_t)I.no[0] * (by + (int64_t)I.no[1] * bz));
 }
 
-// Work-group table of o-bin sums, flushed with one atomic per value per bin.
-constexpr int kSlots = 64;
+// ------------------------------------------------------- exact o-bin sums
+// The moment terms of one particle (kinds as in ObAcc), computed the same
+// way in both passes: m (v - shift), m (v - shift)^2, the virial terms and
+// the mass.
+__device__ __forceinline__ void moment_terms(double m, double vx, double vy, double vz, const double* S,
+                                             double virx, double viry, double virz, double t[kAccVals]) {
+    const double ex = vx - S[0], ey = vy - S[1], ez = vz - S[2];
+    t[0] = m * ex; t[1] = m * ey; t[2] = m * ez;
+    t[3] = t[0] * ex; t[4] = t[1] * ey; t[5] = t[2] * ez;
+    t[6] = virx; t[7] = viry; t[8] = virz;
+    t[9] = m;
+}
+
+// Biased exponent E + kExpBias of the smallest power of two 2^E > |x| (0 for
+// x = 0).
+__device__ __forceinline__ int exp_above(double x) {
+    return x != 0.0 ? ilogb(x) + 1 + kExpBias : 0;
+}
+
+// x rounded to the nearest multiple of 2^(E-50), in units of that quantum;
+// scale = 2^(50-E) and |x| < 2^E, so |x scale| < 2^50.  Adding 1.5 2^52
+// rounds x scale to an integer (nearest, ties to even; the product is exact)
+// and leaves that integer plus 2^51 in the low mantissa bits.
+__device__ __forceinline__ long long to_fixed(double x, double scale) {
+    constexpr double kMagic = 6755399441055744.0;  // 1.5 * 2^52
+    return __double_as_longlong(fma(x, scale, kMagic)) - 0x4338000000000000ll;
+}
+
+// 2^(50-E) for a biased exponent, kept a normal double.
+__device__ __forceinline__ double fixed_scale(int eb) {
+    const int e = eb > 0 ? eb - kExpBias : 0;
+    return ldexp(1.0, 50 - max(e, -969));
+}
+
+template <int CTRL>
+__device__ __forceinline__ long long dpp_move64(long long v) {
+    const uint32_t l0 = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)v, CTRL, 0xF, 0xF, false);
+    const uint32_t l1 = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)((unsigned long long)v >> 32), CTRL,
+                                                           0xF, 0xF, false);
+    return (long long)(((unsigned long long)l1 << 32) | l0);
+}
+
+// Adds one work-group (or lane) sum of a value to the global sums of an
+// o-bin: the low digit and the rest into separate words (see ObAcc).
+__device__ __forceinline__ void global_acc_add(ObAcc& G, int k, long long v) {
+    if (v == 0) return;
+    const unsigned long long lo = (uint32_t)v;
+    const long long hi = v >> 32;
+    if (lo) atomicAdd(&G.lo[k], lo);
+    if (hi) atomicAdd((unsigned long long*)&G.hi[k], (unsigned long long)hi);
+}
+
+// Work-group tables keyed by o-bin (open addressing), flushed to the global
+// accumulators once per work-group: exponent maxima in the move, value sums
+// in the moment pass.
+constexpr int kSlots = 64;       // exponent table (the move's 256 records)
+constexpr int kMomSlots = 64;    // value table (the moment pass's 256 records)
+constexpr int kTabWords = kAccVals + 2;  // values, particle count, collider count
 struct MomentTable {
-    int key[kSlots];
-    double val[kSlots][TPKMC_MOMENT_STRIDE];
+    static constexpr int kN = kMomSlots;
+    int key[kN];
+    long long val[kN][kTabWords];
+};
+struct ExpTable {
+    static constexpr int kN = kSlots;
+    int key[kN];
+    int e[kN][4];
 };
 
-__device__ __forceinline__ int table_slot(MomentTable& T, int ob) {
-    int h = (ob * 0x9E3779B1u) >> 25;  // 7 bits
-    for (int probe = 0; probe < kSlots; ++probe) {
-        const int s = (h + probe) & (kSlots - 1);
+template <typename Table>
+__device__ __forceinline__ int table_slot(Table& T, int ob) {
+    constexpr int N = Table::kN;
+    const int h = (int)((ob * 0x9E3779B1u) >> 24);  // 8 bits
+    for (int probe = 0; probe < N; ++probe) {
+        const int s = (h + probe) & (N - 1);
         const int cur = T.key[s];
         if (cur == ob) return s;
         if (cur == -1) {
@@ -1175,61 +1239,107 @@ __device__ __forceinline__ int table_slot(MomentTable& T, int ob) {
     return -1;
 }
 
+// Runs of one o-bin across the lanes of a wave: whether this lane starts
+// one, and lim = the lanes of its run inside its row of 16 lanes, from this
+// lane on (for a segmented maximum by DPP row shifts of 1, 2, 4 and 8).
+__device__ __forceinline__ int row_lim(int mob, int lane, bool& head) {
+    const int prev_mob = __shfl_up(mob, 1);
+    head = lane == 0 || prev_mob != mob;
+    const uint64_t heads = __ballot(head);
+    const uint64_t after = heads & ~lanes_le(lane);
+    const int seg1 = after ? __ffsll((long long)after) - 1 : 64;
+    const int rl = lane & 15;
+    return min(seg1, lane - rl + 16) - lane;
+}
+
+__device__ __forceinline__ long long row_sum64(long long v, int lim) {
+    long long u = dpp_move64<kRowShl1>(v);
+    if (1 < lim) v += u;
+    u = dpp_move64<kRowShl2>(v);
+    if (2 < lim) v += u;
+    u = dpp_move64<kRowShl4>(v);
+    if (4 < lim) v += u;
+    u = dpp_move64<kRowShl8>(v);
+    if (8 < lim) v += u;
+    return v;
+}
+
+__device__ __forceinline__ uint32_t row_sum32(uint32_t v, int lim) {
+    uint32_t u = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kRowShl1, 0xF, 0xF, false);
+    if (1 < lim) v += u;
+    u = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kRowShl2, 0xF, 0xF, false);
+    if (2 < lim) v += u;
+    u = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kRowShl4, 0xF, 0xF, false);
+    if (4 < lim) v += u;
+    u = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, kRowShl8, 0xF, 0xF, false);
+    if (8 < lim) v += u;
+    return v;
+}
+
+__device__ __forceinline__ int row_max32(int v, int lim) {
+    int u = __builtin_amdgcn_mov_dpp(v, kRowShl1, 0xF, 0xF, false);
+    if (1 < lim) v = max(v, u);
+    u = __builtin_amdgcn_mov_dpp(v, kRowShl2, 0xF, 0xF, false);
+    if (2 < lim) v = max(v, u);
+    u = __builtin_amdgcn_mov_dpp(v, kRowShl4, 0xF, 0xF, false);
+    if (4 < lim) v = max(v, u);
+    u = __builtin_amdgcn_mov_dpp(v, kRowShl8, 0xF, 0xF, false);
+    if (8 < lim) v = max(v, u);
+    return v;
+}
+
 // Unambiguous pairs (each the other's closest candidate) scatter; every
-// particle moves and meets the walls; o-bin moments and global sums.  Each
-// lane takes kMoveRec consecutive records: records in c-bin order come in
-// runs of one o-bin, so a lane sums its run in registers and touches the
+// particle moves and meets the walls; global sums; with moments, the first
+// pass of the exact o-bin sums (see ObAcc): the exponent maxima, and each
+// particle's collider flag and virial terms for the moment pass.  Each lane
+// takes kMoveRec consecutive records: records in c-bin order come in runs of
+// one o-bin, so a lane keeps its run's maxima in registers and touches the
 // work-group's o-bin table only when the o-bin changes, and the global sums
-// are reduced once per kMoveRec records.  The next record is loaded while the
-// current one is processed.  Two records per lane balance these savings
+// are reduced once per kMoveRec records.  The next record is loaded while
+// the current one is processed.  Two records per lane balance these savings
 // against the coalescing and occupancy of one record per lane.
 constexpr int kMoveRec = 2;
 constexpr int kMoveLanes = kBlock / kMoveRec;
 
-// The table and the global fallback are written on separate paths, so the
-// table's adds stay LDS atomics (one pointer for both would make every add a
-// generic-address atomic).  Zero values are skipped: the virial and collider
-// count outside collisions, the mass sum without per-particle masses (the
-// finalisation takes count x mass), the z terms in the plane.
+// A lane's run maxima of one o-bin into the work-group table, or straight
+// into the global accumulators when the table is full.
 template <typename real>
-__device__ __forceinline__ void moment_flush(MomentTable& tab, const StepArgs<real>& a, int ob, const double* mv) {
+__device__ __forceinline__ void exp_flush(ExpTable& tab, const StepArgs<real>& a, int ob, const int* e) {
     const int slot = table_slot(tab, ob);
-    if (slot >= 0) {
+    int* d = slot >= 0 ? tab.e[slot] : nullptr;
 #pragma unroll
-        for (int k = 0; k < TPKMC_MOMENT_STRIDE; ++k)
-            if (mv[k] != 0.0) unsafeAtomicAdd(&tab.val[slot][k], mv[k]);
-    } else {
-        double* dst = a.moments + (int64_t)ob * TPKMC_MOMENT_STRIDE;
-#pragma unroll
-        for (int k = 0; k < TPKMC_MOMENT_STRIDE; ++k)
-            if (mv[k] != 0.0) unsafeAtomicAdd(dst + k, mv[k]);
+    for (int k = 0; k < 4; ++k) {
+        if (!e[k]) continue;
+        if (d) atomicMax(d + k, e[k]);
+        else atomicMax(&a.macc[ob].e[k], e[k]);
     }
 }
 
 template <typename real>
 __global__ void __launch_bounds__(kMoveLanes) k_move(StepArgs<real> a) {
-    __shared__ MomentTable tab;
+    __shared__ ExpTable tab;
     __shared__ double red[kMoveLanes / 64][11];
-    const Blk bt = a.blk[blockIdx.x];
+    // Consecutive work-groups on one XCD: partners' records and keys, a few
+    // c-bins away in record order, are then mostly in that XCD's L2.
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    const Blk bt = a.blk[lb];
     const Inst<real>& I = a.inst[bt.inst];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int64_t end = I.off + I.cnt;
     const bool reorder = (I.flags & TPKMC_ALLOW_REORDER) != 0;
     const bool has_mass = (I.flags & kHasMass) != 0;
-    if (a.moments) {
+    if (a.macc) {
         for (int t = tid; t < kSlots; t += kMoveLanes) {
             tab.key[t] = -1;
-            for (int k = 0; k < TPKMC_MOMENT_STRIDE; ++k) tab.val[t][k] = 0.0;
+            for (int k = 0; k < 4; ++k) tab.e[t][k] = 0;
         }
         __syncthreads();
     }
     double gpx = 0, gpy = 0, gpz = 0, gek = 0, gvm = 0, gvir = 0, gm = 0, galive = 0, gpairs = 0, gabs = 0, ghave = 0;
-    int mob = -1;                              // o-bin of the run being summed
-    double shx = 0, shy = 0, shz = 0;          // its velocity shift
-    double mv[TPKMC_MOMENT_STRIDE];            // its sums
-#pragma unroll
-    for (int k = 0; k < TPKMC_MOMENT_STRIDE; ++k) mv[k] = 0.0;
+    int mob = -1;                              // o-bin of the run
+    double sh[3] = {0.0, 0.0, 0.0};            // its velocity shift
+    int me[4] = {0, 0, 0, 0};                  // its exponent maxima per kind
     // The next record and its partner key are loaded while the current one
     // is processed (two records in flight per lane).
     const int64_t i_first = (int64_t)bt.first + kMoveRec * tid;
@@ -1381,21 +1491,29 @@ __global__ void __launch_bounds__(kMoveLanes) k_move(StepArgs<real> a) {
                     gvir += (virx + viry) + virz;
                     gm += m;
                     galive += 1.0;
-                    if (a.moments) {
+                    if (a.macc) {
                         const int ob = obin_of(I, nx, ny, nz);
                         if (ob != mob) {
-                            if (mob >= 0) moment_flush(tab, a, mob, mv);
+                            if (mob >= 0) exp_flush(tab, a, mob, me);
                             const double* S = a.shift + (int64_t)ob * 3;
-                            shx = S[0]; shy = S[1]; shz = S[2];
+                            sh[0] = S[0]; sh[1] = S[1]; sh[2] = S[2];
                             mob = ob;
 #pragma unroll
-                            for (int k = 0; k < TPKMC_MOMENT_STRIDE; ++k) mv[k] = 0.0;
+                            for (int k = 0; k < 4; ++k) me[k] = 0;
                         }
-                        const double ex = dvx - shx, ey = dvy - shy, ez = dvz - shz;
-                        mv[0] += 1.0; mv[1] += m * ex; mv[2] += m * ey; mv[3] += m * ez;
-                        mv[4] += m * ex * ex; mv[5] += m * ey * ey; mv[6] += m * ez * ez;
-                        mv[7] += virx; mv[8] += viry; mv[9] += virz; mv[10] += mutual ? 1.0 : 0.0;
-                        if (has_mass) mv[11] += m;
+                        double t[kAccVals];
+                        moment_terms(m, dvx, dvy, dvz, sh, virx, viry, virz, t);
+                        me[0] = max(me[0], exp_above(fmax(fmax(fabs(t[0]), fabs(t[1])), fabs(t[2]))));
+                        me[1] = max(me[1], exp_above(fmax(fmax(t[3], t[4]), t[5])));
+                        if (mutual)
+                            me[2] = max(me[2], exp_above(fmax(fmax(fabs(t[6]), fabs(t[7])), fabs(t[8]))));
+                        if (has_mass) me[3] = max(me[3], exp_above(t[9]));
+                        a.coll[dst] = mutual ? 1 : 0;
+                        if (mutual) {
+                            a.vir[3 * dst] = (real)virx;
+                            a.vir[3 * dst + 1] = (real)viry;
+                            a.vir[3 * dst + 2] = (real)virz;
+                        }
                     }
                 }
             }
@@ -1418,42 +1536,21 @@ __global__ void __launch_bounds__(kMoveLanes) k_move(StepArgs<real> a) {
             }
         }
     }
-    if (a.moments) {
+    if (a.macc) {
         // Consecutive lanes hold consecutive records, so their last runs come
-        // in runs of one o-bin across the wave.  Within each row of 16 lanes,
-        // the lanes of one run are first summed into the run's first lane of
-        // the row (a segmented suffix sum by doubling, DPP row shifts of 1, 2,
-        // 4 and 8 lanes), which alone goes through the table.
-        const int prev_mob = __shfl_up(mob, 1);
-        const bool head = lane == 0 || prev_mob != mob;
-        const uint64_t heads = __ballot(head);
-        const uint64_t after = heads & ~lanes_le(lane);
-        const int seg1 = after ? __ffsll((long long)after) - 1 : 64;
-        const int rl = lane & 15;
-        const int lim = min(seg1, lane - rl + 16) - lane;  // lanes of my run in my row, from me on
-        const bool coll = __ballot(mv[7] != 0.0 || mv[8] != 0.0 || mv[9] != 0.0 || mv[10] != 0.0) != 0;
+        // in runs of one o-bin across the wave: within each row of 16 lanes
+        // the run's maxima go to its first lane, which alone goes through the
+        // table; then the table goes to the global maxima.
+        bool head;
+        const int lim = row_lim(mob, lane, head);
 #pragma unroll
-        for (int k = 0; k < TPKMC_MOMENT_STRIDE; ++k) {
-            if ((k >= 7 && k <= 10 && !coll) || (k == 11 && !has_mass)) continue;  // wave-uniform
-            double v = mv[k];
-            double u = dpp_move<kRowShl1>(v);
-            if (1 < lim) v += u;
-            u = dpp_move<kRowShl2>(v);
-            if (2 < lim) v += u;
-            u = dpp_move<kRowShl4>(v);
-            if (4 < lim) v += u;
-            u = dpp_move<kRowShl8>(v);
-            if (8 < lim) v += u;
-            mv[k] = v;
-        }
-        if ((head || rl == 0) && mob >= 0) moment_flush(tab, a, mob, mv);
+        for (int k = 0; k < 4; ++k) me[k] = row_max32(me[k], lim);
+        if ((head || (lane & 15) == 0) && mob >= 0) exp_flush(tab, a, mob, me);
         __syncthreads();
-        for (int t = tid; t < kSlots; t += kMoveLanes) {
-            const int ob = tab.key[t];
-            if (ob < 0) continue;
-            double* M = a.moments + (int64_t)ob * TPKMC_MOMENT_STRIDE;
-            for (int k = 0; k < TPKMC_MOMENT_STRIDE; ++k)
-                if (tab.val[t][k] != 0.0) unsafeAtomicAdd(M + k, tab.val[t][k]);
+        for (int t = tid; t < kSlots * 4; t += kMoveLanes) {
+            const int slot = t >> 2, k = t & 3;
+            const int ob = tab.key[slot];
+            if (ob >= 0 && tab.e[slot][k]) atomicMax(&a.macc[ob].e[k], tab.e[slot][k]);
         }
     }
     double v[11] = {gpx, gpy, gpz, gek, gvm, gvir, gm, galive, gpairs, gabs, ghave};
@@ -1470,26 +1567,152 @@ __global__ void __launch_bounds__(kMoveLanes) k_move(StepArgs<real> a) {
                 for (int k = 0; k < 11; ++k) v[k] = k == 4 ? fmax(v[k], red[w][k]) : v[k] + red[w][k];
     }
     if (tid == 0) {
-        double* gp = a.gpart + (int64_t)blockIdx.x * kGPart;
+        double* gp = a.gpart + (int64_t)lb * kGPart;
         gp[GP_PX] = v[0]; gp[GP_PY] = v[1]; gp[GP_PZ] = v[2]; gp[GP_EKIN] = v[3]; gp[GP_VMAX2] = v[4];
         gp[GP_VIR] = v[5]; gp[GP_MASS] = v[6]; gp[GP_ALIVE] = v[7]; gp[GP_PAIRS] = v[8]; gp[GP_ABSORBED] = v[9];
         gp[GP_HAVEBEST] = v[10];
     }
 }
 
-// Time step of Sec. 3 per instance, dt = dx / v_max, from the work-group
-// maxima of |v|^2 left by the key kernel; the caller's dt is the cap.  One
-// work-group per instance; writes the instance's dt for the later kernels.
+// Second pass of the exact o-bin sums (see ObAcc), over the step's output
+// state in record order, one record per lane in the move's blocks: each
+// term is rounded to its o-bin's quantum; the integers of the lanes of one
+// o-bin run are summed within each row of 16 lanes, then in the
+// work-group's table, then into the global accumulators.  The sums are
+// integers, so none of these orders is visible.  One record per lane, with
+// the block and its instance uniform over the work-group (scalar loads),
+// measured fastest on the sparse 16M Sedov blast; several consecutive
+// records per lane lose more to their strided loads than they save.
 template <typename real>
-__global__ void __launch_bounds__(256) k_adapt_dt(Inst<real>* inst, const double* gpart) {
+__device__ __forceinline__ void value_flush(MomentTable& tab, const StepArgs<real>& a, int ob, const long long* q,
+                                            uint32_t cnt, uint32_t coll) {
+    const int slot = table_slot(tab, ob);
+    if (slot >= 0) {
+        unsigned long long* T = reinterpret_cast<unsigned long long*>(tab.val[slot]);
+#pragma unroll
+        for (int k = 0; k < kAccVals; ++k)
+            if (q[k]) atomicAdd(T + k, (unsigned long long)q[k]);
+        atomicAdd(T + kAccVals, (unsigned long long)cnt);
+        if (coll) atomicAdd(T + kAccVals + 1, (unsigned long long)coll);
+    } else {
+        ObAcc& G = a.macc[ob];
+#pragma unroll
+        for (int k = 0; k < kAccVals; ++k) global_acc_add(G, k, q[k]);
+        atomicAdd(&G.cnt, (unsigned long long)cnt);
+        if (coll) atomicAdd(&G.coll, (unsigned long long)coll);
+    }
+}
+
+template <typename real>
+__global__ void __launch_bounds__(kBlock) k_moments(StepArgs<real> a) {
+    __shared__ MomentTable tab;
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    const Blk bt = a.blk[lb];
+    const Inst<real>& I = a.inst[bt.inst];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int64_t end = I.off + I.cnt;
+    const bool reorder = (I.flags & TPKMC_ALLOW_REORDER) != 0;
+    const bool has_mass = (I.flags & kHasMass) != 0;
+    for (int t = tid; t < kMomSlots; t += kBlock) tab.key[t] = -1;
+    for (int t = tid; t < kMomSlots * kTabWords; t += kBlock) (&tab.val[0][0])[t] = 0;
+    __syncthreads();
+    const int64_t i = (int64_t)bt.first + tid;
+    int ob = -1;
+    long long q[kAccVals];
+#pragma unroll
+    for (int k = 0; k < kAccVals; ++k) q[k] = 0;
+    uint32_t cnt = 0, coll = 0;
+    if (i < end) {
+        // The same particles as the move's moment terms: alive after the
+        // step (not absorbed), finite, with a valid mass.
+        const int64_t p = reorder ? i : (int64_t)a.src[i];
+        const bool alive = a.alive ? a.alive[p] != 0 : true;
+        const real x = a.x[p], y = a.y[p], z = a.z[p], vx = a.vx[p], vy = a.vy[p], vz = a.vz[p];
+        const real mi = has_mass ? a.mass[p] : I.mass;
+        const bool fin = finite3(x, y, z) && finite3(vx, vy, vz) &&
+                         (!has_mass || (mi > real(0) && mi < real(INFINITY)));
+        if (alive && fin) {
+            ob = obin_of(I, x, y, z);
+            const bool c = a.coll[p] != 0;
+            double vir[3] = {0.0, 0.0, 0.0};
+            if (c) {
+                vir[0] = (double)a.vir[3 * p];
+                vir[1] = (double)a.vir[3 * p + 1];
+                vir[2] = (double)a.vir[3 * p + 2];
+            }
+            const double m = has_mass ? (double)mi : I.mass_d;
+            const double* S = a.shift + (int64_t)ob * 3;
+            double t[kAccVals];
+            moment_terms(m, (double)vx, (double)vy, (double)vz, S, vir[0], vir[1], vir[2], t);
+            const ObAcc& G = a.macc[ob];
+            const double s0 = fixed_scale(G.e[0]), s1 = fixed_scale(G.e[1]);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                q[k] = to_fixed(t[k], s0);
+                q[3 + k] = to_fixed(t[3 + k], s1);
+            }
+            if (c) {
+                const double s2 = fixed_scale(G.e[2]);
+#pragma unroll
+                for (int k = 6; k < 9; ++k) q[k] = to_fixed(t[k], s2);
+            }
+            if (has_mass) q[9] = to_fixed(t[9], fixed_scale(G.e[3]));
+            cnt = 1;
+            coll = c ? 1 : 0;
+        }
+    }
+    bool head;
+    const int lim = row_lim(ob, lane, head);
+    const bool anyc = __ballot(coll != 0) != 0;
+#pragma unroll
+    for (int k = 0; k < kAccVals; ++k) {
+        if ((k >= 6 && k <= 8 && !anyc) || (k == 9 && !has_mass)) continue;  // wave-uniform
+        q[k] = row_sum64(q[k], lim);
+    }
+    cnt = row_sum32(cnt, lim);
+    if (anyc) coll = row_sum32(coll, lim);
+    if ((head || (lane & 15) == 0) && ob >= 0) value_flush(tab, a, ob, q, cnt, coll);
+    __syncthreads();
+    // The table to the global sums: one thread per (slot, table word).
+    for (int t = tid; t < kMomSlots * kTabWords; t += kBlock) {
+        const int slot = t / kTabWords, wd = t % kTabWords;
+        const int o = tab.key[slot];
+        if (o < 0) continue;
+        const long long v = tab.val[slot][wd];
+        ObAcc& G = a.macc[o];
+        if (wd < kAccVals) global_acc_add(G, wd, v);
+        else if (v) atomicAdd(wd == kAccVals ? &G.cnt : &G.coll, (unsigned long long)v);
+    }
+}
+
+// Time step of Sec. 3 per instance, dt = dx / v_max, from the work-group
+// maxima of |v|^2 left by the key kernel; the caller's dt is the cap.
+// gridDim.x work-groups per instance fold those maxima into a running
+// maximum (a single work-group would wait on its loads one after another);
+// the last to arrive writes the instance's dt for the later kernels.
+template <typename real>
+__global__ void __launch_bounds__(256) k_prep(Inst<real>* inst, const double* gpart) {
     __shared__ double lds[16];
-    Inst<real>& I = inst[blockIdx.x];
-    if (!(I.flags & TPKMC_ADAPTIVE_DT)) return;
+    __shared__ bool last;
+    Inst<real>& I = inst[blockIdx.y];
+    if (!(I.flags & TPKMC_ADAPTIVE_DT)) return;  // whole work-group
     double v = 0.0;
-    for (int b = threadIdx.x; b < I.nblk; b += blockDim.x)
-        v = fmax(v, gpart[(int64_t)(I.blk0 + b) * kGPart + GP_VMAX0]);
-    const double vmax2 = block_max(v, lds);
-    if (threadIdx.x != 0) return;
+    const double* g0 = gpart + (int64_t)I.blk0 * kGPart;
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < I.nblk; b += gridDim.x * blockDim.x)
+        v = fmax(v, g0[(int64_t)b * kGPart + GP_VMAX0]);
+    v = block_max(v, lds);
+    if (threadIdx.x == 0) {
+        // Non-negative doubles order like their bit patterns.
+        atomicMax(&I.run_v2, (unsigned long long)__double_as_longlong(v));
+        __threadfence();
+        last = atomicAdd(&I.prep_done, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last || threadIdx.x != 0) return;
+    __threadfence();
+    const double vmax2 = __longlong_as_double((long long)atomicExch(&I.run_v2, 0ull));
+    atomicExch(&I.prep_done, 0u);
     double dt = I.dt_cap;
     if (I.dx_d > 0.0 && vmax2 > 0.0) {
         const double t = I.dx_d / sqrt(vmax2);
@@ -1509,8 +1732,9 @@ void launch_scatter(const StepArgs<real>& a, hipStream_t s) {
     hipLaunchKernelGGL(k_scatter<real>, dim3(a.nblk), dim3(kBlock), 0, s, a);
 }
 template <typename real>
-void launch_adapt_dt(Inst<real>* inst, const double* gpart, int n_inst, hipStream_t s) {
-    hipLaunchKernelGGL(k_adapt_dt<real>, dim3(n_inst), dim3(256), 0, s, inst, gpart);
+void launch_prep(Inst<real>* inst, const double* gpart, int n_inst, int max_nblk, hipStream_t s) {
+    const int gx = std::max(1, std::min(64, (max_nblk + 1023) / 1024));
+    hipLaunchKernelGGL(k_prep<real>, dim3(gx, n_inst), dim3(256), 0, s, inst, gpart);
 }
 template <typename real>
 void launch_search(const StepArgs<real>& a, int block, int group, hipStream_t s) {
@@ -1539,6 +1763,10 @@ void launch_random_pairs(const StepArgs<real>& a, hipStream_t s) {
 template <typename real>
 void launch_move(const StepArgs<real>& a, hipStream_t s) {
     hipLaunchKernelGGL(k_move<real>, dim3(a.nblk), dim3(kMoveLanes), 0, s, a);
+}
+template <typename real>
+void launch_moments(const StepArgs<real>& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_moments<real>, dim3(a.nblk), dim3(kBlock), 0, s, a);
 }
 
 }  // namespace tpkmc
