@@ -137,7 +137,11 @@ enum {
 enum {
     TPKMC_STATUS_PAIR_OVERFLOW = 1, /* more pairs than outputs.pair_cap       */
     TPKMC_STATUS_NONFINITE = 2,     /* an alive particle had a NaN/Inf value  */
-    TPKMC_STATUS_FAST = 4           /* |v_a| dt > c-bin width on some axis    */
+    TPKMC_STATUS_FAST = 4,          /* |v_a| dt > c-bin width on some axis    */
+    TPKMC_STATUS_CELLS = 8          /* c-bins refined by tpkmc_autotune fell
+                                       below the pair reach D + 2 v_max dt:
+                                       results may differ from the configured
+                                       c-bins' (tune again)                  */
 };
 
 /* Counters (uint64[8] per instance). */
@@ -322,12 +326,33 @@ int tpkmc_run(tpkmc_handle* h, const tpkmc_particles* s,
               const tpkmc_instance* inst, int32_t n_inst, int32_t nsteps,
               const tpkmc_outputs* o, void* hip_stream);
 
-/* Times the results-neutral launch shapes of the partner search on this
- * batch (work-group size and particles per work-item) and keeps the
- * fastest for later steps of this handle.  Runs the search kernel only; the
- * particle state is not modified.  Synchronises the stream. */
+/* Chooses the results-neutral knobs of the partner search on this batch
+ * and keeps them for later steps of this handle:
+ *  - c-bins (S10 of the search's design: the stencil of Sec. 2.4 holds every
+ *    pair that can meet the criteria in a step when a c-bin is at least
+ *    D + 2 v_max dt wide on that axis): per instance and axis, the c-bins are
+ *    refined to the largest count that keeps a factor 1.5 over that reach
+ *    on this state, when that at least doubles the configured count (3 or
+ *    more on periodic axes; never with TPKMC_PAIR_RANDOM, whose draw depends
+ *    on the c-bin), with at most one c-bin per two particles.  The refined
+ *    c-bins apply to the instance at the same batch position while its grid,
+ *    sigma, dt and flags stay those it was tuned with; pairs, states and all
+ *    outputs other than the search's work counters (TPKMC_CNT_TESTS,
+ *    TPKMC_CNT_CAND) equal those of the configured c-bins.  Each step checks
+ *    the reach against its own v_max and sets TPKMC_STATUS_CELLS if a refined
+ *    width fell below it.  The time step and the fast-particle check keep the
+ *    configured c-bins.  May grow the handle's c-bin storage.
+ *  - the launch shape (work-group size and particles per work-item): timed,
+ *    the fastest kept.
+ * Runs the binning and search kernels only; the particle state is not
+ * modified.  Synchronises the stream. */
 int tpkmc_autotune(tpkmc_handle* h, const tpkmc_particles* s,
                    const tpkmc_instance* inst, int32_t n_inst, void* hip_stream);
+
+/* The c-bins per axis tpkmc_autotune chose for batch position k of the batch
+ * it last tuned (the configured counts where it kept them).  EINVAL if k is
+ * not a tuned position. */
+int tpkmc_tuned_cells(tpkmc_handle* h, int32_t k, int32_t ncell[3]);
 
 /* Diagnostic: the arithmetic mix of the partner search on a state, for the
  * roofline of the search.  counts (host, uint64[3]) receives, summed over

@@ -347,6 +347,17 @@ struct tpkmc_handle {
     int search_block = kWave;
     int search_group = 2;
     bool shape_chosen = false;  // set by tpkmc_set_search or tpkmc_autotune
+    // c-bins chosen by tpkmc_autotune per batch position, each applied while
+    // the instance at that position keeps the grid and parameters it was
+    // tuned on (the key); capacity of the c-bin counts array.
+    struct Cells {
+        tpkmc_grid g;
+        double sigma, dt;
+        uint32_t flags;
+        int32_t n[3];
+    };
+    std::vector<Cells> cells;
+    int64_t cell_cap = 0;
     bool profiling = false;
     std::vector<ProfRec> prof;
     std::vector<hipEvent_t> pool;
@@ -377,6 +388,8 @@ struct Plan {
     bool adaptive = false;    // some instance takes the adaptive time step
     bool any_search = false;  // some instance takes partners by closest approach
     bool any_random = false;  // some instance takes random partners
+    bool refined = false;     // some instance runs on refined c-bins
+    bool want_vmax = false;   // the largest speeds are wanted (tuning)
     std::vector<Blk> blk;
     std::vector<Chunk> chunks;
     std::vector<char> inst_bytes;
@@ -393,7 +406,8 @@ bool bad_state(const tpkmc_particles* s) {
 // offsets into the c-bin, o-bin, block and chunk tables, which the caller
 // sets.  C and B: its c-bins and o-bins.
 template <typename real>
-int fill_inst(const tpkmc_particles* s, const tpkmc_instance& q, Inst<real>& d, int64_t& C, int64_t& B) {
+int fill_inst(const tpkmc_particles* s, const tpkmc_instance& q, Inst<real>& d, int64_t& C, int64_t& B,
+              const int32_t* nref = nullptr) {
     const tpkmc_grid& g = q.grid;
     const tpkmc_params& p = q.params;
     if (q.offset < 0 || q.count < 0 || q.offset + q.count > s->n) return TPKMC_EINVAL;
@@ -417,11 +431,17 @@ int fill_inst(const tpkmc_particles* s, const tpkmc_instance& q, Inst<real>& d, 
         if (!(std::isfinite(g.lo[a]) && std::isfinite(g.hi[a]) && g.hi[a] > g.lo[a])) return TPKMC_EINVAL;
         if (g.bc[a] < TPKMC_BC_REFLECT || g.bc[a] > TPKMC_BC_ABSORB) return TPKMC_EINVAL;
         if (g.bc[a] == TPKMC_BC_ABSORB && s->alive == nullptr) return TPKMC_EINVAL;
-        C *= g.ncell[a];
+        if (nref && (nref[a] < g.ncell[a] || nref[a] > (1 << 24))) return TPKMC_EINVAL;
+        C *= nref ? nref[a] : g.ncell[a];
         B *= g.nobin[a];
         // Derived grid quantities, in double, in the order of the reference.
+        // With refined c-bins the partner search bins on nc c-bins; the
+        // time step and the fast-particle check keep the configured ones.
         const double L = g.hi[a] - g.lo[a];
-        d.n[a] = g.ncell[a];
+        const int32_t nc = nref ? nref[a] : g.ncell[a];
+        d.n[a] = nc;
+        d.ncfg[a] = g.ncell[a];
+        d.wref[a] = L / (double)nc;
         d.no[a] = g.nobin[a];
         d.bc[a] = g.bc[a];
         d.lo[a] = (real)g.lo[a];
@@ -431,7 +451,7 @@ int fill_inst(const tpkmc_particles* s, const tpkmc_instance& q, Inst<real>& d, 
         d.w[a] = (real)(L / (double)g.ncell[a]);
         wd[a] = L / (double)g.ncell[a];
         if (g.ncell[a] > 1 && (dx == 0.0 || L / (double)g.ncell[a] < dx)) dx = L / (double)g.ncell[a];
-        d.inv_w[a] = (real)((double)g.ncell[a] / L);
+        d.inv_w[a] = (real)((double)nc / L);
         d.inv_wo[a] = (real)((double)g.nobin[a] / L);
     }
     if (C + 1 > (int64_t)1 << 30 || B > (int64_t)1 << 30) return TPKMC_EINVAL;
@@ -443,6 +463,7 @@ int fill_inst(const tpkmc_particles* s, const tpkmc_instance& q, Inst<real>& d, 
     d.step_lo = (uint32_t)p.step;
     d.instance = p.instance;
     d.flags = p.flags | (s->mass ? kHasMass : 0u);
+    if (nref && (nref[0] != g.ncell[0] || nref[1] != g.ncell[1] || nref[2] != g.ncell[2])) d.flags |= kRefined;
     d.dt = (real)p.dt;
     // Largest accepted d_min^2: sigma = pi D^2 in space, sigma = 2 D in
     // the plane (same expressions as the reference).
@@ -462,17 +483,32 @@ int fill_inst(const tpkmc_particles* s, const tpkmc_instance& q, Inst<real>& d, 
     // kBandBytes, so that one XCD's L2 holds the plane its neighbourhood
     // walk reads twice.  Planar and one-row grids keep a single band.
     d.band_log2 = 30;
-    if (g.ncell[2] > 1 && g.ncell[1] > 1 && q.count > 0) {
-        const double row_bytes = (double)g.ncell[0] * ((double)q.count / (double)C) * 8.0 * sizeof(real);
+    if (d.n[2] > 1 && d.n[1] > 1 && q.count > 0) {
+        const double row_bytes = (double)d.n[0] * ((double)q.count / (double)C) * 8.0 * sizeof(real);
         int h = 0;
         while (h < 30 && (double)(2 << h) * row_bytes <= (double)kBandBytes) ++h;
-        if ((1 << h) < g.ncell[1]) d.band_log2 = h;
+        if ((1 << h) < d.n[1]) d.band_log2 = h;
     }
     return TPKMC_OK;
 }
 
+// Flags that decide the choice of c-bins (with the grid, sigma and dt).
+constexpr uint32_t kCellKey = TPKMC_ADAPTIVE_DT | TPKMC_PLANAR | TPKMC_RANK_TIME | TPKMC_PAIR_RANDOM;
+
+// The c-bins autotune chose for batch position k, if the instance there
+// keeps the grid and parameters it was tuned on.
+const int32_t* tuned_cells(const tpkmc_handle* h, int k, const tpkmc_instance& q) {
+    if (k >= (int)h->cells.size()) return nullptr;
+    const tpkmc_handle::Cells& c = h->cells[k];
+    if (std::memcmp(&c.g, &q.grid, sizeof(tpkmc_grid)) != 0 || c.sigma != q.params.sigma ||
+        c.dt != q.params.dt || c.flags != (q.params.flags & kCellKey))
+        return nullptr;
+    return c.n;
+}
+
 template <typename real>
-int make_plan(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* in, int n_inst, Plan& P) {
+int make_plan(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* in, int n_inst, Plan& P,
+              bool configured = false) {
     if (!s || !in || n_inst < 1) return TPKMC_EINVAL;
     if (n_inst > h->max_inst) return TPKMC_ECAPACITY;
     if (s->n < 0) return TPKMC_EINVAL;
@@ -486,6 +522,7 @@ int make_plan(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* i
     P.adaptive = false;
     P.any_search = false;
     P.any_random = false;
+    P.refined = false;
     P.ncell_tot = 0;
     P.nob_tot = 0;
     P.max_nob = 0;
@@ -493,8 +530,9 @@ int make_plan(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* i
         const tpkmc_instance& q = in[k];
         Inst<real>& d = I[k];
         int64_t C, B;
-        const int rc = fill_inst<real>(s, q, d, C, B);
+        const int rc = fill_inst<real>(s, q, d, C, B, configured ? nullptr : tuned_cells(h, k, q));
         if (rc) return rc;
+        if (d.flags & kRefined) P.refined = true;
         spans.push_back({q.offset, q.count});
         if (q.params.flags & TPKMC_PAIR_RANDOM) P.any_random = true;
         else P.any_search = true;
@@ -515,7 +553,7 @@ int make_plan(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* i
     std::sort(spans.begin(), spans.end());
     for (size_t k = 1; k < spans.size(); ++k)
         if (spans[k - 1].first + spans[k - 1].second > spans[k].first) return TPKMC_EINVAL;
-    if (P.ncell_tot + 1 > h->max_cells + 1) return TPKMC_ECAPACITY;
+    if (P.ncell_tot > h->cell_cap) return TPKMC_ECAPACITY;
     if (P.nob_tot > h->max_obins) return TPKMC_ECAPACITY;
     if ((int64_t)P.blk.size() > h->max_blk) return TPKMC_ECAPACITY;
     if ((int64_t)P.chunks.size() > h->max_chunks) return TPKMC_ECAPACITY;
@@ -603,12 +641,12 @@ void enqueue_scan(const Buffers& B, int64_t n, hipStream_t s) {
 struct Shape {
     int n_inst, nblk, nchunk;
     int64_t ncell_tot, nob_tot, max_nob;
-    bool adaptive, any_search, any_random;
+    bool prep, any_search, any_random;  // prep: some instance needs the prep kernel
 };
 
 Shape shape_of(const Plan& P) {
     return Shape{P.n_inst, P.nblk, (int)P.chunks.size(), P.ncell_tot, P.nob_tot, P.max_nob,
-                 P.adaptive, P.any_search, P.any_random};
+                 P.adaptive || P.refined || P.want_vmax, P.any_search, P.any_random};
 }
 
 // Everything of one step after the tables are on the device.  `h` only
@@ -629,7 +667,7 @@ void enqueue_step(tpkmc_handle* h, const Buffers& B, const StepArgs<real>& a, co
     if (P.nblk > 0) {
         PhaseScope ps(h, PH_KEY, s, prof);
         launch_key<real>(a, s);
-        if (P.adaptive) launch_prep<real>((Inst<real>*)B.inst, B.gpart, P.n_inst, P.nblk, s);
+        if (P.prep) launch_prep<real>((Inst<real>*)B.inst, B.gpart, B.status, P.n_inst, P.nblk, s);
     }
     {
         PhaseScope ps(h, PH_SCAN, s, prof);
@@ -709,7 +747,7 @@ int run_impl(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* in
              const tpkmc_outputs* o, hipStream_t caller) {
     if (nsteps < 0) return TPKMC_EINVAL;
     Plan P;
-    int rc = make_plan<real>(h, s, in, n_inst, P);
+    int rc = make_plan<real>(h, s, in, n_inst, P, true);  // validation before anything runs
     if (rc) return rc;
     if ((rc = check_outputs(o))) return rc;
     if (nsteps == 0) return TPKMC_OK;
@@ -725,6 +763,7 @@ int run_impl(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* in
     // First use without a chosen launch shape: tune it on this batch (the
     // state is not modified; every shape gives the same results).
     if (!h->shape_chosen && (rc = tune_impl<real>(h, s, in, n_inst, st))) return rc;
+    if ((rc = make_plan<real>(h, s, in, n_inst, P))) return rc;  // with the tuned c-bins
     if ((rc = upload(h, P, st))) return rc;
     StepArgs<real> a = make_args<real>(h->b, s, o, P.nblk);
     if (h->gexec) {
@@ -752,10 +791,124 @@ int run_impl(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* in
     return hipGetLastError() == hipSuccess ? TPKMC_OK : TPKMC_EHIP;
 }
 
+template <typename T>
+int dalloc(T** p, int64_t count) {
+    *p = nullptr;
+    if (count <= 0) count = 1;
+    return hipMalloc((void**)p, sizeof(T) * (size_t)count) == hipSuccess ? 0 : -1;
+}
+
+// Grows the c-bin counts array (and its scan tiles) to hold `need` c-bins.
+int grow_cells(tpkmc_handle* h, int64_t need) {
+    if (need <= h->cell_cap) return TPKMC_OK;
+    if (need >= ((int64_t)1 << 30)) return TPKMC_ECAPACITY;
+    if (hipDeviceSynchronize() != hipSuccess) return TPKMC_EHIP;
+    if (h->gexec) {
+        hipGraphExecDestroy(h->gexec);
+        h->gexec = nullptr;
+    }
+    hipFree(h->b.start);
+    hipFree(h->b.tiles);
+    h->b.start = nullptr;
+    h->b.tiles = nullptr;
+    const int64_t tiles = (need + 1 + kScanTile - 1) / kScanTile + 1;
+    if (dalloc(&h->b.start, need + 1) || dalloc(&h->b.tiles, tiles)) {
+        h->cell_cap = 0;
+        return TPKMC_ENOMEM;
+    }
+    h->cell_cap = need;
+    return TPKMC_OK;
+}
+
+// Results-neutral c-bins (range S10 of the partner search): any pair that
+// meets the criteria of Sec. 2.4 within the step starts at most D + |u| dt
+// <= D + 2 v_max dt apart on every axis, so c-bins at least that wide on an
+// axis hold every such pair inside the stencil, and narrowing the configured
+// c-bins on that axis down to that width drops only pairs that cannot
+// collide.  Per instance (not with random partners, whose draw depends on the
+// c-bin) and per axis, the c-bins are refined to the largest count whose
+// width keeps a factor 1.5 over the reach measured on this state, when that
+// at least doubles the configured count (3 or more on periodic axes, one on
+// a planar z), with at most one c-bin per two particles.  Each step checks
+// the reach again (TPKMC_STATUS_CELLS).
+template <typename real>
+int choose_cells(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* in, int n_inst, hipStream_t st) {
+    h->cells.clear();
+    Plan P;
+    int rc = make_plan<real>(h, s, in, n_inst, P, true);
+    if (rc) return rc;
+    std::vector<Inst<real>> I(n_inst);
+    std::memcpy(I.data(), P.inst_bytes.data(), P.inst_bytes.size());
+    if (P.nblk > 0) {
+        for (auto& d : I) d.flags |= kWantVmax;
+        std::memcpy(P.inst_bytes.data(), I.data(), P.inst_bytes.size());
+        P.want_vmax = true;
+        if ((rc = upload(h, P, st))) return rc;
+        tpkmc_outputs none{};
+        StepArgs<real> a = make_args<real>(h->b, s, &none, P.nblk);
+        hipLaunchKernelGGL(k_clear, dim3(1024), dim3(256), 0, st, h->b.start, P.ncell_tot + 1,
+                           (unsigned long long*)nullptr, (int64_t)0, h->b.pair_count);
+        launch_key<real>(a, st);
+        launch_prep<real>((Inst<real>*)h->b.inst, h->b.gpart, h->b.status, P.n_inst, P.nblk, st);
+        if (hipMemcpyAsync(I.data(), h->b.inst, sizeof(Inst<real>) * n_inst, hipMemcpyDeviceToHost, st) !=
+                hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess)
+            return TPKMC_EHIP;
+    }
+    int64_t total = 0;
+    for (int k = 0; k < n_inst; ++k) {
+        const tpkmc_instance& q = in[k];
+        tpkmc_handle::Cells c{q.grid, q.params.sigma, q.params.dt, q.params.flags & kCellKey,
+                              {q.grid.ncell[0], q.grid.ncell[1], q.grid.ncell[2]}};
+        const double vmax = sqrt(I[k].vmax2_d);
+        const double reach = sqrt((double)I[k].D2) + 2.0 * vmax * I[k].dt_d;
+        const bool planar = (q.params.flags & TPKMC_PLANAR) != 0;
+        if (!(q.params.flags & TPKMC_PAIR_RANDOM) && q.count > 0 && reach > 0.0 && std::isfinite(reach)) {
+            int64_t cfg = 1;
+            for (int a = 0; a < 3; ++a) cfg *= q.grid.ncell[a];
+            const int64_t cap = std::max<int64_t>(cfg, q.count / 2);
+            for (int a = 0; a < 3; ++a) {
+                if (planar && a == 2) continue;
+                const double L = q.grid.hi[a] - q.grid.lo[a];
+                const double nmax = std::floor(L / (1.5 * reach));
+                if (nmax < 2.0 * q.grid.ncell[a] || nmax > (double)(1 << 24)) continue;
+                if (q.grid.bc[a] == TPKMC_BC_PERIODIC && nmax < 3.0) continue;
+                c.n[a] = (int32_t)nmax;
+            }
+            // At most `cap` c-bins: shrink the most refined axis first.
+            for (;;) {
+                int64_t prod = (int64_t)c.n[0] * c.n[1] * c.n[2];
+                if (prod <= cap) break;
+                int a = -1;
+                double best = 1.0;
+                for (int b = 0; b < 3; ++b) {
+                    const double f = (double)c.n[b] / q.grid.ncell[b];
+                    if (f > best) { best = f; a = b; }
+                }
+                if (a < 0) break;
+                int32_t m = (int32_t)std::floor(c.n[a] * 0.9);
+                const int32_t lo = q.grid.bc[a] == TPKMC_BC_PERIODIC ? std::max(3, 2 * q.grid.ncell[a])
+                                                                     : 2 * q.grid.ncell[a];
+                c.n[a] = m >= lo ? m : q.grid.ncell[a];
+            }
+        }
+        total += (int64_t)c.n[0] * c.n[1] * c.n[2] + 1;
+        h->cells.push_back(c);
+    }
+    if (total > h->cell_cap && (rc = grow_cells(h, total))) {
+        h->cells.clear();
+        return rc;
+    }
+    return TPKMC_OK;
+}
+
 template <typename real>
 int tune_impl(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* in, int n_inst, hipStream_t st) {
+    if (hipSetDevice(h->device) != hipSuccess) return TPKMC_EHIP;
+    int rc = choose_cells<real>(h, s, in, n_inst, st);
+    if (rc) return rc;
     Plan P;
-    int rc = make_plan<real>(h, s, in, n_inst, P);
+    rc = make_plan<real>(h, s, in, n_inst, P);
     if (rc) return rc;
     if (P.nblk == 0) return TPKMC_OK;
     if (hipSetDevice(h->device) != hipSuccess) return TPKMC_EHIP;
@@ -766,7 +919,8 @@ int tune_impl(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* i
     hipLaunchKernelGGL(k_clear, dim3(1024), dim3(256), 0, st, h->b.start, P.ncell_tot + 1,
                        (unsigned long long*)nullptr, (int64_t)0, h->b.pair_count);
     launch_key<real>(a, st);
-    if (P.adaptive) launch_prep<real>((Inst<real>*)h->b.inst, h->b.gpart, P.n_inst, P.nblk, st);
+    if (P.adaptive || P.refined || P.want_vmax)
+        launch_prep<real>((Inst<real>*)h->b.inst, h->b.gpart, h->b.status, P.n_inst, P.nblk, st);
     enqueue_scan(h->b, P.ncell_tot + 1, st);
     launch_scatter<real>(a, st);
     hipEvent_t e0, e1;
@@ -826,7 +980,8 @@ int mix_impl(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* in
     hipLaunchKernelGGL(k_clear, dim3(1024), dim3(256), 0, st, h->b.start, P.ncell_tot + 1,
                        (unsigned long long*)nullptr, (int64_t)0, h->b.pair_count);
     launch_key<real>(a, st);
-    if (P.adaptive) launch_prep<real>((Inst<real>*)h->b.inst, h->b.gpart, P.n_inst, P.nblk, st);
+    if (P.adaptive || P.refined || P.want_vmax)
+        launch_prep<real>((Inst<real>*)h->b.inst, h->b.gpart, h->b.status, P.n_inst, P.nblk, st);
     enqueue_scan(h->b, P.ncell_tot + 1, st);
     launch_scatter<real>(a, st);
     if (hipMemsetAsync(h->b.mix, 0, 3 * sizeof(unsigned long long), st) != hipSuccess) return TPKMC_EHIP;
@@ -839,12 +994,6 @@ int mix_impl(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* in
     return hipGetLastError() == hipSuccess ? TPKMC_OK : TPKMC_EHIP;
 }
 
-template <typename T>
-int dalloc(T** p, int64_t count) {
-    *p = nullptr;
-    if (count <= 0) count = 1;
-    return hipMalloc((void**)p, sizeof(T) * (size_t)count) == hipSuccess ? 0 : -1;
-}
 
 void free_all(tpkmc_handle* h) {
     for (int k = 0; k < tpkmc_handle::kRing; ++k) {
@@ -1000,6 +1149,7 @@ int tpkmc_create(const tpkmc_config* cfg, tpkmc_handle** out) {
     h->precision = cfg->precision;
     h->max_n = cfg->max_particles;
     h->max_cells = cfg->max_cells;
+    h->cell_cap = cfg->max_cells;
     h->max_obins = cfg->max_obins;
     h->max_inst = cfg->max_instances;
     h->max_blk = cfg->max_particles / kBlock + cfg->max_instances + 1;
@@ -1106,6 +1256,12 @@ int tpkmc_autotune(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instan
     hipStream_t st = (hipStream_t)stream;
     return h->precision == TPKMC_FP64 ? tune_impl<double>(h, s, inst, n_inst, st)
                                       : tune_impl<float>(h, s, inst, n_inst, st);
+}
+
+int tpkmc_tuned_cells(tpkmc_handle* h, int32_t k, int32_t ncell[3]) {
+    if (!h || !ncell || k < 0 || k >= (int32_t)h->cells.size()) return TPKMC_EINVAL;
+    for (int a = 0; a < 3; ++a) ncell[a] = h->cells[k].n[a];
+    return TPKMC_OK;
 }
 
 int tpkmc_search_mix(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* inst, int32_t n_inst,

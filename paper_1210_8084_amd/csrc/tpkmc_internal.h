@@ -71,7 +71,18 @@ struct Inst {
     // one to finish resets both.
     unsigned long long run_v2;
     uint32_t prep_done;
+    // Refined c-bins (kRefined): the configured c-bins per axis and the
+    // refined widths; this step's largest |v|^2 before the move.
+    int32_t ncfg[3];
+    double wref[3];
+    double vmax2_d;
 };
+
+// Bits of Inst::flags set by the host (outside the public flag bits): the
+// c-bins are a results-neutral refinement of the configured ones (S10 range,
+// checked every step), and the step's largest speed is wanted (tuning).
+constexpr uint32_t kRefined = 1u << 30;
+constexpr uint32_t kWantVmax = 1u << 29;
 
 // Bit of Inst::flags, set by the host (outside the public flag bits): the
 // particles carry their own masses.
@@ -127,8 +138,8 @@ struct StepArgs {
 // Launchers implemented per precision (tpkmc_f32.hip / tpkmc_f64.hip).
 template <typename real> void launch_key(const StepArgs<real>& a, hipStream_t s);
 template <typename real> void launch_scatter(const StepArgs<real>& a, hipStream_t s);
-template <typename real> void launch_prep(Inst<real>* inst, const double* gpart, int n_inst, int max_nblk,
-                                         hipStream_t s);
+template <typename real> void launch_prep(Inst<real>* inst, const double* gpart, uint32_t* status, int n_inst,
+                                         int max_nblk, hipStream_t s);
 template <typename real> void launch_search(const StepArgs<real>& a, int block, int group, hipStream_t s);
 template <typename real> void launch_search_mix(const StepArgs<real>& a, int block, hipStream_t s);
 template <typename real> void launch_move(const StepArgs<real>& a, hipStream_t s);

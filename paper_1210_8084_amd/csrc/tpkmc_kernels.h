@@ -309,7 +309,7 @@ __global__ void __launch_bounds__(kWave) k_key(StepArgs<real> a) {
     const Inst<real>& I = a.inst[bt.inst];
     const int lane = threadIdx.x;
     const int64_t end = I.off + I.cnt;
-    const bool adaptive = (I.flags & TPKMC_ADAPTIVE_DT) != 0;
+    const bool want_v2 = (I.flags & (TPKMC_ADAPTIVE_DT | kRefined | kWantVmax)) != 0;
     real x[kKeyRec], y[kKeyRec], z[kKeyRec], vx[kKeyRec], vy[kKeyRec], vz[kKeyRec];
     bool alive[kKeyRec];
 #pragma unroll
@@ -338,7 +338,7 @@ __global__ void __launch_bounds__(kWave) k_key(StepArgs<real> a) {
         bool fin = true;
         key[r] = in ? cbin_key(a, I, p, x[r], y[r], z[r], vx[r], vy[r], vz[r], alive[r], fin) : 0;
         if (in && alive[r] && fin) {
-            if (adaptive) v2 = fmax(v2, speed2((double)vx[r], (double)vy[r], (double)vz[r]));
+            if (want_v2) v2 = fmax(v2, speed2((double)vx[r], (double)vy[r], (double)vz[r]));
         } else if (in) {
             nonfin += (alive[r] && !fin) ? 1.0 : 0.0;
         }
@@ -1686,17 +1686,21 @@ __global__ void __launch_bounds__(kBlock) k_moments(StepArgs<real> a) {
     }
 }
 
-// Time step of Sec. 3 per instance, dt = dx / v_max, from the work-group
-// maxima of |v|^2 left by the key kernel; the caller's dt is the cap.
-// gridDim.x work-groups per instance fold those maxima into a running
-// maximum (a single work-group would wait on its loads one after another);
-// the last to arrive writes the instance's dt for the later kernels.
+// Per instance, from the work-group maxima of |v|^2 left by the key kernel:
+// the step's largest speed; with ADAPTIVE_DT the time step of Sec. 3,
+// dt = dx / v_max (dx of the configured c-bins), the caller's dt being the
+// cap; with refined c-bins the check that each refined width still holds
+// the pair reach D + 2 v_max dt, so that every pair the configured c-bins
+// allow is still inside the stencil (TPKMC_STATUS_CELLS otherwise).
+// gridDim.x work-groups per instance fold the maxima into a running maximum
+// (a single work-group would wait on its loads one after another); the last
+// to arrive writes the instance's quantities for the later kernels.
 template <typename real>
-__global__ void __launch_bounds__(256) k_prep(Inst<real>* inst, const double* gpart) {
+__global__ void __launch_bounds__(256) k_prep(Inst<real>* inst, const double* gpart, uint32_t* status) {
     __shared__ double lds[16];
     __shared__ bool last;
     Inst<real>& I = inst[blockIdx.y];
-    if (!(I.flags & TPKMC_ADAPTIVE_DT)) return;  // whole work-group
+    if (!(I.flags & (TPKMC_ADAPTIVE_DT | kRefined | kWantVmax))) return;  // whole work-group
     double v = 0.0;
     const double* g0 = gpart + (int64_t)I.blk0 * kGPart;
     for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < I.nblk; b += gridDim.x * blockDim.x)
@@ -1713,13 +1717,22 @@ __global__ void __launch_bounds__(256) k_prep(Inst<real>* inst, const double* gp
     __threadfence();
     const double vmax2 = __longlong_as_double((long long)atomicExch(&I.run_v2, 0ull));
     atomicExch(&I.prep_done, 0u);
-    double dt = I.dt_cap;
-    if (I.dx_d > 0.0 && vmax2 > 0.0) {
-        const double t = I.dx_d / sqrt(vmax2);
-        if (t < dt) dt = t;
+    I.vmax2_d = vmax2;
+    if (I.flags & TPKMC_ADAPTIVE_DT) {
+        double dt = I.dt_cap;
+        if (I.dx_d > 0.0 && vmax2 > 0.0) {
+            const double t = I.dx_d / sqrt(vmax2);
+            if (t < dt) dt = t;
+        }
+        I.dt_d = dt;
+        I.dt = (real)dt;
     }
-    I.dt_d = dt;
-    I.dt = (real)dt;
+    if (I.flags & kRefined) {
+        const double reach = sqrt((double)I.D2) + 2.0 * sqrt(vmax2) * I.dt_d;
+        bool ok = true;
+        for (int ax = 0; ax < 3; ++ax) ok = ok && (I.n[ax] == I.ncfg[ax] || I.wref[ax] >= reach);
+        if (!ok) atomicOr(status, (uint32_t)TPKMC_STATUS_CELLS);
+    }
 }
 
 // ---------------------------------------------------------------- launchers
@@ -1732,9 +1745,9 @@ void launch_scatter(const StepArgs<real>& a, hipStream_t s) {
     hipLaunchKernelGGL(k_scatter<real>, dim3(a.nblk), dim3(kBlock), 0, s, a);
 }
 template <typename real>
-void launch_prep(Inst<real>* inst, const double* gpart, int n_inst, int max_nblk, hipStream_t s) {
+void launch_prep(Inst<real>* inst, const double* gpart, uint32_t* status, int n_inst, int max_nblk, hipStream_t s) {
     const int gx = std::max(1, std::min(64, (max_nblk + 1023) / 1024));
-    hipLaunchKernelGGL(k_prep<real>, dim3(gx, n_inst), dim3(256), 0, s, inst, gpart);
+    hipLaunchKernelGGL(k_prep<real>, dim3(gx, n_inst), dim3(256), 0, s, inst, gpart, status);
 }
 template <typename real>
 void launch_search(const StepArgs<real>& a, int block, int group, hipStream_t s) {

@@ -28,7 +28,8 @@ def lib():
 def test_header_declares_the_boundary():
     names = declared()
     for f in ("tpkmc_version", "tpkmc_strerror", "tpkmc_create", "tpkmc_destroy", "tpkmc_step",
-              "tpkmc_step_batched", "tpkmc_run", "tpkmc_autotune", "tpkmc_status", "tpkmc_step_noalloc"):
+              "tpkmc_step_batched", "tpkmc_run", "tpkmc_autotune", "tpkmc_status", "tpkmc_step_noalloc",
+              "tpkmc_tuned_cells"):
         assert f in names
 
 
@@ -52,5 +53,6 @@ def test_argument_free_calls(lib):
     assert lib.tpkmc_destroy(None) == tpkmc.OK
     assert lib.tpkmc_step(None, None, None, None, None, None) == tpkmc.EINVAL
     assert lib.tpkmc_status(None, None) == tpkmc.EINVAL
+    assert lib.tpkmc_tuned_cells(None, 0, None) == tpkmc.EINVAL
     assert lib.tpkmc_step_noalloc(0, 0, None, None, None, None, None) == tpkmc.EINVAL
     assert lib.tpkmc_step_noalloc(7, 0, None, None, None, None, None) == tpkmc.EINVAL
