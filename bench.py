@@ -331,10 +331,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-ensemble keys")
     ap.add_argument("--start-only", action="store_true",
                     help="time all K steps from the start of the run (no windows at its middle and end)")
-    ap.add_argument("--search", default="2,64",
-                    help="search launch shape 'G,B' (records per lane, lanes per work-group), or 'auto' for the "
-                         "autotuner's choice.  The default is the library's default shape, the one the "
-                         "profiles in profiles/ were taken with")
+    ap.add_argument("--search", default="auto",
+                    help="'auto': the autotuner's results-neutral choice of c-bins and search launch shape; or a "
+                         "fixed shape 'G,B' (records per lane, lanes per work-group) on the configured c-bins")
     ap.add_argument("--batch-scale", type=float, default=1.0, help="batched ensemble: scale every instance size")
     ap.add_argument("--batch-steps", type=int, default=10, help="batched ensemble: timed steps")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -468,8 +467,9 @@ def main():
     peak = PEAK_FLOPS[args.precision]
     shape = eng.get_search()
     shape = (shape[0], min(shape[1], 256 // shape[0]))
+    cbins = list(eng.tuned_cells(0)) if args.search == "auto" else list(g["ncell"])
     traffic = read_traffic(args.workload, args.precision, shape)
-    bytes_per = phase_bytes(rs, w.n, ncell_tot, nob, True)
+    bytes_per = phase_bytes(rs, w.n, int(np.prod(cbins)) + 1, nob, True)
     phases = {}
     for ph, (ms, n) in prof_tot.items():
         if n:
@@ -509,6 +509,7 @@ def main():
         "dtype": "f32" if prec == T.FP32 else "f64",
         "data": "synthetic (seeded initial state of the paper's test problem)",
         "config": {"workload": args.workload, "particles": w.n, "ncell": list(g["ncell"]),
+                   "search_cbins": cbins,
                    "nobin": list(g["nobin"]), "kn": w.info.get("kn"), "run_steps": w.steps,
                    "state_precision": args.precision, "moments": "fp64",
                    "particle_order": "c-bin order kept between steps",
