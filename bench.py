@@ -44,7 +44,6 @@ sys.path.insert(0, ROOT)
 FLOP_S0, FLOP_S1, FLOP_DMIN = 11, 7, 12
 PEAK_FLOPS = {"fp32": 157.3e12, "fp64": 78.6e12}
 HBM_PEAK = 8.0e12
-MOMENT_VALUES = 12  # doubles per o-bin
 
 
 WORKLOAD_NAMES = {"sedov16M": "16M-particle Sedov", "sod4M": "4M-particle Sod", "sod4M_kn0.1": "4M-particle Sod at Kn 0.1",
@@ -71,23 +70,33 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def phase_bytes(rs, n, ncell_tot, nobin, reorder):
+def phase_bytes(rs, n, ncell_tot, nobin, reorder, colliders=0):
     """Algorithmic HBM bytes per launch of each phase (rs = bytes per real):
     what each kernel must read and write once, as listed per kernel in the
-    design notes."""
+    design notes.  The move phase runs two kernels, the move and the moment
+    pass (listed also on their own)."""
     rec = 8 * rs
     pkey = 8 if rs == 4 else 4   # FP32: 64-bit (d_min^2, partner) key; FP64: partner index
+    acc = 192                    # exact sums of one o-bin
+    src = 0 if reorder else 4
+    # record, own and partner's partner key in; state, id, alive, collided flag
+    # out; colliders' virial terms out
+    move = n * (rec + 2 * pkey + 6 * rs + 4 + 1 + 1 + src) + colliders * 3 * rs
+    # state, alive and collided flag in (colliders' virial terms too); per
+    # o-bin shift and exponents in, exact sums out
+    moments = n * (6 * rs + 1 + 1 + src) + colliders * 3 * rs + nobin * (24 + acc)
     return {
-        "clear": 4 * ncell_tot + 8 * MOMENT_VALUES * nobin,
+        "clear": 4 * ncell_tot + acc * nobin,
         # state and alive in, rank out
         "key": n * (6 * rs + 1 + 4),
         "scan": 12 * ncell_tot,
         # state, id, alive, rank, start[key] in; record (and FP32 key init, permutation) out
-        "scatter": n * (6 * rs + 4 + 1 + 4 + 4 + rec + (8 if rs == 4 else 0) + (0 if reorder else 4)),
+        "scatter": n * (6 * rs + 4 + 1 + 4 + 4 + rec + (8 if rs == 4 else 0) + src),
         # records and the c-bin starts in (each once), partner key or index out
         "search": n * (rec + pkey) + 4 * ncell_tot,
-        # record, own and partner's partner key in; state, id, alive out; o-bin table
-        "move": n * (rec + 2 * pkey + 6 * rs + 4 + 1 + (0 if reorder else 4)) + 2 * 8 * MOMENT_VALUES * nobin,
+        "move": move + moments,
+        "k_move": move,
+        "k_moments": moments,
         "finalize": 0,
     }
 
@@ -100,10 +109,11 @@ def kernel_code_sha256(path):
     return hashlib.sha256("\n".join(line for line in lines if line.strip()).encode()).hexdigest()
 
 
-def read_traffic(workload, precision, shape):
+def read_traffic(workload, precision, shape, cbins):
     """HBM bytes per search launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source and in the launch
-    shape (records per lane, lanes per work-group) this run uses."""
+    summary, if it was taken on the current kernel source, in the launch
+    shape (records per lane, lanes per work-group) and on the c-bins this run
+    uses."""
     path = os.path.join(ROOT, "profiles", f"search_{workload}_{precision}_traffic.txt")
     if not os.path.exists(path):
         return None
@@ -116,6 +126,8 @@ def read_traffic(workload, precision, shape):
     if vals.get("kernel_code_sha256") != kernel_code_sha256(src):
         return None
     if vals.get("search_shape") != f"{shape[0]},{shape[1]}":
+        return None
+    if vals.get("search_cbins") != ",".join(str(int(c)) for c in cbins):
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -468,8 +480,8 @@ def main():
     shape = eng.get_search()
     shape = (shape[0], min(shape[1], 256 // shape[0]))
     cbins = list(eng.tuned_cells(0)) if args.search == "auto" else list(g["ncell"])
-    traffic = read_traffic(args.workload, args.precision, shape)
-    bytes_per = phase_bytes(rs, w.n, int(np.prod(cbins)) + 1, nob, True)
+    traffic = read_traffic(args.workload, args.precision, shape, cbins)
+    bytes_per = phase_bytes(rs, w.n, int(np.prod(cbins)) + 1, nob, True, colliders=2 * pairs / max(K, 1))
     phases = {}
     for ph, (ms, n) in prof_tot.items():
         if n:
