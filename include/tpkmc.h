@@ -343,11 +343,24 @@ int tpkmc_run(tpkmc_handle* h, const tpkmc_particles* s,
  *    width fell below it.  The time step and the fast-particle check keep the
  *    configured c-bins.  May grow the handle's c-bin storage.
  *  - the launch shape (work-group size and particles per work-item): timed,
- *    the fastest kept.
+ *    the fastest kept;
+ *  - the order in which the search's work-groups are dealt to the XCDs:
+ *    contiguous ranges (the default: neighbouring work-groups share an L2)
+ *    or chunks of 1, 16 or 128 work-groups round-robin (balance when the
+ *    work per work-group varies, as across a batch of instances), timed in
+ *    the chosen shape and kept when at least 3% faster.
  * Runs the binning and search kernels only; the particle state is not
  * modified.  Synchronises the stream. */
 int tpkmc_autotune(tpkmc_handle* h, const tpkmc_particles* s,
                    const tpkmc_instance* inst, int32_t n_inst, void* hip_stream);
+
+/* The search's work-group order in use: 0 for contiguous ranges per XCD,
+ * S > 0 for chunks of S work-groups dealt round-robin. */
+int tpkmc_search_order(tpkmc_handle* h, int32_t* order);
+
+/* Sets that order (0, or a chunk of 1..4096 work-groups); results do not
+ * depend on it. */
+int tpkmc_set_search_order(tpkmc_handle* h, int32_t order);
 
 /* The c-bins per axis tpkmc_autotune chose for batch position k of the batch
  * it last tuned (the configured counts where it kept them).  EINVAL if k is

@@ -124,6 +124,7 @@ struct StepArgs {
     unsigned long long* bkey; // record -> (d_min^2 bits, partner record) (FP32 search)
     double* gpart;            // [nblk][kGPart]
     double* shift;            // per-o-bin velocity shift (3 per o-bin)
+    int32_t order;            // search work-group order: 0 contiguous per XCD, S > 0 chunks of S round-robin
     ObAcc* macc;              // per-o-bin exact sums, or null (no moments)
     real* vir;                // virial terms of each collider (3 per particle, caller index)
     uint8_t* coll;            // 1 if the particle collided this step (caller index)

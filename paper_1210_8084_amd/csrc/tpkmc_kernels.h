@@ -215,6 +215,20 @@ __device__ __forceinline__ int xcd_remap(int bid, int nb) {
     return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
 }
 
+// The other order: chunks of S consecutive work-groups dealt round-robin over
+// the XCDs (S = 1 keeps the dispatch order).  Contiguous ranges keep what
+// neighbouring work-groups share in one L2, but when the work per
+// work-group varies along the table (a batch of instances of different
+// densities) they leave some XCDs with much more work than others; chunks
+// trade some of that locality for balance.  Full rounds of 8 S work-groups
+// are permuted; the last, partial round keeps the dispatch order.
+__device__ __forceinline__ int xcd_chunk_remap(int bid, int nb, int S) {
+    const int round = 8 * S;
+    const int r = bid / round, m = bid - r * round;
+    if ((r + 1) * round > nb) return bid;
+    return r * round + (m & 7) * S + (m >> 3);
+}
+
 // ---------------------------------------------------------------- Philox
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).
 __device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
@@ -920,7 +934,7 @@ k_search(StepArgs<real> a) {
     __shared__ double lds[16];
     const int lanes = kBlock / G;
     const int sub = lanes / blockDim.x;
-    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int lb = a.order > 0 ? xcd_chunk_remap(blockIdx.x, gridDim.x, a.order) : xcd_remap(blockIdx.x, gridDim.x);
     const int entry = lb / sub;
     const Blk bt = a.blk[entry];
     const Inst<real>& I = a.inst[bt.inst];

@@ -98,10 +98,12 @@ def lib():
         L.tpkmc_step_noalloc.argtypes = [ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P]
         L.tpkmc_search_mix.argtypes = [_P, _P, _P, ctypes.c_int32, _P, _P]
         L.tpkmc_tuned_cells.argtypes = [_P, ctypes.c_int32, _P]
+        L.tpkmc_search_order.argtypes = [_P, _P]
+        L.tpkmc_set_search_order.argtypes = [_P, ctypes.c_int32]
         for f in ("tpkmc_create", "tpkmc_destroy", "tpkmc_step", "tpkmc_step_batched", "tpkmc_run",
                   "tpkmc_autotune", "tpkmc_status", "tpkmc_profile_enable", "tpkmc_profile_read",
                   "tpkmc_set_search", "tpkmc_get_search", "tpkmc_step_noalloc", "tpkmc_search_mix",
-                  "tpkmc_tuned_cells"):
+                  "tpkmc_tuned_cells", "tpkmc_search_order", "tpkmc_set_search_order"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -327,6 +329,15 @@ class Engine:
         _check(lib().tpkmc_search_mix(self.h, ctypes.byref(S), arr, len(specs), counts.ctypes.data_as(_P),
                                       _P(_stream_ptr(stream))), "tpkmc_search_mix")
         return tuple(int(v) for v in counts)
+
+    def search_order(self):
+        """Work-group order of the search: 0 contiguous per XCD, S chunks of S."""
+        v = ctypes.c_int32(0)
+        _check(lib().tpkmc_search_order(self.h, ctypes.byref(v)), "tpkmc_search_order")
+        return int(v.value)
+
+    def set_search_order(self, order):
+        _check(lib().tpkmc_set_search_order(self.h, int(order)), "tpkmc_set_search_order")
 
     def tuned_cells(self, k=0):
         """c-bins per axis that autotune chose for batch position k."""

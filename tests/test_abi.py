@@ -29,7 +29,7 @@ def test_header_declares_the_boundary():
     names = declared()
     for f in ("tpkmc_version", "tpkmc_strerror", "tpkmc_create", "tpkmc_destroy", "tpkmc_step",
               "tpkmc_step_batched", "tpkmc_run", "tpkmc_autotune", "tpkmc_status", "tpkmc_step_noalloc",
-              "tpkmc_tuned_cells"):
+              "tpkmc_tuned_cells", "tpkmc_search_order", "tpkmc_set_search_order"):
         assert f in names
 
 
@@ -54,5 +54,7 @@ def test_argument_free_calls(lib):
     assert lib.tpkmc_step(None, None, None, None, None, None) == tpkmc.EINVAL
     assert lib.tpkmc_status(None, None) == tpkmc.EINVAL
     assert lib.tpkmc_tuned_cells(None, 0, None) == tpkmc.EINVAL
+    assert lib.tpkmc_search_order(None, None) == tpkmc.EINVAL
+    assert lib.tpkmc_set_search_order(None, 1) == tpkmc.EINVAL
     assert lib.tpkmc_step_noalloc(0, 0, None, None, None, None, None) == tpkmc.EINVAL
     assert lib.tpkmc_step_noalloc(7, 0, None, None, None, None, None) == tpkmc.EINVAL
