@@ -343,7 +343,7 @@ int tpkmc_run(tpkmc_handle* h, const tpkmc_particles* s,
  *    width fell below it.  The time step and the fast-particle check keep the
  *    configured c-bins.  May grow the handle's c-bin storage.
  *  - the launch shape (work-group size and particles per work-item): timed,
- *    the fastest kept;
+ *    the default kept unless another is at least 5% faster;
  *  - the order in which the search's work-groups are dealt to the XCDs:
  *    contiguous ranges (the default: neighbouring work-groups share an L2)
  *    or chunks of 1, 16 or 128 work-groups round-robin (balance when the

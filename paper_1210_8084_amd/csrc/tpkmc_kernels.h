@@ -1306,13 +1306,14 @@ __device__ __forceinline__ int row_max32(int v, int lim) {
 // particle moves and meets the walls; global sums; with moments, the first
 // pass of the exact o-bin sums (see ObAcc): the exponent maxima, and each
 // particle's collider flag and virial terms for the moment pass.  Each lane
-// takes kMoveRec consecutive records: records in c-bin order come in runs of
-// one o-bin, so a lane keeps its run's maxima in registers and touches the
-// work-group's o-bin table only when the o-bin changes, and the global sums
-// are reduced once per kMoveRec records.  The next record is loaded while
-// the current one is processed.  Two records per lane balance these savings
-// against the coalescing and occupancy of one record per lane.
-constexpr int kMoveRec = 2;
+// takes kMoveRec consecutive records (a lane keeps its run's maxima in
+// registers and touches the work-group's o-bin table only when the o-bin
+// changes; the next record is loaded while the current one is processed).
+// Since the moment sums moved to their own pass, one record per lane is the
+// fastest: move and moment pass 0.66 ms on the 16M Sedov blast against 0.75
+// and 0.97 ms with two and four records per lane, with the same order on
+// the Noh implosion and the Sod tube.
+constexpr int kMoveRec = 1;
 constexpr int kMoveLanes = kBlock / kMoveRec;
 
 // A lane's run maxima of one o-bin into the work-group table, or straight
