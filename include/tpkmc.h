@@ -137,11 +137,7 @@ enum {
 enum {
     TPKMC_STATUS_PAIR_OVERFLOW = 1, /* more pairs than outputs.pair_cap       */
     TPKMC_STATUS_NONFINITE = 2,     /* an alive particle had a NaN/Inf value  */
-    TPKMC_STATUS_FAST = 4,          /* |v_a| dt > c-bin width on some axis    */
-    TPKMC_STATUS_CELLS = 8          /* c-bins refined by tpkmc_autotune fell
-                                       below the pair reach D + 2 v_max dt:
-                                       results may differ from the configured
-                                       c-bins' (tune again)                  */
+    TPKMC_STATUS_FAST = 4           /* |v_a| dt > c-bin width on some axis    */
 };
 
 /* Counters (uint64[8] per instance). */
@@ -328,20 +324,24 @@ int tpkmc_run(tpkmc_handle* h, const tpkmc_particles* s,
 
 /* Chooses the results-neutral knobs of the partner search on this batch
  * and keeps them for later steps of this handle:
- *  - c-bins (S10 of the search's design: the stencil of Sec. 2.4 holds every
- *    pair that can meet the criteria in a step when a c-bin is at least
- *    D + 2 v_max dt wide on that axis): per instance and axis, the c-bins are
- *    refined to the largest count that keeps a factor 1.5 over that reach
- *    on this state, when that at least doubles the configured count (3 or
- *    more on periodic axes; never with TPKMC_PAIR_RANDOM, whose draw depends
- *    on the c-bin), with at most one c-bin per two particles.  The refined
- *    c-bins apply to the instance at the same batch position while its grid,
- *    sigma, dt and flags stay those it was tuned with; pairs, states and all
- *    outputs other than the search's work counters (TPKMC_CNT_TESTS,
- *    TPKMC_CNT_CAND) equal those of the configured c-bins.  Each step checks
- *    the reach against its own v_max and sets TPKMC_STATUS_CELLS if a refined
- *    width fell below it.  The time step and the fast-particle check keep the
- *    configured c-bins.  May grow the handle's c-bin storage.
+ *  - c-bins split by speed (S10 of the search's design).  Two particles of
+ *    speed at most v_c that meet the criteria of Sec. 2.4 within a step start
+ *    at most D + 2 v_c dt apart, so on c-bins at least that wide the stencil
+ *    holds every such pair.  Per instance, with v_c = 3 times the
+ *    root-mean-square speed of its live particles on this state, the slow
+ *    particles (|v| <= v_c, decided every step) are binned on c-bins refined
+ *    per axis to the largest count that keeps a factor 1 + 1/64 over that
+ *    reach, when that is at least 1.25 times the configured count (3 or more
+ *    on periodic axes; never with TPKMC_PAIR_RANDOM, whose draw depends on
+ *    the c-bin), with at most one c-bin per two particles; the fast ones keep
+ *    the configured c-bins and are tested against every particle of their
+ *    configured neighbourhood.  The split applies to the instance at the
+ *    same batch position while its grid, sigma, dt and flags stay those it
+ *    was tuned with; at any later speeds, pairs, states and all outputs
+ *    other than the search's work counters (TPKMC_CNT_TESTS,
+ *    TPKMC_CNT_CAND) equal those of the configured c-bins.  The time step
+ *    and the fast-particle check keep the configured c-bins.  May grow the
+ *    handle's c-bin storage.
  *  - the launch shape (work-group size and particles per work-item): timed,
  *    the default kept unless another is at least 5% faster;
  *  - the order in which the search's work-groups are dealt to the XCDs:
@@ -362,10 +362,14 @@ int tpkmc_search_order(tpkmc_handle* h, int32_t* order);
  * depend on it. */
 int tpkmc_set_search_order(tpkmc_handle* h, int32_t order);
 
-/* The c-bins per axis tpkmc_autotune chose for batch position k of the batch
- * it last tuned (the configured counts where it kept them).  EINVAL if k is
- * not a tuned position. */
+/* The slow particles' c-bins per axis that tpkmc_autotune chose for batch
+ * position k of the batch it last tuned (the configured counts where it kept
+ * them).  EINVAL if k is not a tuned position. */
 int tpkmc_tuned_cells(tpkmc_handle* h, int32_t k, int32_t ncell[3]);
+
+/* The speed bound v_c of the slow particles at batch position k (0 where
+ * the c-bins are not split).  EINVAL if k is not a tuned position. */
+int tpkmc_tuned_speed(tpkmc_handle* h, int32_t k, double* speed);
 
 /* Diagnostic: the arithmetic mix of the partner search on a state, for the
  * roofline of the search.  counts (host, uint64[3]) receives, summed over

@@ -8,10 +8,12 @@
 namespace tpkmc {
 template void launch_key<double>(const StepArgs<double>&, hipStream_t);
 template void launch_scatter<double>(const StepArgs<double>&, hipStream_t);
-template void launch_prep<double>(Inst<double>*, const double*, uint32_t*, int, int, hipStream_t);
+template void launch_prep<double>(Inst<double>*, const double*, int, int, hipStream_t);
 template void launch_search<double>(const StepArgs<double>&, int, int, hipStream_t);
-template void launch_search_mix<double>(const StepArgs<double>&, int, hipStream_t);
+template void launch_search_mix<double>(const StepArgs<double>&, int, int, bool, hipStream_t);
+template void launch_search_fast<double>(const StepArgs<double>&, int, hipStream_t);
 template void launch_move<double>(const StepArgs<double>&, hipStream_t);
 template void launch_moments<double>(const StepArgs<double>&, hipStream_t);
 template void launch_random_pairs<double>(const StepArgs<double>&, hipStream_t);
+template void launch_speed_stats<double>(const StepArgs<double>&, hipStream_t);
 }  // namespace tpkmc

@@ -355,7 +355,8 @@ struct tpkmc_handle {
         tpkmc_grid g;
         double sigma, dt;
         uint32_t flags;
-        int32_t n[3];
+        int32_t n[3];   // c-bins of the slow particles (the configured ones: no split)
+        double vc;      // speed bound of the slow particles
     };
     std::vector<Cells> cells;
     int64_t cell_cap = 0;
@@ -388,9 +389,8 @@ struct Plan {
     int nblk = 0;
     bool adaptive = false;    // some instance takes the adaptive time step
     bool any_search = false;  // some instance takes partners by closest approach
+    bool split = false;       // some instance has c-bins split by speed
     bool any_random = false;  // some instance takes random partners
-    bool refined = false;     // some instance runs on refined c-bins
-    bool want_vmax = false;   // the largest speeds are wanted (tuning)
     std::vector<Blk> blk;
     std::vector<Chunk> chunks;
     std::vector<char> inst_bytes;
@@ -405,10 +405,11 @@ bool bad_state(const tpkmc_particles* s) {
 
 // Validates one instance and fills its device descriptor, except the
 // offsets into the c-bin, o-bin, block and chunk tables, which the caller
-// sets.  C and B: its c-bins and o-bins.
+// sets.  C and B: its c-bins and o-bins.  nref (split c-bins): the slow
+// particles' c-bins per axis, vc their speed bound.
 template <typename real>
 int fill_inst(const tpkmc_particles* s, const tpkmc_instance& q, Inst<real>& d, int64_t& C, int64_t& B,
-              const int32_t* nref = nullptr) {
+              const int32_t* nref = nullptr, double vc = 0.0) {
     const tpkmc_grid& g = q.grid;
     const tpkmc_params& p = q.params;
     if (q.offset < 0 || q.count < 0 || q.offset + q.count > s->n) return TPKMC_EINVAL;
@@ -425,6 +426,7 @@ int fill_inst(const tpkmc_particles* s, const tpkmc_instance& q, Inst<real>& d, 
     std::memset(&d, 0, sizeof(d));
     C = 1;
     B = 1;
+    int64_t Cc = 1;
     double dx = 0.0, wd[3];
     for (int a = 0; a < 3; ++a) {
         if (g.ncell[a] < 1 || g.nobin[a] < 1) return TPKMC_EINVAL;
@@ -434,15 +436,17 @@ int fill_inst(const tpkmc_particles* s, const tpkmc_instance& q, Inst<real>& d, 
         if (g.bc[a] == TPKMC_BC_ABSORB && s->alive == nullptr) return TPKMC_EINVAL;
         if (nref && (nref[a] < g.ncell[a] || nref[a] > (1 << 24))) return TPKMC_EINVAL;
         C *= nref ? nref[a] : g.ncell[a];
+        Cc *= g.ncell[a];
         B *= g.nobin[a];
         // Derived grid quantities, in double, in the order of the reference.
-        // With refined c-bins the partner search bins on nc c-bins; the
-        // time step and the fast-particle check keep the configured ones.
+        // With split c-bins the slow particles are binned on nc c-bins; the
+        // fast ones, the time step and the fast-particle check keep the
+        // configured ones.
         const double L = g.hi[a] - g.lo[a];
         const int32_t nc = nref ? nref[a] : g.ncell[a];
         d.n[a] = nc;
         d.ncfg[a] = g.ncell[a];
-        d.wref[a] = L / (double)nc;
+        d.inv_wc[a] = (real)((double)g.ncell[a] / L);
         d.no[a] = g.nobin[a];
         d.bc[a] = g.bc[a];
         d.lo[a] = (real)g.lo[a];
@@ -455,16 +459,23 @@ int fill_inst(const tpkmc_particles* s, const tpkmc_instance& q, Inst<real>& d, 
         d.inv_w[a] = (real)((double)nc / L);
         d.inv_wo[a] = (real)((double)g.nobin[a] / L);
     }
+    const bool split = nref && (nref[0] != g.ncell[0] || nref[1] != g.ncell[1] || nref[2] != g.ncell[2]);
+    const int64_t Cf = C;
+    if (split) C = Cf + Cc;
     if (C + 1 > (int64_t)1 << 30 || B > (int64_t)1 << 30) return TPKMC_EINVAL;
     d.off = q.offset;
     d.cnt = q.count;
     d.C = (int32_t)C;
+    d.Cf = (int32_t)Cf;
     d.seed_lo = (uint32_t)p.seed;
     d.seed_hi = (uint32_t)(p.seed >> 32);
     d.step_lo = (uint32_t)p.step;
     d.instance = p.instance;
     d.flags = p.flags | (s->mass ? kHasMass : 0u);
-    if (nref && (nref[0] != g.ncell[0] || nref[1] != g.ncell[1] || nref[2] != g.ncell[2])) d.flags |= kRefined;
+    if (split) {
+        d.flags |= kSplit;
+        d.vc2 = (real)(vc * vc);
+    }
     d.dt = (real)p.dt;
     // Largest accepted d_min^2: sigma = pi D^2 in space, sigma = 2 D in
     // the plane (same expressions as the reference).
@@ -485,7 +496,7 @@ int fill_inst(const tpkmc_particles* s, const tpkmc_instance& q, Inst<real>& d, 
     // walk reads twice.  Planar and one-row grids keep a single band.
     d.band_log2 = 30;
     if (d.n[2] > 1 && d.n[1] > 1 && q.count > 0) {
-        const double row_bytes = (double)d.n[0] * ((double)q.count / (double)C) * 8.0 * sizeof(real);
+        const double row_bytes = (double)d.n[0] * ((double)q.count / (double)Cf) * 8.0 * sizeof(real);
         int h = 0;
         while (h < 30 && (double)(2 << h) * row_bytes <= (double)kBandBytes) ++h;
         if ((1 << h) < d.n[1]) d.band_log2 = h;
@@ -498,13 +509,13 @@ constexpr uint32_t kCellKey = TPKMC_ADAPTIVE_DT | TPKMC_PLANAR | TPKMC_RANK_TIME
 
 // The c-bins autotune chose for batch position k, if the instance there
 // keeps the grid and parameters it was tuned on.
-const int32_t* tuned_cells(const tpkmc_handle* h, int k, const tpkmc_instance& q) {
+const tpkmc_handle::Cells* tuned_cells(const tpkmc_handle* h, int k, const tpkmc_instance& q) {
     if (k >= (int)h->cells.size()) return nullptr;
     const tpkmc_handle::Cells& c = h->cells[k];
     if (std::memcmp(&c.g, &q.grid, sizeof(tpkmc_grid)) != 0 || c.sigma != q.params.sigma ||
         c.dt != q.params.dt || c.flags != (q.params.flags & kCellKey))
         return nullptr;
-    return c.n;
+    return &c;
 }
 
 template <typename real>
@@ -522,8 +533,8 @@ int make_plan(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* i
     P.n_inst = n_inst;
     P.adaptive = false;
     P.any_search = false;
+    P.split = false;
     P.any_random = false;
-    P.refined = false;
     P.ncell_tot = 0;
     P.nob_tot = 0;
     P.max_nob = 0;
@@ -531,9 +542,10 @@ int make_plan(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* i
         const tpkmc_instance& q = in[k];
         Inst<real>& d = I[k];
         int64_t C, B;
-        const int rc = fill_inst<real>(s, q, d, C, B, configured ? nullptr : tuned_cells(h, k, q));
+        const tpkmc_handle::Cells* tc = configured ? nullptr : tuned_cells(h, k, q);
+        const int rc = fill_inst<real>(s, q, d, C, B, tc ? tc->n : nullptr, tc ? tc->vc : 0.0);
         if (rc) return rc;
-        if (d.flags & kRefined) P.refined = true;
+        if (d.flags & kSplit) P.split = true;
         spans.push_back({q.offset, q.count});
         if (q.params.flags & TPKMC_PAIR_RANDOM) P.any_random = true;
         else P.any_search = true;
@@ -642,12 +654,12 @@ void enqueue_scan(const Buffers& B, int64_t n, hipStream_t s) {
 struct Shape {
     int n_inst, nblk, nchunk;
     int64_t ncell_tot, nob_tot, max_nob;
-    bool prep, any_search, any_random;  // prep: some instance needs the prep kernel
+    bool prep, any_search, any_random, split;  // prep: some instance needs the prep kernel
 };
 
 Shape shape_of(const Plan& P) {
     return Shape{P.n_inst, P.nblk, (int)P.chunks.size(), P.ncell_tot, P.nob_tot, P.max_nob,
-                 P.adaptive || P.refined || P.want_vmax, P.any_search, P.any_random};
+                 P.adaptive, P.any_search, P.any_random, P.split};
 }
 
 // Everything of one step after the tables are on the device.  `h` only
@@ -668,7 +680,7 @@ void enqueue_step(tpkmc_handle* h, const Buffers& B, const StepArgs<real>& a, co
     if (P.nblk > 0) {
         PhaseScope ps(h, PH_KEY, s, prof);
         launch_key<real>(a, s);
-        if (P.prep) launch_prep<real>((Inst<real>*)B.inst, B.gpart, B.status, P.n_inst, P.nblk, s);
+        if (P.prep) launch_prep<real>((Inst<real>*)B.inst, B.gpart, P.n_inst, P.nblk, s);
     }
     {
         PhaseScope ps(h, PH_SCAN, s, prof);
@@ -682,6 +694,7 @@ void enqueue_step(tpkmc_handle* h, const Buffers& B, const StepArgs<real>& a, co
         {
             PhaseScope ps(h, PH_SEARCH, s, prof);
             if (P.any_search) launch_search<real>(a, search_block, search_group, s);
+            if (P.split) launch_search_fast<real>(a, P.n_inst, s);
             if (P.any_random) launch_random_pairs<real>(a, s);
         }
         {
@@ -823,17 +836,27 @@ int grow_cells(tpkmc_handle* h, int64_t need) {
     return TPKMC_OK;
 }
 
-// Results-neutral c-bins (range S10 of the partner search): any pair that
-// meets the criteria of Sec. 2.4 within the step starts at most D + |u| dt
-// <= D + 2 v_max dt apart on every axis, so c-bins at least that wide on an
-// axis hold every such pair inside the stencil, and narrowing the configured
-// c-bins on that axis down to that width drops only pairs that cannot
-// collide.  Per instance (not with random partners, whose draw depends on the
-// c-bin) and per axis, the c-bins are refined to the largest count whose
-// width keeps a factor 1.5 over the reach measured on this state, when that
-// at least doubles the configured count (3 or more on periodic axes, one on
-// a planar z), with at most one c-bin per two particles.  Each step checks
-// the reach again (TPKMC_STATUS_CELLS).
+// Split c-bins (range S10 of the partner search).  Two particles of speed at
+// most v_c that meet the criteria of Sec. 2.4 within the step start at most
+// D + 2 v_c dt apart, so the slow particles (|v| <= v_c) can be binned on
+// c-bins down to that width without losing a pair, and every pair of them
+// that meets the criteria lies in neighbouring configured c-bins too.  The
+// fast particles keep the configured c-bins and neighbourhood (the search's
+// fast_records), so the step's results are the configured grid's whatever
+// the speeds do later; only the search's work changes.  The bound is
+// v_c = 3 v_rms over the instance's live particles: a Maxwellian gas has
+// about 6e-6 of its particles above it, and an isolated gas keeps its
+// root-mean-square speed as it thermalises (its energy is conserved), while
+// its largest speed grows with the tail of the distribution.  Per instance
+// (not with random partners, whose draw depends on the c-bin) and per axis,
+// the slow particles' c-bins are the largest count whose width keeps a
+// factor 1 + 1/64 over that reach (the rounding of the binning and of the
+// pair test), used when it is at least 1.25 times the configured count
+// (3 or more on periodic axes, never on a planar z), with at most one c-bin
+// per two particles.
+constexpr double kSpeedBound = 3.0;
+constexpr double kReachMargin = 1.0 + 1.0 / 64.0;
+constexpr double kMinRefine = 1.25;
 template <typename real>
 int choose_cells(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* in, int n_inst, hipStream_t st) {
     h->cells.clear();
@@ -842,40 +865,43 @@ int choose_cells(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance
     if (rc) return rc;
     std::vector<Inst<real>> I(n_inst);
     std::memcpy(I.data(), P.inst_bytes.data(), P.inst_bytes.size());
+    std::vector<double> v2sum(n_inst, 0.0), nlive(n_inst, 0.0);
     if (P.nblk > 0) {
-        for (auto& d : I) d.flags |= kWantVmax;
-        std::memcpy(P.inst_bytes.data(), I.data(), P.inst_bytes.size());
-        P.want_vmax = true;
         if ((rc = upload(h, P, st))) return rc;
         tpkmc_outputs none{};
         StepArgs<real> a = make_args<real>(h->b, s, &none, P.nblk);
-        hipLaunchKernelGGL(k_clear, dim3(1024), dim3(256), 0, st, h->b.start, P.ncell_tot + 1,
-                           (unsigned long long*)nullptr, (int64_t)0, h->b.pair_count);
-        launch_key<real>(a, st);
-        launch_prep<real>((Inst<real>*)h->b.inst, h->b.gpart, h->b.status, P.n_inst, P.nblk, st);
-        if (hipMemcpyAsync(I.data(), h->b.inst, sizeof(Inst<real>) * n_inst, hipMemcpyDeviceToHost, st) !=
+        launch_speed_stats<real>(a, st);
+        std::vector<double> gp((size_t)P.nblk * kGPart);
+        if (hipMemcpyAsync(gp.data(), h->b.gpart, sizeof(double) * gp.size(), hipMemcpyDeviceToHost, st) !=
                 hipSuccess ||
             hipStreamSynchronize(st) != hipSuccess)
             return TPKMC_EHIP;
+        // Summed in block order, so the same state always gives the same c-bins.
+        for (int b = 0; b < P.nblk; ++b) {
+            v2sum[P.blk[b].inst] += gp[(size_t)b * kGPart + GP_PX];
+            nlive[P.blk[b].inst] += gp[(size_t)b * kGPart + GP_PY];
+        }
     }
     int64_t total = 0;
     for (int k = 0; k < n_inst; ++k) {
         const tpkmc_instance& q = in[k];
         tpkmc_handle::Cells c{q.grid, q.params.sigma, q.params.dt, q.params.flags & kCellKey,
-                              {q.grid.ncell[0], q.grid.ncell[1], q.grid.ncell[2]}};
-        const double vmax = sqrt(I[k].vmax2_d);
-        const double reach = sqrt((double)I[k].D2) + 2.0 * vmax * I[k].dt_d;
+                              {q.grid.ncell[0], q.grid.ncell[1], q.grid.ncell[2]}, 0.0};
+        const double vc = nlive[k] > 0.0 ? kSpeedBound * sqrt(v2sum[k] / nlive[k]) : 0.0;
+        const double reach = sqrt((double)I[k].D2) + 2.0 * vc * q.params.dt;
         const bool planar = (q.params.flags & TPKMC_PLANAR) != 0;
+        int64_t cfg = 1;
+        for (int a = 0; a < 3; ++a) cfg *= q.grid.ncell[a];
         if (!(q.params.flags & TPKMC_PAIR_RANDOM) && q.count > 0 && reach > 0.0 && std::isfinite(reach)) {
-            int64_t cfg = 1;
-            for (int a = 0; a < 3; ++a) cfg *= q.grid.ncell[a];
             const int64_t cap = std::max<int64_t>(cfg, q.count / 2);
+            int32_t lo[3];
             for (int a = 0; a < 3; ++a) {
+                lo[a] = (int32_t)std::ceil(kMinRefine * q.grid.ncell[a]);
+                if (q.grid.bc[a] == TPKMC_BC_PERIODIC) lo[a] = std::max(lo[a], 3);
                 if (planar && a == 2) continue;
                 const double L = q.grid.hi[a] - q.grid.lo[a];
-                const double nmax = std::floor(L / (1.5 * reach));
-                if (nmax < 2.0 * q.grid.ncell[a] || nmax > (double)(1 << 24)) continue;
-                if (q.grid.bc[a] == TPKMC_BC_PERIODIC && nmax < 3.0) continue;
+                const double nmax = std::floor(L / (kReachMargin * reach));
+                if (nmax < (double)lo[a] || nmax > (double)(1 << 24)) continue;
                 c.n[a] = (int32_t)nmax;
             }
             // At most `cap` c-bins: shrink the most refined axis first.
@@ -889,13 +915,13 @@ int choose_cells(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance
                     if (f > best) { best = f; a = b; }
                 }
                 if (a < 0) break;
-                int32_t m = (int32_t)std::floor(c.n[a] * 0.9);
-                const int32_t lo = q.grid.bc[a] == TPKMC_BC_PERIODIC ? std::max(3, 2 * q.grid.ncell[a])
-                                                                     : 2 * q.grid.ncell[a];
-                c.n[a] = m >= lo ? m : q.grid.ncell[a];
+                const int32_t m = (int32_t)std::floor(c.n[a] * 0.9);
+                c.n[a] = m >= lo[a] ? m : q.grid.ncell[a];
             }
         }
-        total += (int64_t)c.n[0] * c.n[1] * c.n[2] + 1;
+        const int64_t nslow = (int64_t)c.n[0] * c.n[1] * c.n[2];
+        if (nslow != cfg) c.vc = vc;
+        total += (nslow != cfg ? nslow + cfg : cfg) + 1;
         h->cells.push_back(c);
     }
     if (total > h->cell_cap && (rc = grow_cells(h, total))) {
@@ -923,8 +949,7 @@ int tune_impl(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* i
     hipLaunchKernelGGL(k_clear, dim3(1024), dim3(256), 0, st, h->b.start, P.ncell_tot + 1,
                        (unsigned long long*)nullptr, (int64_t)0, h->b.pair_count);
     launch_key<real>(a, st);
-    if (P.adaptive || P.refined || P.want_vmax)
-        launch_prep<real>((Inst<real>*)h->b.inst, h->b.gpart, h->b.status, P.n_inst, P.nblk, st);
+    if (P.adaptive) launch_prep<real>((Inst<real>*)h->b.inst, h->b.gpart, P.n_inst, P.nblk, st);
     enqueue_scan(h->b, P.ncell_tot + 1, st);
     launch_scatter<real>(a, st);
     hipEvent_t e0, e1;
@@ -1012,12 +1037,11 @@ int mix_impl(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* in
     hipLaunchKernelGGL(k_clear, dim3(1024), dim3(256), 0, st, h->b.start, P.ncell_tot + 1,
                        (unsigned long long*)nullptr, (int64_t)0, h->b.pair_count);
     launch_key<real>(a, st);
-    if (P.adaptive || P.refined || P.want_vmax)
-        launch_prep<real>((Inst<real>*)h->b.inst, h->b.gpart, h->b.status, P.n_inst, P.nblk, st);
+    if (P.adaptive) launch_prep<real>((Inst<real>*)h->b.inst, h->b.gpart, P.n_inst, P.nblk, st);
     enqueue_scan(h->b, P.ncell_tot + 1, st);
     launch_scatter<real>(a, st);
     if (hipMemsetAsync(h->b.mix, 0, 3 * sizeof(unsigned long long), st) != hipSuccess) return TPKMC_EHIP;
-    launch_search_mix<real>(a, h->search_block, st);
+    launch_search_mix<real>(a, h->search_block, P.n_inst, P.split, st);
     if (hipMemcpyAsync(counts, h->b.mix, 3 * sizeof(uint64_t), hipMemcpyDeviceToHost, st) != hipSuccess)
         return TPKMC_EHIP;
     if (hipStreamSynchronize(st) != hipSuccess) return TPKMC_EHIP;
@@ -1305,6 +1329,12 @@ int tpkmc_set_search_order(tpkmc_handle* h, int32_t order) {
 int tpkmc_tuned_cells(tpkmc_handle* h, int32_t k, int32_t ncell[3]) {
     if (!h || !ncell || k < 0 || k >= (int32_t)h->cells.size()) return TPKMC_EINVAL;
     for (int a = 0; a < 3; ++a) ncell[a] = h->cells[k].n[a];
+    return TPKMC_OK;
+}
+
+int tpkmc_tuned_speed(tpkmc_handle* h, int32_t k, double* speed) {
+    if (!h || !speed || k < 0 || k >= (int32_t)h->cells.size()) return TPKMC_EINVAL;
+    *speed = h->cells[k].vc;
     return TPKMC_OK;
 }
 

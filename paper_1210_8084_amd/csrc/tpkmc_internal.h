@@ -71,18 +71,21 @@ struct Inst {
     // one to finish resets both.
     unsigned long long run_v2;
     uint32_t prep_done;
-    // Refined c-bins (kRefined): the configured c-bins per axis and the
-    // refined widths; this step's largest |v|^2 before the move.
+    // Split c-bins (kSplit): a particle is slow when its |v|^2 <= vc2; slow
+    // particles are binned on the n[] c-bins (the first Cf of the C), the
+    // others on the configured ncfg[] c-bins after them, numbered
+    // x + ncfg[0] * (y + ncfg[1] * z).  inv_wc: configured c-bins per unit
+    // length.  vmax2_d: this step's largest |v|^2 before the move.
     int32_t ncfg[3];
-    double wref[3];
+    int32_t Cf;
+    real vc2;
+    real inv_wc[3];
     double vmax2_d;
 };
 
-// Bits of Inst::flags set by the host (outside the public flag bits): the
-// c-bins are a results-neutral refinement of the configured ones (S10 range,
-// checked every step), and the step's largest speed is wanted (tuning).
-constexpr uint32_t kRefined = 1u << 30;
-constexpr uint32_t kWantVmax = 1u << 29;
+// Bit of Inst::flags set by the host (outside the public flag bits): the
+// c-bins are split by speed (slow particles on refined c-bins, see Inst).
+constexpr uint32_t kSplit = 1u << 30;
 
 // Bit of Inst::flags, set by the host (outside the public flag bits): the
 // particles carry their own masses.
@@ -139,12 +142,15 @@ struct StepArgs {
 // Launchers implemented per precision (tpkmc_f32.hip / tpkmc_f64.hip).
 template <typename real> void launch_key(const StepArgs<real>& a, hipStream_t s);
 template <typename real> void launch_scatter(const StepArgs<real>& a, hipStream_t s);
-template <typename real> void launch_prep(Inst<real>* inst, const double* gpart, uint32_t* status, int n_inst,
-                                         int max_nblk, hipStream_t s);
+template <typename real> void launch_prep(Inst<real>* inst, const double* gpart, int n_inst, int max_nblk,
+                                         hipStream_t s);
 template <typename real> void launch_search(const StepArgs<real>& a, int block, int group, hipStream_t s);
-template <typename real> void launch_search_mix(const StepArgs<real>& a, int block, hipStream_t s);
+template <typename real> void launch_search_mix(const StepArgs<real>& a, int block, int n_inst, bool split,
+                                               hipStream_t s);
+template <typename real> void launch_search_fast(const StepArgs<real>& a, int n_inst, hipStream_t s);
 template <typename real> void launch_move(const StepArgs<real>& a, hipStream_t s);
 template <typename real> void launch_moments(const StepArgs<real>& a, hipStream_t s);
 template <typename real> void launch_random_pairs(const StepArgs<real>& a, hipStream_t s);
+template <typename real> void launch_speed_stats(const StepArgs<real>& a, hipStream_t s);
 
 }  // namespace tpkmc

@@ -285,8 +285,17 @@ __device__ __forceinline__ double speed2(double vx, double vy, double vz) {
 }
 
 // ---------------------------------------------------------------- 1. key
+// |v|^2 in the state's precision with fixed fused operations, so that the key
+// and scatter kernels class a particle as slow or fast alike.
+template <typename real>
+__device__ __forceinline__ real speed2_r(real vx, real vy, real vz) {
+    return fma(vz, vz, fma(vy, vy, vx * vx));
+}
+
 // c-bin key of caller-order particle p: its c-bin, or the instance's trailing
-// bin for a dead or non-finite particle.  The key and scatter kernels both
+// bin for a dead or non-finite particle.  With split c-bins a fast particle
+// (|v|^2 above the instance's bound) takes its configured c-bin, numbered
+// after the slow particles' refined ones.  The key and scatter kernels both
 // evaluate it on the same loaded values, so the key is never stored.
 template <typename real>
 __device__ __forceinline__ int cbin_key(const StepArgs<real>& a, const Inst<real>& I, int64_t p, real x, real y,
@@ -297,6 +306,12 @@ __device__ __forceinline__ int cbin_key(const StepArgs<real>& a, const Inst<real
         fin = fin && m > real(0) && m < real(INFINITY);
     }
     if (!(alive && fin)) return (int)(I.cell_off + I.C);
+    if ((I.flags & kSplit) && !(speed2_r(vx, vy, vz) <= I.vc2)) {
+        const int cx = axis_bin(x, I.lo[0], I.inv_wc[0], I.ncfg[0]);
+        const int cy = axis_bin(y, I.lo[1], I.inv_wc[1], I.ncfg[1]);
+        const int cz = axis_bin(z, I.lo[2], I.inv_wc[2], I.ncfg[2]);
+        return (int)I.cell_off + I.Cf + cx + I.ncfg[0] * (cy + I.ncfg[1] * cz);
+    }
     const int cx = axis_bin(x, I.lo[0], I.inv_w[0], I.n[0]);
     const int cy = axis_bin(y, I.lo[1], I.inv_w[1], I.n[1]);
     const int cz = axis_bin(z, I.lo[2], I.inv_w[2], I.n[2]);
@@ -323,7 +338,7 @@ __global__ void __launch_bounds__(kWave) k_key(StepArgs<real> a) {
     const Inst<real>& I = a.inst[bt.inst];
     const int lane = threadIdx.x;
     const int64_t end = I.off + I.cnt;
-    const bool want_v2 = (I.flags & (TPKMC_ADAPTIVE_DT | kRefined | kWantVmax)) != 0;
+    const bool want_v2 = (I.flags & TPKMC_ADAPTIVE_DT) != 0;
     real x[kKeyRec], y[kKeyRec], z[kKeyRec], vx[kKeyRec], vy[kKeyRec], vz[kKeyRec];
     bool alive[kKeyRec];
 #pragma unroll
@@ -647,19 +662,21 @@ __device__ __forceinline__ int cz_of(real z, const Inst<real>& I) { return axis_
 // Visits the record ranges of the neighbourhood of record i (bin cx, cy, cz).
 // HALF: only pairs (i, j) not visited from j's side -- bins of larger index
 // and, in i's own bin, records after i -- so every unordered pair is met once.
-template <bool HALF, typename real, typename F>
+// COARSE: the fast particles of split c-bins, on the configured c-bins n[]
+// (rows y + n_y z after the slow particles' c-bins).
+template <bool HALF, bool COARSE = false, typename real, typename F>
 __device__ __forceinline__ void for_neighbourhood(const int32_t* start, const Inst<real>& I, int64_t base,
                                                   const int n[3], const bool per[3], int cx, int cy, int cz,
                                                   int32_t i, F&& visit) {
-    const int64_t cell_off = I.cell_off;
+    const int64_t cell_off = COARSE ? I.cell_off + I.Cf : I.cell_off;
     int xa[2], xb[2];
     const int nxr = x_ranges(cx, n[0], per[0], xa, xb);
-    const int own_row = row_of(I, cy, cz);
+    const int own_row = COARSE ? cy + n[1] * cz : row_of(I, cy, cz);
     for (int k = 0; k < 9; ++k) {
         int y, z;
         if (!axis_nb(cz, k / 3 - 1, n[2], per[2], z)) continue;
         if (!axis_nb(cy, k % 3 - 1, n[1], per[1], y)) continue;
-        const int row_idx = row_of(I, y, z);
+        const int row_idx = COARSE ? y + n[1] * z : row_of(I, y, z);
         if (HALF && row_idx < own_row) continue;
         const bool own = row_idx == own_row;
         const int64_t row = cell_off + (int64_t)n[0] * row_idx;
@@ -764,19 +781,9 @@ __device__ __forceinline__ void search_group(const StepArgs<real>& a, const Inst
             }
         }
     };
-    // Tests record j against the lane's records k with take[k] set.
-    auto visit = [&](int32_t j, const bool take[G]) {
-        real xj, yj, zj, vxj, vyj, vzj;
-        uint32_t idj = 0;
-        if constexpr (UNIFORM) {
-            RecU<real>::load(a.rec, j, xj, yj, zj, idj, vxj, vyj, vzj);
-        } else if constexpr (HALF) {
-            // FP32 keys carry the record index, not the id: skip that word.
-            Rec<float>::load6(a.rec, (uint32_t)j, xj, yj, zj, vxj, vyj, vzj);
-        } else {
-            uint32_t flj;
-            Rec<real>::load(a.rec, j, xj, yj, zj, idj, vxj, vyj, vzj, flj);
-        }
+    // Tests record j (loaded) against the lane's records k with take[k] set.
+    auto screen = [&](int32_t j, uint32_t idj, real xj, real yj, real zj, real vxj, real vyj, real vzj,
+                      const bool take[G]) {
         Screen<real> S[G];
         bool p1[G];
         bool any1 = false;
@@ -803,6 +810,20 @@ __device__ __forceinline__ void search_group(const StepArgs<real>& a, const Inst
 #pragma unroll
         for (int k = 0; k < G; ++k)
             if (p2[k]) hit(k, j, idj, S[k]);
+    };
+    auto visit = [&](int32_t j, const bool take[G]) {
+        real xj, yj, zj, vxj, vyj, vzj;
+        uint32_t idj = 0;
+        if constexpr (UNIFORM) {
+            RecU<real>::load(a.rec, j, xj, yj, zj, idj, vxj, vyj, vzj);
+        } else if constexpr (HALF) {
+            // FP32 keys carry the record index, not the id: skip that word.
+            Rec<float>::load6(a.rec, (uint32_t)j, xj, yj, zj, vxj, vyj, vzj);
+        } else {
+            uint32_t flj;
+            Rec<real>::load(a.rec, j, xj, yj, zj, idj, vxj, vyj, vzj, flj);
+        }
+        screen(j, idj, xj, yj, zj, vxj, vyj, vzj, take);
     };
 
     if (UNIFORM || joint) {
@@ -884,6 +905,33 @@ __device__ __forceinline__ void search_group(const StepArgs<real>& a, const Inst
             });
         }
     }
+    if constexpr (!HALF) {
+        // Split c-bins: ordered scans also take the fast particles of each
+        // record's configured neighbourhood (binned apart from the slow ones).
+        if (I.flags & kSplit) {
+            const int nc[3] = {I.ncfg[0], I.ncfg[1], I.ncfg[2]};
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                if (k >= nrec) continue;
+                const int ccx = axis_bin(xi[k], I.lo[0], I.inv_wc[0], nc[0]);
+                const int ccy = axis_bin(yi[k], I.lo[1], I.inv_wc[1], nc[1]);
+                const int ccz = axis_bin(zi[k], I.lo[2], I.inv_wc[2], nc[2]);
+                for_neighbourhood<false, true>(a.start, I, base, nc, G_.per, ccx, ccy, ccz, i0 + k,
+                                               [&](int32_t j0, int32_t j1) {
+                    seen += j1 > j0 ? j1 - j0 : 0;
+                    for (int32_t j = j0; j < j1; ++j) {
+                        bool take[G];
+#pragma unroll
+                        for (int kk = 0; kk < G; ++kk) take[kk] = kk == k;
+                        real xj, yj, zj, vxj, vyj, vzj;
+                        uint32_t idj, flj;
+                        Rec<real>::load(a.rec, j, xj, yj, zj, idj, vxj, vyj, vzj, flj);
+                        screen(j, idj, xj, yj, zj, vxj, vyj, vzj, take);
+                    }
+                });
+            }
+        }
+    }
 #pragma unroll
     for (int k = 0; k < G; ++k) {
         if (k >= nrec) continue;
@@ -896,6 +944,155 @@ __device__ __forceinline__ void search_group(const StepArgs<real>& a, const Inst
     // Ordered scans see every pair twice and count the record itself once.
     tests = HALF ? (double)seen : 0.5 * (double)(seen - nrec);
     cand = HALF ? 2.0 * (double)nc : (double)nc;
+}
+
+// ---------------------------------------------------------------- 4a. fast particles of split c-bins
+// With split c-bins the slow particles are binned on refined c-bins, at
+// least as wide as the largest distance at which two slow particles can
+// meet the criteria of Sec. 2.4 within the step (D + 2 v_c dt, v_c the speed
+// bound), so every candidate pair of two slow particles lies in
+// neighbouring refined c-bins, and every such pair that meets the criteria
+// also lies in neighbouring configured c-bins.  The fast particles keep the
+// configured c-bins and the configured 27-bin neighbourhood: their
+// candidates are exactly those of the unsplit grid.
+
+__device__ __forceinline__ int floor_div(int64_t a, int64_t b) {  // b > 0
+    return (int)(a >= 0 ? a / b : -((-a + b - 1) / b));
+}
+
+// Fine (refined) c-bins along one axis that can hold a particle whose
+// configured c-bin neighbours configured c-bin cc (cc - 1 .. cc + 1, wrapped
+// on a periodic axis), as at most two ranges [fa, fb]: the neighbours'
+// extent in fine c-bins, one fine c-bin wider on each side for the rounding
+// of either binning; the particle's configured c-bin is then checked
+// exactly.  On an axis that is not refined the two binnings are the same
+// and the ranges exact.
+__device__ __forceinline__ int fine_span(int cc, int nc, int nf, bool periodic, int fa[2], int fb[2]) {
+    if (periodic && nc <= 3) { fa[0] = 0; fb[0] = nf - 1; return 1; }
+    int c0 = cc - 1, c1 = cc + 1;
+    if (!periodic) { c0 = c0 < 0 ? 0 : c0; c1 = c1 > nc - 1 ? nc - 1 : c1; }
+    int lo = c0, hi = c1;
+    if (nf != nc) {
+        lo = floor_div((int64_t)c0 * nf, nc) - 1;
+        hi = floor_div((int64_t)(c1 + 1) * nf, nc) + 1;
+    }
+    if (!periodic) {
+        fa[0] = lo < 0 ? 0 : lo;
+        fb[0] = hi > nf - 1 ? nf - 1 : hi;
+        return 1;
+    }
+    if (hi - lo + 1 >= nf) { fa[0] = 0; fb[0] = nf - 1; return 1; }
+    if (lo < 0) { fa[0] = 0; fb[0] = hi; fa[1] = lo + nf; fb[1] = nf - 1; return 2; }
+    if (hi > nf - 1) { fa[0] = lo; fb[0] = nf - 1; fa[1] = 0; fb[1] = hi - nf; return 2; }
+    fa[0] = lo; fb[0] = hi;
+    return 1;
+}
+
+// The fast records [i_first, i_first + cnt) of a lane, one at a time.  Each
+// is tested against the slow particles of its configured neighbourhood (the
+// fine rows of fine_span, each record kept only when its configured c-bin
+// is a neighbour) and against the fast ones (configured c-bins; in FP32 the
+// half neighbourhood).  FP32 half scans of slow records never meet a fast
+// particle, so each unordered pair with a fast particle is tested once, here.
+// FP64 scans are ordered: the slow records' scans also take the fast
+// particles of their configured neighbourhood (search_group), these take all.
+// The pair test, the ranking key and the tie-breaks are those of
+// search_group, so the step's results are the unsplit grid's.
+template <typename real, bool HALF, bool MIX>
+__device__ void fast_records(const StepArgs<real>& a, const Inst<real>& I, int64_t base, int32_t i_first, int cnt,
+                             double& tests, double& cand, uint32_t& n_s0, uint32_t& n_c1) {
+    const Geo<real> G_(I);
+    const bool by_time = (I.flags & TPKMC_RANK_TIME) != 0;
+    const int nf[3] = {I.n[0], I.n[1], I.n[2]};
+    const int nc[3] = {I.ncfg[0], I.ncfg[1], I.ncfg[2]};
+    for (int q = 0; q < cnt; ++q) {
+        const int32_t i = i_first + q;
+        real xi, yi, zi, vxi, vyi, vzi;
+        uint32_t idi, fli;
+        Rec<real>::load(a.rec, i, xi, yi, zi, idi, vxi, vyi, vzi, fli);
+        const real pi[3] = {xi, yi, zi};
+        int cc[3], clo[3], cspan[3];
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            cc[ax] = axis_bin(pi[ax], I.lo[ax], I.inv_wc[ax], nc[ax]);
+            if (G_.per[ax] && nc[ax] <= 3) { clo[ax] = 0; cspan[ax] = nc[ax] - 1; }
+            else if (G_.per[ax]) { clo[ax] = cc[ax] == 0 ? nc[ax] - 1 : cc[ax] - 1; cspan[ax] = 2; }
+            else {
+                clo[ax] = cc[ax] > 0 ? cc[ax] - 1 : 0;
+                cspan[ax] = (cc[ax] < nc[ax] - 1 ? cc[ax] + 1 : nc[ax] - 1) - clo[ax];
+            }
+        }
+        unsigned long long mine = ~0ull;
+        int32_t bj = -1;
+        real bd2 = real(0);
+        uint32_t bid = 0;
+        int32_t seen = 0, found = 0;
+        auto test = [&](int32_t j, bool check) {
+            real xj, yj, zj, vxj, vyj, vzj;
+            uint32_t idj, flj;
+            Rec<real>::load(a.rec, j, xj, yj, zj, idj, vxj, vyj, vzj, flj);
+            if (check) {
+                const real pj[3] = {xj, yj, zj};
+                bool in = true;
+#pragma unroll
+                for (int ax = 0; ax < 3; ++ax) {
+                    if (nf[ax] == nc[ax]) continue;
+                    int t = axis_bin(pj[ax], I.lo[ax], I.inv_wc[ax], nc[ax]) - clo[ax];
+                    t += t < 0 ? nc[ax] : 0;
+                    in = in && t <= cspan[ax];
+                }
+                if (!in) return;
+            }
+            ++seen;
+            Screen<real> S;
+            const bool p1 = PairTest<real, -1>::stage1(G_, xi, yi, zi, vxi, vyi, vzi, xj, yj, zj, vxj, vyj, vzj, S);
+            if constexpr (MIX) {
+                n_s0 += S.s0 < real(0) ? 1u : 0u;
+                n_c1 += p1 ? 1u : 0u;
+            }
+            if (!p1 || !PairTest<real, -1>::stage2(G_, S)) return;
+            const real d2 = PairTest<real, -1>::finish(G_, S);
+            if (!(d2 >= real(0))) return;
+            ++found;
+            const real key = by_time ? PairTest<real, -1>::contact(G_, S) : d2;
+            if constexpr (HALF) {
+                const unsigned long long hi = (unsigned long long)sortable((float)key) << 32;
+                atomicMin(a.bkey + j, hi | (uint32_t)i);
+                const unsigned long long kk = hi | (uint32_t)j;
+                mine = kk < mine ? kk : mine;
+            } else {
+                if (bj < 0 || key < bd2 || (key == bd2 && idj < bid)) { bj = j; bd2 = key; bid = idj; }
+            }
+        };
+        int xa[2], xb[2], ya[2], yb[2], za[2], zb[2];
+        const int nxr = fine_span(cc[0], nc[0], nf[0], G_.per[0], xa, xb);
+        const int nyr = fine_span(cc[1], nc[1], nf[1], G_.per[1], ya, yb);
+        const int nzr = fine_span(cc[2], nc[2], nf[2], G_.per[2], za, zb);
+        for (int rz = 0; rz < nzr; ++rz)
+            for (int z = za[rz]; z <= zb[rz]; ++z)
+                for (int ry = 0; ry < nyr; ++ry)
+                    for (int y = ya[ry]; y <= yb[ry]; ++y) {
+                        const int64_t row = I.cell_off + (int64_t)nf[0] * row_of(I, y, z);
+                        for (int rx = 0; rx < nxr; ++rx) {
+                            const int32_t j0 = (int32_t)(base + a.start[row + xa[rx]]);
+                            const int32_t j1 = (int32_t)(base + a.start[row + xb[rx] + 1]);
+                            for (int32_t j = j0; j < j1; ++j) test(j, true);
+                        }
+                    }
+        for_neighbourhood<HALF, true>(a.start, I, base, nc, G_.per, cc[0], cc[1], cc[2], i,
+                                      [&](int32_t j0, int32_t j1) {
+            for (int32_t j = j0; j < j1; ++j) test(j, false);
+        });
+        if constexpr (HALF) {
+            if (mine != ~0ull) atomicMin(a.bkey + i, mine);
+            tests += (double)seen;
+            cand += 2.0 * (double)found;
+        } else {
+            a.best[i] = bj;
+            tests += 0.5 * (double)(seen - 1);  // the record met itself once
+            cand += (double)found;
+        }
+    }
 }
 
 // search_group for the instance's periodic axes: FP32 has builds for the
@@ -948,10 +1145,14 @@ k_search(StepArgs<real> a) {
     double tests = 0.0, cand = 0.0;
     const int64_t live_stop = live_end < end ? live_end : end;
     const int nrec = i0 < live_stop ? (int)(live_stop - i0 < G ? live_stop - i0 : G) : 0;
-    // Wave-uniform mode when the wave's live records lie in at most two
+    // Split c-bins: the slow records come first; the fast ones after them are
+    // searched by k_search_fast.
+    const int64_t slow_stop = (I.flags & kSplit) ? min(base + a.start[I.cell_off + I.Cf], live_stop) : live_stop;
+    const int nslow = i0 < slow_stop ? (int)(slow_stop - i0 < nrec ? slow_stop - i0 : nrec) : 0;
+    // Wave-uniform mode when the wave's live slow records lie in at most two
     // neighbouring bins of one row (dense bins): decided on the first and
-    // last live record, so the branch is uniform.
-    const uint64_t live = __ballot(nrec > 0);
+    // last of them, so the branch is uniform.
+    const uint64_t live = __ballot(nslow > 0);
     bool uni = false;
     int32_t wfirst = 0;
     int wub = 0;
@@ -959,7 +1160,7 @@ k_search(StepArgs<real> a) {
         const int fl = __ffsll((long long)live) - 1;
         const int ll = 63 - __clzll((long long)live);
         wfirst = __builtin_amdgcn_readlane((int32_t)i0, fl);
-        const int32_t wlast = __builtin_amdgcn_readlane((int32_t)(i0 + nrec - 1), ll);
+        const int32_t wlast = __builtin_amdgcn_readlane((int32_t)(i0 + nslow - 1), ll);
         real xf, yf, zf, vxf, vyf, vzf, xl, yl, zl, vxl, vyl, vzl;
         uint32_t idf, idl;
         RecU<real>::load(a.rec, wfirst, xf, yf, zf, idf, vxf, vyf, vzf);
@@ -977,12 +1178,14 @@ k_search(StepArgs<real> a) {
     }
     uint32_t n_s0 = 0, n_c1 = 0;
     if (uni) {
-        if (nrec > 0)
-            search_for_axes<real, HALF, G, true, MIX>(pm, a, I, base, (int32_t)i0, nrec, wfirst, wub, tests, cand,
+        if (nslow > 0)
+            search_for_axes<real, HALF, G, true, MIX>(pm, a, I, base, (int32_t)i0, nslow, wfirst, wub, tests, cand,
                                                       n_s0, n_c1);
-    } else if (nrec > 0) {
-        search_for_axes<real, HALF, G, false, MIX>(pm, a, I, base, (int32_t)i0, nrec, 0, 0, tests, cand, n_s0, n_c1);
+    } else if (nslow > 0) {
+        search_for_axes<real, HALF, G, false, MIX>(pm, a, I, base, (int32_t)i0, nslow, 0, 0, tests, cand, n_s0,
+                                                   n_c1);
     }
+
     if constexpr (MIX) {
         // Counted twice per unordered pair, so every work-group's share is an
         // integer: ordered scans meet each pair from both sides (s0 is
@@ -1012,6 +1215,50 @@ k_search(StepArgs<real> a) {
         } else {
             unsafeAtomicAdd(gp + GP_TESTS2, 2.0 * t);
             unsafeAtomicAdd(gp + GP_CAND, c);
+        }
+    }
+}
+
+// The fast records of split c-bins, in a launch of their own after k_search
+// (FP32 keys combine with atomicMin in any order; in FP64 each fast record
+// writes its own partner), so that the slow records' search keeps its
+// register budget.  Threads stride over each instance's fast records; the
+// search's work counters go to the block-table entry holding the record.
+template <typename real, bool HALF, bool MIX = false>
+__global__ void __launch_bounds__(256) k_search_fast(StepArgs<real> a, int n_inst) {
+    __shared__ double lds[16];
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+    double mt = 0.0;
+    uint32_t n_s0 = 0, n_c1 = 0;
+    for (int k = 0; k < n_inst; ++k) {
+        const Inst<real>& I = a.inst[k];
+        if (!(I.flags & kSplit) || (I.flags & TPKMC_PAIR_RANDOM)) continue;
+        const int64_t base = I.off - a.start[I.cell_off];
+        const int64_t f0 = base + a.start[I.cell_off + I.Cf];
+        const int64_t live_end = base + a.start[I.cell_off + I.C];
+        const int64_t f1 = live_end < I.off + I.cnt ? live_end : I.off + I.cnt;
+        for (int64_t r = f0 + tid; r < f1; r += nth) {
+            double t = 0.0, c = 0.0;
+            fast_records<real, HALF, MIX>(a, I, base, (int32_t)r, 1, t, c, n_s0, n_c1);
+            if constexpr (MIX) {
+                mt += t;
+            } else {
+                double* gp = a.gpart + (int64_t)(I.blk0 + (r - I.off) / kBlock) * kGPart;
+                if (t > 0.0) unsafeAtomicAdd(gp + GP_TESTS2, 2.0 * t);
+                if (c > 0.0) unsafeAtomicAdd(gp + GP_CAND, c);
+            }
+        }
+    }
+    if constexpr (MIX) {
+        // The counting convention of k_search's diagnostic build.
+        const double f = HALF ? 2.0 : 1.0;
+        const double t0 = block_sum(2.0 * mt, lds), t1 = block_sum(f * (double)n_s0, lds),
+                     t2 = block_sum(f * (double)n_c1, lds);
+        if (threadIdx.x == 0) {
+            if (t0 > 0.0) atomicAdd(a.mix + 0, (unsigned long long)t0);
+            if (t1 > 0.0) atomicAdd(a.mix + 1, (unsigned long long)t1);
+            if (t2 > 0.0) atomicAdd(a.mix + 2, (unsigned long long)t2);
         }
     }
 }
@@ -1704,18 +1951,15 @@ __global__ void __launch_bounds__(kBlock) k_moments(StepArgs<real> a) {
 // Per instance, from the work-group maxima of |v|^2 left by the key kernel:
 // the step's largest speed; with ADAPTIVE_DT the time step of Sec. 3,
 // dt = dx / v_max (dx of the configured c-bins), the caller's dt being the
-// cap; with refined c-bins the check that each refined width still holds
-// the pair reach D + 2 v_max dt, so that every pair the configured c-bins
-// allow is still inside the stencil (TPKMC_STATUS_CELLS otherwise).
-// gridDim.x work-groups per instance fold the maxima into a running maximum
-// (a single work-group would wait on its loads one after another); the last
-// to arrive writes the instance's quantities for the later kernels.
+// cap.  gridDim.x work-groups per instance fold the maxima into a running
+// maximum (a single work-group would wait on its loads one after another);
+// the last to arrive writes the instance's quantities for the later kernels.
 template <typename real>
-__global__ void __launch_bounds__(256) k_prep(Inst<real>* inst, const double* gpart, uint32_t* status) {
+__global__ void __launch_bounds__(256) k_prep(Inst<real>* inst, const double* gpart) {
     __shared__ double lds[16];
     __shared__ bool last;
     Inst<real>& I = inst[blockIdx.y];
-    if (!(I.flags & (TPKMC_ADAPTIVE_DT | kRefined | kWantVmax))) return;  // whole work-group
+    if (!(I.flags & TPKMC_ADAPTIVE_DT)) return;  // whole work-group
     double v = 0.0;
     const double* g0 = gpart + (int64_t)I.blk0 * kGPart;
     for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < I.nblk; b += gridDim.x * blockDim.x)
@@ -1742,11 +1986,30 @@ __global__ void __launch_bounds__(256) k_prep(Inst<real>* inst, const double* gp
         I.dt_d = dt;
         I.dt = (real)dt;
     }
-    if (I.flags & kRefined) {
-        const double reach = sqrt((double)I.D2) + 2.0 * sqrt(vmax2) * I.dt_d;
-        bool ok = true;
-        for (int ax = 0; ax < 3; ++ax) ok = ok && (I.n[ax] == I.ncfg[ax] || I.wref[ax] >= reach);
-        if (!ok) atomicOr(status, (uint32_t)TPKMC_STATUS_CELLS);
+}
+
+// Tuning statistics of the speeds: per work-group, the sum of |v|^2 and the
+// count of live particles with a finite state, in the slots GP_PX and GP_PY
+// (free until the move writes them).
+template <typename real>
+__global__ void __launch_bounds__(kBlock) k_speed_stats(StepArgs<real> a) {
+    __shared__ double lds[16];
+    const Blk bt = a.blk[blockIdx.x];
+    const Inst<real>& I = a.inst[bt.inst];
+    const int64_t p = (int64_t)bt.first + threadIdx.x;
+    double v2 = 0.0, n = 0.0;
+    if (p < I.off + I.cnt && (a.alive == nullptr || a.alive[p] != 0)) {
+        const double vx = (double)a.vx[p], vy = (double)a.vy[p], vz = (double)a.vz[p];
+        if (finite3((double)a.x[p], (double)a.y[p], (double)a.z[p]) && finite3(vx, vy, vz)) {
+            v2 = speed2(vx, vy, vz);
+            n = 1.0;
+        }
+    }
+    v2 = block_sum(v2, lds);
+    n = block_sum(n, lds);
+    if (threadIdx.x == 0) {
+        a.gpart[(int64_t)blockIdx.x * kGPart + GP_PX] = v2;
+        a.gpart[(int64_t)blockIdx.x * kGPart + GP_PY] = n;
     }
 }
 
@@ -1760,9 +2023,13 @@ void launch_scatter(const StepArgs<real>& a, hipStream_t s) {
     hipLaunchKernelGGL(k_scatter<real>, dim3(a.nblk), dim3(kBlock), 0, s, a);
 }
 template <typename real>
-void launch_prep(Inst<real>* inst, const double* gpart, uint32_t* status, int n_inst, int max_nblk, hipStream_t s) {
+void launch_prep(Inst<real>* inst, const double* gpart, int n_inst, int max_nblk, hipStream_t s) {
     const int gx = std::max(1, std::min(64, (max_nblk + 1023) / 1024));
-    hipLaunchKernelGGL(k_prep<real>, dim3(gx, n_inst), dim3(256), 0, s, inst, gpart, status);
+    hipLaunchKernelGGL(k_prep<real>, dim3(gx, n_inst), dim3(256), 0, s, inst, gpart);
+}
+template <typename real>
+void launch_speed_stats(const StepArgs<real>& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_speed_stats<real>, dim3(a.nblk), dim3(kBlock), 0, s, a);
 }
 template <typename real>
 void launch_search(const StepArgs<real>& a, int block, int group, hipStream_t s) {
@@ -1775,12 +2042,22 @@ void launch_search(const StepArgs<real>& a, int block, int group, hipStream_t s)
     else hipLaunchKernelGGL((k_search<real, half, 1>), dim3(grid), dim3(bs), 0, s, a);
 }
 template <typename real>
-void launch_search_mix(const StepArgs<real>& a, int block, hipStream_t s) {
+void launch_search_mix(const StepArgs<real>& a, int block, int n_inst, bool split, hipStream_t s) {
     constexpr bool half = std::is_same<real, float>::value;
     const int lanes = kBlock / 2;
     const int bs = block < lanes ? block : lanes;
     const unsigned grid = (unsigned)a.nblk * (unsigned)(lanes / bs);
     hipLaunchKernelGGL((k_search<real, half, 2, true>), dim3(grid), dim3(bs), 0, s, a);
+    if (split) {
+        const unsigned fg = (unsigned)std::max(1, std::min(2048, a.nblk));
+        hipLaunchKernelGGL((k_search_fast<real, half, true>), dim3(fg), dim3(256), 0, s, a, n_inst);
+    }
+}
+template <typename real>
+void launch_search_fast(const StepArgs<real>& a, int n_inst, hipStream_t s) {
+    constexpr bool half = std::is_same<real, float>::value;
+    const unsigned fg = (unsigned)std::max(1, std::min(2048, a.nblk));
+    hipLaunchKernelGGL((k_search_fast<real, half>), dim3(fg), dim3(256), 0, s, a, n_inst);
 }
 template <typename real>
 void launch_random_pairs(const StepArgs<real>& a, hipStream_t s) {

@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(HERE, "libtpkmc.so")
 FP64, FP32 = 0, 1
 REFLECT, PERIODIC, ABSORB = 0, 1, 2
 EMIT_PAIRS, ALLOW_REORDER, ADAPTIVE_DT, PLANAR, RANK_TIME, PAIR_RANDOM = 1, 2, 4, 8, 16, 32
-STATUS_PAIR_OVERFLOW, STATUS_NONFINITE, STATUS_FAST, STATUS_CELLS = 1, 2, 4, 8
+STATUS_PAIR_OVERFLOW, STATUS_NONFINITE, STATUS_FAST = 1, 2, 4
 CNT = dict(alive=0, pairs=1, tests=2, cand=3, fast=4, nonfinite=5, absorbed=6, have_best=7)
 GLB = dict(px=0, py=1, pz=2, ekin=3, vmax2=4, virial=5, mass=6, dt=7)
 PHASES = ("clear", "key", "scan", "scatter", "search", "move", "finalize")
@@ -98,12 +98,13 @@ def lib():
         L.tpkmc_step_noalloc.argtypes = [ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P]
         L.tpkmc_search_mix.argtypes = [_P, _P, _P, ctypes.c_int32, _P, _P]
         L.tpkmc_tuned_cells.argtypes = [_P, ctypes.c_int32, _P]
+        L.tpkmc_tuned_speed.argtypes = [_P, ctypes.c_int32, _P]
         L.tpkmc_search_order.argtypes = [_P, _P]
         L.tpkmc_set_search_order.argtypes = [_P, ctypes.c_int32]
         for f in ("tpkmc_create", "tpkmc_destroy", "tpkmc_step", "tpkmc_step_batched", "tpkmc_run",
                   "tpkmc_autotune", "tpkmc_status", "tpkmc_profile_enable", "tpkmc_profile_read",
                   "tpkmc_set_search", "tpkmc_get_search", "tpkmc_step_noalloc", "tpkmc_search_mix",
-                  "tpkmc_tuned_cells", "tpkmc_search_order", "tpkmc_set_search_order"):
+                  "tpkmc_tuned_cells", "tpkmc_tuned_speed", "tpkmc_search_order", "tpkmc_set_search_order"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -340,10 +341,17 @@ class Engine:
         _check(lib().tpkmc_set_search_order(self.h, int(order)), "tpkmc_set_search_order")
 
     def tuned_cells(self, k=0):
-        """c-bins per axis that autotune chose for batch position k."""
+        """The slow particles' c-bins per axis that autotune chose for batch
+        position k."""
         n = (ctypes.c_int32 * 3)()
         _check(lib().tpkmc_tuned_cells(self.h, int(k), n), "tpkmc_tuned_cells")
         return tuple(int(v) for v in n)
+
+    def tuned_speed(self, k=0):
+        """Speed bound of the slow particles at batch position k (0: no split)."""
+        v = ctypes.c_double()
+        _check(lib().tpkmc_tuned_speed(self.h, int(k), ctypes.byref(v)), "tpkmc_tuned_speed")
+        return float(v.value)
 
     def set_search(self, group, block):
         """Fix the partner-search launch shape: `group` records per lane (1, 2

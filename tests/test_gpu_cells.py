@@ -1,18 +1,19 @@
-"""Results-neutral c-bins chosen by the autotuner (S10 of the partner
-search): where a c-bin is at least D + 2 v_max dt wide on an axis, every pair
-that can meet the criteria of Sec. 2.4 in a step lies inside the stencil, so
-c-bins refined down to that width (with a margin) change nothing but the
-search's work.
+"""c-bins split by speed, chosen by the autotuner (S10 of the partner
+search).  Two particles of speed at most v_c that meet the criteria of
+Sec. 2.4 within a step start at most D + 2 v_c dt apart, so the slow
+particles are searched on c-bins refined down to that width and the fast
+ones on the configured c-bins against every particle of their configured
+neighbourhood; nothing but the search's work changes, at any speeds.
 
- - FP64: after autotune refines a tube's c-bins, steps equal the oracle's on
-   the configured c-bins bit for bit (state, pairs, counters other than the
-   search's work counters), with far fewer pair tests.
+ - FP64: steps on split c-bins equal the oracle's on the configured ones bit
+   for bit (state, pairs, counters other than the search's work counters,
+   moments): a shock tube; boxes holding a fast population (walls, periodic
+   axes including one of three configured c-bins, absorbing walls, the
+   plane, contact-time ranking); a tube whose speeds are raised after tuning.
  - Random partners (their draw depends on the c-bin) keep the configured
    c-bins; a planar grid keeps one c-bin on z.
- - Each step checks the reach with its own v_max: speeds raised after
-   tuning set TPKMC_STATUS_CELLS.
  - FP32: the tuned handle's pairs equal an untuned handle's, also through a
-   captured graph and inside a batch."""
+   captured graph, with fast particles, and inside a batch."""
 import numpy as np
 import pytest
 
@@ -52,7 +53,7 @@ def test_fp64_refined_tube_equals_oracle(T, oracle):
     dst = T.to_device(w.state, T.FP64)
     eng.autotune(dst, [(0, w.n, g, p)])
     cells = eng.tuned_cells(0)
-    print("configured", g["ncell"], "tuned", cells, flush=True)
+    print("configured", g["ncell"], "tuned", cells, "speed bound", eng.tuned_speed(0), flush=True)
     assert cells[1] >= 3 and cells[2] >= 3 and np.prod(cells) >= 4 * np.prod(g["ncell"])
     out = T.make_outputs(1, T.nobins(g), pair_cap=w.n)
     st = W.copy_state(w.state)
@@ -72,7 +73,6 @@ def test_fp64_refined_tube_equals_oracle(T, oracle):
         assert gc[T.CNT["tests"]] * 4 < rc[T.CNT["tests"]], (gc[T.CNT["tests"]], rc[T.CNT["tests"]])
         assert np.array_equal(go["moments"][:, 0], ro["moments"][:, 0])
         assert rc[T.CNT["pairs"]] > 100
-    assert eng.status() & T.STATUS_CELLS == 0
     eng.close()
 
 
@@ -82,7 +82,7 @@ def test_random_partners_and_plane_keep_their_cells(T):
     eng = engine(T, w, T.FP64)
     dst = T.to_device(w.state, T.FP64)
     eng.autotune(dst, [(0, w.n, g, p)])
-    assert eng.tuned_cells(0) == tuple(g["ncell"])
+    assert eng.tuned_cells(0) == tuple(g["ncell"]) and eng.tuned_speed(0) == 0.0
     eng.close()
     w2 = tube(planar=True)
     eng = engine(T, w2, T.FP64)
@@ -93,21 +93,98 @@ def test_random_partners_and_plane_keep_their_cells(T):
     eng.close()
 
 
-def test_speeds_beyond_the_tuned_reach_are_flagged(T):
-    w = tube()
+def fast_box(n, seed, ncell, bc, planar=False, rank_time=False, fast_frac=0.01, fast_speed=20.0):
+    """A Gaussian gas (unit speed per component) with a fraction of fast
+    particles at fast_speed, isotropic; D is a quarter of the smallest
+    configured c-bin and the gas moves 2% of it per step, so the slow
+    particles' reach lets the autotuner refine their c-bins about 1.5 times
+    per axis while the fast ones stay above the speed bound."""
+    w = W.random_box(n=n, seed=seed, ncell=ncell, bc=bc, d_over_w=0.25, dt_over=0.02)
+    rng = np.random.default_rng(seed + 100)
+    fast = rng.random(n) < fast_frac
+    d = rng.normal(size=(3, n))
+    d /= np.sqrt((d * d).sum(axis=0))
+    for k, a in enumerate(("vx", "vy", "vz")):
+        w.state[a] = np.where(fast, fast_speed * d[k], w.state[a])
+    p = dict(w.params, rank_time=rank_time)
+    if planar:
+        # In the plane sigma = 2 D.
+        wmin = min((h - l) / c for l, h, c in zip(w.grid["lo"], w.grid["hi"], w.grid["ncell"]) if c > 1)
+        p = dict(p, planar=True, sigma=2.0 * 0.25 * wmin)
+        w.state["z"] = np.full(n, 0.5 * (w.grid["lo"][2] + w.grid["hi"][2]))
+        w.state["vz"] = np.zeros(n)
+    w.params = p
+    return w
+
+
+def fp64_steps_equal_oracle(T, oracle, w, steps=3, after_tune=None):
+    """FP64 steps on the autotuned (split) c-bins against the oracle on the
+    configured ones; returns the tuned c-bins and the speed bound."""
     g, p = w.grid, w.params
     eng = engine(T, w, T.FP64)
     dst = T.to_device(w.state, T.FP64)
     eng.autotune(dst, [(0, w.n, g, p)])
-    out = T.make_outputs(1, T.nobins(g))
-    eng.step(dst, g, p, out)
-    assert eng.status() & T.STATUS_CELLS == 0
-    for k in ("vx", "vy", "vz"):
-        dst[k].mul_(8.0)
-    eng.step(dst, g, dict(p, step=1), out)
-    assert eng.status() & T.STATUS_CELLS
+    cells, vc = eng.tuned_cells(0), eng.tuned_speed(0)
+    st = W.copy_state(w.state)
+    if after_tune:
+        after_tune(st)
+        dst = T.to_device(st, T.FP64)
+    out = T.make_outputs(1, T.nobins(g), pair_cap=w.n)
+    n_fast = 0
+    for s in range(steps):
+        v = np.sqrt(st["vx"] ** 2 + st["vy"] ** 2 + st["vz"] ** 2)
+        n_fast += int(((v > vc) & (st["alive"] != 0)).sum())
+        eng.step(dst, g, dict(p, step=s), out, flags=T.EMIT_PAIRS)
+        torch.cuda.synchronize()
+        go = out.host()
+        ro = oracle.step(st, g, dict(p, step=s))
+        got = T.to_host(dst)
+        for k in ("x", "y", "z", "vx", "vy", "vz", "alive"):
+            assert np.array_equal(got[k], st[k]), (s, k)
+        assert sorted(map(tuple, go["pairs"].tolist())) == sorted(map(tuple, np.asarray(ro["pairs"]).tolist()))
+        gc, rc = go["counters"][0], ro["counters"]
+        for name, k in T.CNT.items():
+            if name not in WORK:
+                assert gc[k] == rc[k], (s, name)
+        assert np.array_equal(go["moments"][:, 0], ro["moments"][:, 0])
+        assert rc[T.CNT["pairs"]] > 50
     eng.close()
+    return cells, vc, n_fast
 
+
+CASES = {
+    "walls": dict(ncell=(6, 5, 4), bc=(R, R, R)),
+    "periodic": dict(ncell=(3, 6, 5), bc=(P, P, P)),
+    "absorb": dict(ncell=(6, 5, 4), bc=(A, P, R)),
+    "plane": dict(ncell=(8, 6, 1), bc=(R, P, P), planar=True),
+    "contact time": dict(ncell=(6, 5, 4), bc=(P, R, P), rank_time=True),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_fp64_split_with_fast_particles_equals_oracle(T, oracle, case):
+    kw = dict(CASES[case])
+    w = fast_box(n=24_000, seed=41, **kw)
+    cells, vc, n_fast = fp64_steps_equal_oracle(T, oracle, w)
+    print(case, "configured", w.grid["ncell"], "tuned", cells, "speed bound", vc, "fast", n_fast, flush=True)
+    refined = [a for a in range(3) if cells[a] > w.grid["ncell"][a]]
+    assert len(refined) >= 2 and vc > 0.0
+    assert n_fast > 100
+
+
+def test_fp64_speeds_raised_after_tuning_equal_oracle(T, oracle):
+    """Tuned on a cold tube; then a tenth of the particles move 30 times
+    faster, far above the speed bound: they are searched on the configured
+    c-bins and the steps still equal the oracle's."""
+    w = tube()
+
+    def raise_speeds(st):
+        sel = np.arange(w.n) % 10 == 3
+        for k in ("vx", "vy", "vz"):
+            st[k] = np.where(sel, 30.0 * st[k], st[k])
+
+    cells, vc, n_fast = fp64_steps_equal_oracle(T, oracle, w, after_tune=raise_speeds)
+    assert np.prod(cells) > np.prod(w.grid["ncell"]) and n_fast > 1000
 
 def _fp32_pairs(T, w, tune, steps=2, graph=False):
     g, p = w.grid, w.params
@@ -132,8 +209,9 @@ def _fp32_pairs(T, w, tune, steps=2, graph=False):
 
 
 @pytest.mark.parametrize("graph", [False, True], ids=["step", "graph"])
-def test_fp32_tuned_cells_keep_the_pairs(T, graph):
-    w = tube(n=60_000, seed=7)
+@pytest.mark.parametrize("kind", ["tube", "fast particles"])
+def test_fp32_tuned_cells_keep_the_pairs(T, graph, kind):
+    w = tube(n=60_000, seed=7) if kind == "tube" else fast_box(n=60_000, seed=8, ncell=(6, 5, 4), bc=(R, P, P))
     ref, _ = _fp32_pairs(T, w, tune=False)
     got, cells = _fp32_pairs(T, w, tune=True, graph=graph)
     assert np.prod(cells) > np.prod(w.grid["ncell"])
