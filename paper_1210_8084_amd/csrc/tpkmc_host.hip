@@ -659,7 +659,7 @@ struct Shape {
 
 Shape shape_of(const Plan& P) {
     return Shape{P.n_inst, P.nblk, (int)P.chunks.size(), P.ncell_tot, P.nob_tot, P.max_nob,
-                 P.adaptive, P.any_search, P.any_random, P.split};
+                 P.adaptive || P.split, P.any_search, P.any_random, P.split};
 }
 
 // Everything of one step after the tables are on the device.  `h` only
@@ -842,21 +842,26 @@ int grow_cells(tpkmc_handle* h, int64_t need) {
 // c-bins down to that width without losing a pair, and every pair of them
 // that meets the criteria lies in neighbouring configured c-bins too.  The
 // fast particles keep the configured c-bins and neighbourhood (the search's
-// fast_records), so the step's results are the configured grid's whatever
-// the speeds do later; only the search's work changes.  The bound is
-// v_c = 3 v_rms over the instance's live particles: a Maxwellian gas has
+// fast particle pass), so the step's results are the configured grid's
+// whatever the speeds do later; only the search's work changes.  The bound
+// is v_c = 3 v_rms over the instance's live particles: a Maxwellian gas has
 // about 6e-6 of its particles above it, and an isolated gas keeps its
 // root-mean-square speed as it thermalises (its energy is conserved), while
-// its largest speed grows with the tail of the distribution.  Per instance
-// (not with random partners, whose draw depends on the c-bin) and per axis,
-// the slow particles' c-bins are the largest count whose width keeps a
-// factor 1 + 1/64 over that reach (the rounding of the binning and of the
-// pair test), used when it is at least 1.25 times the configured count
-// (3 or more on periodic axes, never on a planar z), with at most one c-bin
-// per two particles.
+// its largest speed grows with the tail of the distribution.  The split is
+// used only when the particles above v_c hold less than a tenth of the
+// kinetic energy: where they hold most of it (a point blast), collisions
+// share it out and lift many more particles above the bound later in the
+// run, whose searches then cost more than the refinement saves.  Per
+// instance (not with random partners, whose draw depends on the c-bin) and
+// per axis, the slow particles' c-bins are the largest count whose width
+// keeps a factor 1 + 1/64 over that reach (the rounding of the binning and
+// of the pair test), used when it is at least 1.25 times the configured
+// count (3 or more on periodic axes, never on a planar z), with at most one
+// c-bin per two particles.
 constexpr double kSpeedBound = 3.0;
 constexpr double kReachMargin = 1.0 + 1.0 / 64.0;
 constexpr double kMinRefine = 1.25;
+constexpr double kHotEnergy = 0.1;
 template <typename real>
 int choose_cells(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* in, int n_inst, hipStream_t st) {
     h->cells.clear();
@@ -865,21 +870,37 @@ int choose_cells(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance
     if (rc) return rc;
     std::vector<Inst<real>> I(n_inst);
     std::memcpy(I.data(), P.inst_bytes.data(), P.inst_bytes.size());
-    std::vector<double> v2sum(n_inst, 0.0), nlive(n_inst, 0.0);
+    std::vector<double> v2sum(n_inst, 0.0), nlive(n_inst, 0.0), hot(n_inst, 0.0);
     if (P.nblk > 0) {
-        if ((rc = upload(h, P, st))) return rc;
-        tpkmc_outputs none{};
-        StepArgs<real> a = make_args<real>(h->b, s, &none, P.nblk);
-        launch_speed_stats<real>(a, st);
-        std::vector<double> gp((size_t)P.nblk * kGPart);
-        if (hipMemcpyAsync(gp.data(), h->b.gpart, sizeof(double) * gp.size(), hipMemcpyDeviceToHost, st) !=
-                hipSuccess ||
-            hipStreamSynchronize(st) != hipSuccess)
-            return TPKMC_EHIP;
-        // Summed in block order, so the same state always gives the same c-bins.
-        for (int b = 0; b < P.nblk; ++b) {
-            v2sum[P.blk[b].inst] += gp[(size_t)b * kGPart + GP_PX];
-            nlive[P.blk[b].inst] += gp[(size_t)b * kGPart + GP_PY];
+        // Two passes: the root-mean-square speeds, then the energy held above
+        // each instance's bound.
+        for (int pass = 0; pass < 2; ++pass) {
+            if (pass == 1) {
+                for (int k = 0; k < n_inst; ++k) {
+                    const double vc = nlive[k] > 0.0 ? kSpeedBound * sqrt(v2sum[k] / nlive[k]) : 0.0;
+                    I[k].vc2 = (real)(vc * vc);
+                }
+                std::memcpy(P.inst_bytes.data(), I.data(), P.inst_bytes.size());
+            }
+            if ((rc = upload(h, P, st))) return rc;
+            tpkmc_outputs none{};
+            StepArgs<real> a = make_args<real>(h->b, s, &none, P.nblk);
+            launch_speed_stats<real>(a, st);
+            std::vector<double> gp((size_t)P.nblk * kGPart);
+            if (hipMemcpyAsync(gp.data(), h->b.gpart, sizeof(double) * gp.size(), hipMemcpyDeviceToHost, st) !=
+                    hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess)
+                return TPKMC_EHIP;
+            // Summed in block order, so the same state always gives the same c-bins.
+            for (int b = 0; b < P.nblk; ++b) {
+                const int k = P.blk[b].inst;
+                if (pass == 0) {
+                    v2sum[k] += gp[(size_t)b * kGPart + GP_PX];
+                    nlive[k] += gp[(size_t)b * kGPart + GP_PY];
+                } else {
+                    hot[k] += gp[(size_t)b * kGPart + GP_PZ];
+                }
+            }
         }
     }
     int64_t total = 0;
@@ -892,7 +913,8 @@ int choose_cells(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance
         const bool planar = (q.params.flags & TPKMC_PLANAR) != 0;
         int64_t cfg = 1;
         for (int a = 0; a < 3; ++a) cfg *= q.grid.ncell[a];
-        if (!(q.params.flags & TPKMC_PAIR_RANDOM) && q.count > 0 && reach > 0.0 && std::isfinite(reach)) {
+        const bool cold = !(hot[k] > kHotEnergy * v2sum[k]);
+        if (!(q.params.flags & TPKMC_PAIR_RANDOM) && q.count > 0 && reach > 0.0 && std::isfinite(reach) && cold) {
             const int64_t cap = std::max<int64_t>(cfg, q.count / 2);
             int32_t lo[3];
             for (int a = 0; a < 3; ++a) {
@@ -949,7 +971,7 @@ int tune_impl(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* i
     hipLaunchKernelGGL(k_clear, dim3(1024), dim3(256), 0, st, h->b.start, P.ncell_tot + 1,
                        (unsigned long long*)nullptr, (int64_t)0, h->b.pair_count);
     launch_key<real>(a, st);
-    if (P.adaptive) launch_prep<real>((Inst<real>*)h->b.inst, h->b.gpart, P.n_inst, P.nblk, st);
+    if (P.adaptive || P.split) launch_prep<real>((Inst<real>*)h->b.inst, h->b.gpart, P.n_inst, P.nblk, st);
     enqueue_scan(h->b, P.ncell_tot + 1, st);
     launch_scatter<real>(a, st);
     hipEvent_t e0, e1;
@@ -1037,7 +1059,7 @@ int mix_impl(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* in
     hipLaunchKernelGGL(k_clear, dim3(1024), dim3(256), 0, st, h->b.start, P.ncell_tot + 1,
                        (unsigned long long*)nullptr, (int64_t)0, h->b.pair_count);
     launch_key<real>(a, st);
-    if (P.adaptive) launch_prep<real>((Inst<real>*)h->b.inst, h->b.gpart, P.n_inst, P.nblk, st);
+    if (P.adaptive || P.split) launch_prep<real>((Inst<real>*)h->b.inst, h->b.gpart, P.n_inst, P.nblk, st);
     enqueue_scan(h->b, P.ncell_tot + 1, st);
     launch_scatter<real>(a, st);
     if (hipMemsetAsync(h->b.mix, 0, 3 * sizeof(unsigned long long), st) != hipSuccess) return TPKMC_EHIP;

@@ -338,7 +338,7 @@ __global__ void __launch_bounds__(kWave) k_key(StepArgs<real> a) {
     const Inst<real>& I = a.inst[bt.inst];
     const int lane = threadIdx.x;
     const int64_t end = I.off + I.cnt;
-    const bool want_v2 = (I.flags & TPKMC_ADAPTIVE_DT) != 0;
+    const bool want_v2 = (I.flags & (TPKMC_ADAPTIVE_DT | kSplit)) != 0;
     real x[kKeyRec], y[kKeyRec], z[kKeyRec], vx[kKeyRec], vy[kKeyRec], vz[kKeyRec];
     bool alive[kKeyRec];
 #pragma unroll
@@ -664,32 +664,38 @@ __device__ __forceinline__ int cz_of(real z, const Inst<real>& I) { return axis_
 // and, in i's own bin, records after i -- so every unordered pair is met once.
 // COARSE: the fast particles of split c-bins, on the configured c-bins n[]
 // (rows y + n_y z after the slow particles' c-bins).
+// One of the nine rows (k = 3 (dz + 1) + dy + 1) of that neighbourhood.
+template <bool HALF, bool COARSE = false, typename real, typename F>
+__device__ __forceinline__ void neighbourhood_row(const int32_t* start, const Inst<real>& I, int64_t base,
+                                                  const int n[3], const bool per[3], int cx, int cy, int cz,
+                                                  int32_t i, int k, F&& visit) {
+    const int64_t cell_off = COARSE ? I.cell_off + I.Cf : I.cell_off;
+    int y, z;
+    if (!axis_nb(cz, k / 3 - 1, n[2], per[2], z)) return;
+    if (!axis_nb(cy, k % 3 - 1, n[1], per[1], y)) return;
+    const int own_row = COARSE ? cy + n[1] * cz : row_of(I, cy, cz);
+    const int row_idx = COARSE ? y + n[1] * z : row_of(I, y, z);
+    if (HALF && row_idx < own_row) return;
+    const bool own = row_idx == own_row;
+    int xa[2], xb[2];
+    const int nxr = x_ranges(cx, n[0], per[0], xa, xb);
+    const int64_t row = cell_off + (int64_t)n[0] * row_idx;
+    for (int r = 0; r < nxr; ++r) {
+        int32_t j0 = (int32_t)(base + start[row + xa[r]]);
+        const int32_t j1 = (int32_t)(base + start[row + xb[r] + 1]);
+        if (HALF && own) {
+            if (r == 0) j0 = i + 1;           // range holding cx: after i
+            else if (xa[r] < cx) continue;    // wrapped bins below cx
+        }
+        visit(j0, j1);
+    }
+}
+
 template <bool HALF, bool COARSE = false, typename real, typename F>
 __device__ __forceinline__ void for_neighbourhood(const int32_t* start, const Inst<real>& I, int64_t base,
                                                   const int n[3], const bool per[3], int cx, int cy, int cz,
                                                   int32_t i, F&& visit) {
-    const int64_t cell_off = COARSE ? I.cell_off + I.Cf : I.cell_off;
-    int xa[2], xb[2];
-    const int nxr = x_ranges(cx, n[0], per[0], xa, xb);
-    const int own_row = COARSE ? cy + n[1] * cz : row_of(I, cy, cz);
-    for (int k = 0; k < 9; ++k) {
-        int y, z;
-        if (!axis_nb(cz, k / 3 - 1, n[2], per[2], z)) continue;
-        if (!axis_nb(cy, k % 3 - 1, n[1], per[1], y)) continue;
-        const int row_idx = COARSE ? y + n[1] * z : row_of(I, y, z);
-        if (HALF && row_idx < own_row) continue;
-        const bool own = row_idx == own_row;
-        const int64_t row = cell_off + (int64_t)n[0] * row_idx;
-        for (int r = 0; r < nxr; ++r) {
-            int32_t j0 = (int32_t)(base + start[row + xa[r]]);
-            const int32_t j1 = (int32_t)(base + start[row + xb[r] + 1]);
-            if (HALF && own) {
-                if (r == 0) j0 = i + 1;           // range holding cx: after i
-                else if (xa[r] < cx) continue;    // wrapped bins below cx
-            }
-            visit(j0, j1);
-        }
-    }
+    for (int k = 0; k < 9; ++k) neighbourhood_row<HALF, COARSE>(start, I, base, n, per, cx, cy, cz, i, k, visit);
 }
 
 // Closest-candidate search with register blocking: one lane owns up to G
@@ -960,139 +966,355 @@ __device__ __forceinline__ int floor_div(int64_t a, int64_t b) {  // b > 0
     return (int)(a >= 0 ? a / b : -((-a + b - 1) / b));
 }
 
-// Fine (refined) c-bins along one axis that can hold a particle whose
-// configured c-bin neighbours configured c-bin cc (cc - 1 .. cc + 1, wrapped
-// on a periodic axis), as at most two ranges [fa, fb]: the neighbours'
-// extent in fine c-bins, one fine c-bin wider on each side for the rounding
-// of either binning; the particle's configured c-bin is then checked
-// exactly.  On an axis that is not refined the two binnings are the same
-// and the ranges exact.
-__device__ __forceinline__ int fine_span(int cc, int nc, int nf, bool periodic, int fa[2], int fb[2]) {
-    if (periodic && nc <= 3) { fa[0] = 0; fb[0] = nf - 1; return 1; }
-    int c0 = cc - 1, c1 = cc + 1;
-    if (!periodic) { c0 = c0 < 0 ? 0 : c0; c1 = c1 > nc - 1 ? nc - 1 : c1; }
-    int lo = c0, hi = c1;
-    if (nf != nc) {
-        lo = floor_div((int64_t)c0 * nf, nc) - 1;
-        hi = floor_div((int64_t)(c1 + 1) * nf, nc) + 1;
+// Fine (refined) c-bins along one axis that a fast particle at coordinate x,
+// in configured c-bin cc, can meet a slow partner in: those that meet its
+// configured neighbours' extent (cc - 1 .. cc + 1, wrapped on a periodic
+// axis), cut to the fine c-bins within its reach (any pair meeting the
+// criteria starts at most D + (|v_i| + v_c) dt apart on every axis), both
+// widened by a rounding margin of the binnings (1e-3 + 1e-6 n_f fine
+// c-bins, above the few-ulp error of an FP32 bin coordinate).  At most two
+// ranges [fa, fb]; 0 when empty.  A record found there is kept only when
+// its configured c-bin is a neighbour (checked exactly by the caller).  On
+// an axis that is not refined the neighbours' extent is exact.
+template <typename real>
+__device__ __forceinline__ int fast_span(const Inst<real>& I, int ax, real x, double reach, int cc, bool periodic,
+                                         int fa[2], int fb[2]) {
+    const int nc = I.ncfg[ax], nf = I.n[ax];
+    const double eps = 1e-3 + 1e-6 * (double)nf;
+    const bool all = periodic && nc <= 3;  // every configured c-bin is a neighbour
+    int lo = 0, hi = nf - 1;
+    if (!all) {
+        int c0 = cc - 1, c1 = cc + 1;
+        if (!periodic) { c0 = c0 < 0 ? 0 : c0; c1 = c1 > nc - 1 ? nc - 1 : c1; }
+        lo = c0;
+        hi = c1;
+        if (nf != nc) {
+            const double r = (double)nf / (double)nc;
+            lo = (int)floor((double)c0 * r - eps);
+            hi = (int)floor((double)(c1 + 1) * r + eps);
+        }
     }
+    // The reach in fine c-bins (positions far outside the box keep the
+    // neighbours' extent; bins of positions outside are clamped, as here).
+    const double t = ((double)x - (double)I.lo[ax]) * (double)I.inv_w[ax];
+    const double d = reach * (double)I.inv_w[ax];
+    if (t > -0.5 * nf && t < 1.5 * nf) {
+        int bl = (int)floor(t - d - eps), bh = (int)floor(t + d + eps);
+        if (!periodic) {
+            bl = bl < 0 ? 0 : (bl > nf - 1 ? nf - 1 : bl);
+            bh = bh < 0 ? 0 : (bh > nf - 1 ? nf - 1 : bh);
+        }
+        if (all) { lo = bl; hi = bh; }
+        else { lo = lo > bl ? lo : bl; hi = hi < bh ? hi : bh; }
+    }
+    if (hi < lo) return 0;
     if (!periodic) {
         fa[0] = lo < 0 ? 0 : lo;
         fb[0] = hi > nf - 1 ? nf - 1 : hi;
-        return 1;
+        return fb[0] >= fa[0] ? 1 : 0;
     }
     if (hi - lo + 1 >= nf) { fa[0] = 0; fb[0] = nf - 1; return 1; }
-    if (lo < 0) { fa[0] = 0; fb[0] = hi; fa[1] = lo + nf; fb[1] = nf - 1; return 2; }
+    const int k = floor_div(lo, nf);  // shift by whole periods so that 0 <= lo < nf
+    lo -= k * nf;
+    hi -= k * nf;
     if (hi > nf - 1) { fa[0] = lo; fb[0] = nf - 1; fa[1] = 0; fb[1] = hi - nf; return 2; }
     fa[0] = lo; fb[0] = hi;
     return 1;
 }
 
-// The fast records [i_first, i_first + cnt) of a lane, one at a time.  Each
-// is tested against the slow particles of its configured neighbourhood (the
-// fine rows of fine_span, each record kept only when its configured c-bin
-// is a neighbour) and against the fast ones (configured c-bins; in FP32 the
-// half neighbourhood).  FP32 half scans of slow records never meet a fast
-// particle, so each unordered pair with a fast particle is tested once, here.
-// FP64 scans are ordered: the slow records' scans also take the fast
-// particles of their configured neighbourhood (search_group), these take all.
-// The pair test, the ranking key and the tie-breaks are those of
-// search_group, so the step's results are the unsplit grid's.
-template <typename real, bool HALF, bool MIX>
-__device__ void fast_records(const StepArgs<real>& a, const Inst<real>& I, int64_t base, int32_t i_first, int cnt,
-                             double& tests, double& cand, uint32_t& n_s0, uint32_t& n_c1) {
+// Largest number of fine c-bins fast_span gives on one axis for a reach of
+// at most `reach` (the task list's stride per fast record).
+template <typename real>
+__device__ __forceinline__ int fast_span_len(const Inst<real>& I, int ax, double reach, bool periodic) {
+    const int nc = I.ncfg[ax], nf = I.n[ax];
+    const double eps = 1e-3 + 1e-6 * (double)nf;
+    int len = (int)floor(2.0 * reach * (double)I.inv_w[ax] + 2.0 * eps) + 2;
+    if (!(periodic && nc <= 3)) {
+        const int nb = nf == nc ? 3 : (int)floor(3.0 * (double)nf / (double)nc + 2.0 * eps) + 2;
+        len = len < nb ? len : nb;
+    }
+    return len < nf ? len : nf;
+}
+
+// Index t of the concatenation of at most two ranges [a[r], b[r]].
+__device__ __forceinline__ int span_at(const int a[2], const int b[2], int len0, int t) {
+    return t < len0 ? a[0] + t : a[1] + (t - len0);
+}
+
+// The configured neighbours of configured c-bin cc along one axis as
+// (first, count - 1), wrapped on a periodic axis: bin c is a neighbour when
+// (c - first) mod n <= span.  check: whether a slow record the fast
+// particle at coordinate x can reach may lie outside them, so that its
+// configured c-bin has to be checked.  The neighbours extend at least one
+// configured c-bin beyond the particle's own; a record beyond the reach
+// cannot meet the criteria, and one within it lies inside the neighbours
+// unless the reach (widened by the rounding margin of the binnings) crosses
+// a side that has a configured c-bin beyond it.  On an axis that is not
+// refined the fine rows hold exactly the neighbours.
+template <typename real>
+__device__ __forceinline__ void coarse_nb(const Inst<real>& I, int ax, real x, double reach, int cc, bool periodic,
+                                          int& first, int& span, bool& check) {
+    const int nc = I.ncfg[ax];
+    check = false;
+    if (periodic && nc <= 3) { first = 0; span = nc - 1; return; }
+    if (periodic) { first = cc == 0 ? nc - 1 : cc - 1; span = 2; }
+    else {
+        first = cc > 0 ? cc - 1 : 0;
+        span = (cc < nc - 1 ? cc + 1 : nc - 1) - first;
+    }
+    if (I.n[ax] == nc) return;
+    const double eps = 1e-3 + 1e-6 * (double)nc;  // in configured c-bins
+    const double t = ((double)x - (double)I.lo[ax]) * (double)I.inv_wc[ax];
+    const double d = reach * (double)I.inv_wc[ax];
+    const bool below = periodic || cc >= 2, above = periodic || cc <= nc - 3;
+    check = (below && t - d < (double)(cc - 1) + eps) || (above && t + d > (double)(cc + 2) - eps);
+}
+
+// Whether a slow record at (x, y, z) lies in a configured c-bin neighbouring
+// the fast particle's, on the axes that need the check.
+template <typename real>
+__device__ __forceinline__ bool coarse_in(const Inst<real>& I, const bool chk[3], const int nc[3], const int first[3],
+                                          const int span[3], real x, real y, real z) {
+    const real p[3] = {x, y, z};
+    bool in = true;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        if (!chk[ax]) continue;
+        int u = axis_bin(p[ax], I.lo[ax], I.inv_wc[ax], nc[ax]) - first[ax];
+        u += u < 0 ? nc[ax] : 0;
+        in = in && u <= span[ax];
+    }
+    return in;
+}
+
+// Reach of a fast particle of speed^2 v2 towards slow partners, with the
+// margin of the c-bin refinement for the rounding of the pair test.
+template <typename real>
+__device__ __forceinline__ double fast_reach(const Inst<real>& I, double v2) {
+    return (sqrt((double)I.D2) + (sqrt(v2) + sqrt((double)I.vc2)) * (double)I.dt) * (1.0 + 1.0 / 64.0);
+}
+
+// Lexicographic minimum over the wave of (key, id) with a partner (j >= 0),
+// the tie-break of the ordered scans.
+template <typename real>
+__device__ __forceinline__ void wave_best(int32_t& bj, real& bd2, uint32_t& bid) {
+#pragma unroll
+    for (int m = 1; m < kWave; m <<= 1) {
+        const int32_t oj = __shfl_xor(bj, m);
+        const real od = __shfl_xor(bd2, m);
+        const uint32_t oi = __shfl_xor(bid, m);
+        if (oj >= 0 && (bj < 0 || od < bd2 || (od == bd2 && oi < bid))) { bj = oj; bd2 = od; bid = oi; }
+    }
+}
+
+// FP64: one fast record i of split c-bins, searched by a whole wave.  Every
+// particle of its configured neighbourhood is a possible partner, as on the
+// unsplit grid: the slow ones in the fine rows of fast_span (lanes take
+// rows; a record is kept only when its configured c-bin is a neighbour), the
+// fast ones on the configured c-bins (lanes take the nine rows).  The slow
+// records' ordered scans take the fast particles of their configured
+// neighbourhood (search_group).  The pair test, the ranking key and the
+// tie-breaks are search_group's.
+template <typename real, bool MIX>
+__device__ void fast_record(const StepArgs<real>& a, const Inst<real>& I, int64_t base, int32_t i, int lane,
+                            double& tests, double& cand, uint32_t& n_s0, uint32_t& n_c1) {
     const Geo<real> G_(I);
     const bool by_time = (I.flags & TPKMC_RANK_TIME) != 0;
     const int nf[3] = {I.n[0], I.n[1], I.n[2]};
     const int nc[3] = {I.ncfg[0], I.ncfg[1], I.ncfg[2]};
-    for (int q = 0; q < cnt; ++q) {
-        const int32_t i = i_first + q;
-        real xi, yi, zi, vxi, vyi, vzi;
-        uint32_t idi, fli;
-        Rec<real>::load(a.rec, i, xi, yi, zi, idi, vxi, vyi, vzi, fli);
-        const real pi[3] = {xi, yi, zi};
-        int cc[3], clo[3], cspan[3];
+    real xi, yi, zi, vxi, vyi, vzi;
+    uint32_t idi;
+    RecU<real>::load(a.rec, i, xi, yi, zi, idi, vxi, vyi, vzi);
+    const real pi[3] = {xi, yi, zi};
+    const double reach = fast_reach(I, speed2((double)vxi, (double)vyi, (double)vzi));
+    int cc[3], first[3], span[3];
+    bool chk[3];
 #pragma unroll
-        for (int ax = 0; ax < 3; ++ax) {
-            cc[ax] = axis_bin(pi[ax], I.lo[ax], I.inv_wc[ax], nc[ax]);
-            if (G_.per[ax] && nc[ax] <= 3) { clo[ax] = 0; cspan[ax] = nc[ax] - 1; }
-            else if (G_.per[ax]) { clo[ax] = cc[ax] == 0 ? nc[ax] - 1 : cc[ax] - 1; cspan[ax] = 2; }
-            else {
-                clo[ax] = cc[ax] > 0 ? cc[ax] - 1 : 0;
-                cspan[ax] = (cc[ax] < nc[ax] - 1 ? cc[ax] + 1 : nc[ax] - 1) - clo[ax];
-            }
+    for (int ax = 0; ax < 3; ++ax) {
+        cc[ax] = axis_bin(pi[ax], I.lo[ax], I.inv_wc[ax], nc[ax]);
+        coarse_nb(I, ax, pi[ax], reach, cc[ax], G_.per[ax], first[ax], span[ax], chk[ax]);
+    }
+    int32_t bj = -1;
+    real bd2 = real(0);
+    uint32_t bid = 0;
+    int32_t seen = 0, found = 0;
+    auto test = [&](int32_t j, bool check) {
+        real xj, yj, zj, vxj, vyj, vzj;
+        uint32_t idj, flj;
+        Rec<real>::load(a.rec, j, xj, yj, zj, idj, vxj, vyj, vzj, flj);
+        if (check && !coarse_in(I, chk, nc, first, span, xj, yj, zj)) return;
+        ++seen;
+        Screen<real> S;
+        const bool p1 = PairTest<real, -1>::stage1(G_, xi, yi, zi, vxi, vyi, vzi, xj, yj, zj, vxj, vyj, vzj, S);
+        if constexpr (MIX) {
+            n_s0 += S.s0 < real(0) ? 1u : 0u;
+            n_c1 += p1 ? 1u : 0u;
         }
-        unsigned long long mine = ~0ull;
-        int32_t bj = -1;
-        real bd2 = real(0);
-        uint32_t bid = 0;
-        int32_t seen = 0, found = 0;
-        auto test = [&](int32_t j, bool check) {
-            real xj, yj, zj, vxj, vyj, vzj;
-            uint32_t idj, flj;
-            Rec<real>::load(a.rec, j, xj, yj, zj, idj, vxj, vyj, vzj, flj);
-            if (check) {
-                const real pj[3] = {xj, yj, zj};
-                bool in = true;
-#pragma unroll
-                for (int ax = 0; ax < 3; ++ax) {
-                    if (nf[ax] == nc[ax]) continue;
-                    int t = axis_bin(pj[ax], I.lo[ax], I.inv_wc[ax], nc[ax]) - clo[ax];
-                    t += t < 0 ? nc[ax] : 0;
-                    in = in && t <= cspan[ax];
-                }
-                if (!in) return;
-            }
-            ++seen;
-            Screen<real> S;
-            const bool p1 = PairTest<real, -1>::stage1(G_, xi, yi, zi, vxi, vyi, vzi, xj, yj, zj, vxj, vyj, vzj, S);
-            if constexpr (MIX) {
-                n_s0 += S.s0 < real(0) ? 1u : 0u;
-                n_c1 += p1 ? 1u : 0u;
-            }
-            if (!p1 || !PairTest<real, -1>::stage2(G_, S)) return;
-            const real d2 = PairTest<real, -1>::finish(G_, S);
-            if (!(d2 >= real(0))) return;
-            ++found;
-            const real key = by_time ? PairTest<real, -1>::contact(G_, S) : d2;
-            if constexpr (HALF) {
-                const unsigned long long hi = (unsigned long long)sortable((float)key) << 32;
-                atomicMin(a.bkey + j, hi | (uint32_t)i);
-                const unsigned long long kk = hi | (uint32_t)j;
-                mine = kk < mine ? kk : mine;
-            } else {
-                if (bj < 0 || key < bd2 || (key == bd2 && idj < bid)) { bj = j; bd2 = key; bid = idj; }
-            }
-        };
-        int xa[2], xb[2], ya[2], yb[2], za[2], zb[2];
-        const int nxr = fine_span(cc[0], nc[0], nf[0], G_.per[0], xa, xb);
-        const int nyr = fine_span(cc[1], nc[1], nf[1], G_.per[1], ya, yb);
-        const int nzr = fine_span(cc[2], nc[2], nf[2], G_.per[2], za, zb);
-        for (int rz = 0; rz < nzr; ++rz)
-            for (int z = za[rz]; z <= zb[rz]; ++z)
-                for (int ry = 0; ry < nyr; ++ry)
-                    for (int y = ya[ry]; y <= yb[ry]; ++y) {
-                        const int64_t row = I.cell_off + (int64_t)nf[0] * row_of(I, y, z);
-                        for (int rx = 0; rx < nxr; ++rx) {
-                            const int32_t j0 = (int32_t)(base + a.start[row + xa[rx]]);
-                            const int32_t j1 = (int32_t)(base + a.start[row + xb[rx] + 1]);
-                            for (int32_t j = j0; j < j1; ++j) test(j, true);
-                        }
-                    }
-        for_neighbourhood<HALF, true>(a.start, I, base, nc, G_.per, cc[0], cc[1], cc[2], i,
-                                      [&](int32_t j0, int32_t j1) {
-            for (int32_t j = j0; j < j1; ++j) test(j, false);
-        });
-        if constexpr (HALF) {
-            if (mine != ~0ull) atomicMin(a.bkey + i, mine);
-            tests += (double)seen;
-            cand += 2.0 * (double)found;
-        } else {
-            a.best[i] = bj;
-            tests += 0.5 * (double)(seen - 1);  // the record met itself once
-            cand += (double)found;
+        if (!p1 || !PairTest<real, -1>::stage2(G_, S)) return;
+        const real d2 = PairTest<real, -1>::finish(G_, S);
+        if (!(d2 >= real(0))) return;
+        ++found;
+        const real key = by_time ? PairTest<real, -1>::contact(G_, S) : d2;
+        if (bj < 0 || key < bd2 || (key == bd2 && idj < bid)) { bj = j; bd2 = key; bid = idj; }
+    };
+    int xa[2], xb[2], ya[2], yb[2], za[2], zb[2];
+    const int nxr = fast_span(I, 0, xi, reach, cc[0], G_.per[0], xa, xb);
+    const int nyr = fast_span(I, 1, yi, reach, cc[1], G_.per[1], ya, yb);
+    const int nzr = fast_span(I, 2, zi, reach, cc[2], G_.per[2], za, zb);
+    const int ly0 = nyr ? yb[0] - ya[0] + 1 : 0, lz0 = nzr ? zb[0] - za[0] + 1 : 0;
+    const int ny = ly0 + (nyr > 1 ? yb[1] - ya[1] + 1 : 0);
+    const int nz = lz0 + (nzr > 1 ? zb[1] - za[1] + 1 : 0);
+    for (int t = lane; t < ny * nz; t += kWave) {
+        const int y = span_at(ya, yb, ly0, t % ny), z = span_at(za, zb, lz0, t / ny);
+        const int64_t row = I.cell_off + (int64_t)nf[0] * row_of(I, y, z);
+        for (int rx = 0; rx < nxr; ++rx) {
+            const int32_t j0 = (int32_t)(base + a.start[row + xa[rx]]);
+            const int32_t j1 = (int32_t)(base + a.start[row + xb[rx] + 1]);
+            for (int32_t j = j0; j < j1; ++j) test(j, true);
         }
     }
+    if (lane < 9)
+        neighbourhood_row<false, true>(a.start, I, base, nc, G_.per, cc[0], cc[1], cc[2], i, lane,
+                                       [&](int32_t j0, int32_t j1) {
+            for (int32_t j = j0; j < j1; ++j) test(j, false);
+        });
+    double sn = (double)seen, fn = (double)found;
+#pragma unroll
+    for (int m = 1; m < kWave; m <<= 1) {
+        sn += __shfl_xor(sn, m);
+        fn += __shfl_xor(fn, m);
+    }
+    wave_best(bj, bd2, bid);
+    if (lane == 0) a.best[i] = bj;
+    tests += 0.5 * (sn - 1.0);  // the record met itself once
+    cand += fn;
+}
+
+// FP32: the fast records' searches as a flat list of tasks, one per lane:
+// (fast record, row) for the fine rows of fast_span (index t < ny * nz) and
+// for the nine rows of configured c-bins of the fast particles (half
+// neighbourhood), so lanes stay busy however few rows a record has or
+// however many fast records there are.  A slow row longer than kLongRow
+// records (dense bins) is walked by the whole wave, lanes striding over its
+// records.  Every candidate lowers both keys with atomicMin, so the tasks of
+// one record may run in any lanes and any order.
+constexpr int kLongRow = 64;
+
+template <bool MIX>
+__device__ void fast_tasks(const StepArgs<float>& a, const Inst<float>& I, int64_t base, int64_t f0, int64_t ntask,
+                           int per_rec, int rmax, int64_t q, int lane, double& seen, double& cand, uint32_t& n_s0,
+                           uint32_t& n_c1) {
+    const Geo<float> G_(I);
+    const bool by_time = (I.flags & TPKMC_RANK_TIME) != 0;
+    const int nf[3] = {I.n[0], I.n[1], I.n[2]};
+    const int nc[3] = {I.ncfg[0], I.ncfg[1], I.ncfg[2]};
+    const bool valid = q < ntask;
+    int32_t i = 0;
+    int t = 0;
+    float xi = 0.f, yi = 0.f, zi = 0.f, vxi = 0.f, vyi = 0.f, vzi = 0.f;
+    int cc[3] = {0, 0, 0}, first[3] = {0, 0, 0}, span[3] = {0, 0, 0};
+    bool chk[3] = {false, false, false};
+    int32_t ja[2] = {0, 0}, jb[2] = {0, 0};
+    bool slow = false;
+    if (valid) {
+        i = (int32_t)(f0 + q / per_rec);
+        t = (int)(q % per_rec);
+        Rec<float>::load6(a.rec, (uint32_t)i, xi, yi, zi, vxi, vyi, vzi);
+        const float pi[3] = {xi, yi, zi};
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) cc[ax] = axis_bin(pi[ax], I.lo[ax], I.inv_wc[ax], nc[ax]);
+        if (t < rmax) {
+            const double reach = fast_reach(I, speed2((double)vxi, (double)vyi, (double)vzi));
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax)
+                coarse_nb(I, ax, pi[ax], reach, cc[ax], G_.per[ax], first[ax], span[ax], chk[ax]);
+            int ya[2], yb[2], za[2], zb[2];
+            const int nyr = fast_span(I, 1, yi, reach, cc[1], G_.per[1], ya, yb);
+            const int nzr = fast_span(I, 2, zi, reach, cc[2], G_.per[2], za, zb);
+            const int ly0 = nyr ? yb[0] - ya[0] + 1 : 0, lz0 = nzr ? zb[0] - za[0] + 1 : 0;
+            const int ny = ly0 + (nyr > 1 ? yb[1] - ya[1] + 1 : 0);
+            const int nz = lz0 + (nzr > 1 ? zb[1] - za[1] + 1 : 0);
+            if (t < ny * nz) {
+                int xa[2], xb[2];
+                const int nxr = fast_span(I, 0, xi, reach, cc[0], G_.per[0], xa, xb);
+                const int y = span_at(ya, yb, ly0, t % ny), z = span_at(za, zb, lz0, t / ny);
+                const int64_t row = I.cell_off + (int64_t)nf[0] * row_of(I, y, z);
+                for (int rx = 0; rx < nxr; ++rx) {
+                    ja[rx] = (int32_t)(base + a.start[row + xa[rx]]);
+                    jb[rx] = (int32_t)(base + a.start[row + xb[rx] + 1]);
+                }
+                slow = true;
+            }
+        }
+    }
+    // Tests slow or fast record j against fast record ii (the lane's own or,
+    // for long rows, the owner lane's, whose values are passed in).
+    auto test = [&](int32_t ii, float x0, float y0, float z0, float u0, float u1, float u2, int32_t j,
+                    unsigned long long& mine) {
+        float xj, yj, zj, vxj, vyj, vzj;
+        Rec<float>::load6(a.rec, (uint32_t)j, xj, yj, zj, vxj, vyj, vzj);
+        seen += 1.0;
+        Screen<float> S;
+        const bool p1 = PairTest<float, -1>::stage1(G_, x0, y0, z0, u0, u1, u2, xj, yj, zj, vxj, vyj, vzj, S);
+        if constexpr (MIX) {
+            n_s0 += S.s0 < 0.0f ? 1u : 0u;
+            n_c1 += p1 ? 1u : 0u;
+        }
+        if (!p1 || !PairTest<float, -1>::stage2(G_, S)) return;
+        const float d2 = PairTest<float, -1>::finish(G_, S);
+        if (!(d2 >= 0.0f)) return;
+        cand += 2.0;  // both orders, as search_group counts
+        const float key = by_time ? PairTest<float, -1>::contact(G_, S) : d2;
+        const unsigned long long hi = (unsigned long long)sortable(key) << 32;
+        atomicMin(a.bkey + j, hi | (uint32_t)ii);
+        const unsigned long long kk = hi | (uint32_t)j;
+        mine = kk < mine ? kk : mine;
+    };
+    const int len = slow ? (jb[0] - ja[0]) + (jb[1] - ja[1]) : 0;
+    // Long slow rows: the whole wave, one owner lane at a time.
+    uint64_t longm = __ballot(len > kLongRow);
+    while (longm) {
+        const int o = __ffsll((long long)longm) - 1;
+        longm &= longm - 1;
+        const int32_t io = __builtin_amdgcn_readlane(i, o);
+        const float xo = __shfl(xi, o), yo = __shfl(yi, o), zo = __shfl(zi, o);
+        const float uo0 = __shfl(vxi, o), uo1 = __shfl(vyi, o), uo2 = __shfl(vzi, o);
+        int fo[3], so[3];
+        bool co[3];
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            fo[ax] = __builtin_amdgcn_readlane(first[ax], o);
+            so[ax] = __builtin_amdgcn_readlane(span[ax], o);
+            co[ax] = __builtin_amdgcn_readlane((int)chk[ax], o) != 0;
+        }
+        unsigned long long mo = ~0ull;
+#pragma unroll
+        for (int rx = 0; rx < 2; ++rx) {
+            const int32_t a0 = __builtin_amdgcn_readlane(ja[rx], o), b0 = __builtin_amdgcn_readlane(jb[rx], o);
+            for (int32_t j = a0 + lane; j < b0; j += kWave) {
+                float xj, yj, zj, vxj, vyj, vzj;
+                Rec<float>::load6(a.rec, (uint32_t)j, xj, yj, zj, vxj, vyj, vzj);
+                if (coarse_in(I, co, nc, fo, so, xj, yj, zj)) test(io, xo, yo, zo, uo0, uo1, uo2, j, mo);
+            }
+        }
+        if (mo != ~0ull) atomicMin(a.bkey + io, mo);
+    }
+    unsigned long long mine = ~0ull;
+    if (slow && len <= kLongRow) {
+#pragma unroll
+        for (int rx = 0; rx < 2; ++rx)
+            for (int32_t j = ja[rx]; j < jb[rx]; ++j) {
+                float xj, yj, zj, vxj, vyj, vzj;
+                Rec<float>::load6(a.rec, (uint32_t)j, xj, yj, zj, vxj, vyj, vzj);
+                if (coarse_in(I, chk, nc, first, span, xj, yj, zj)) test(i, xi, yi, zi, vxi, vyi, vzi, j, mine);
+            }
+    } else if (valid && t >= rmax) {
+        neighbourhood_row<true, true>(a.start, I, base, nc, G_.per, cc[0], cc[1], cc[2], i, t - rmax,
+                                      [&](int32_t j0, int32_t j1) {
+            for (int32_t j = j0; j < j1; ++j) test(i, xi, yi, zi, vxi, vyi, vzi, j, mine);
+        });
+    }
+    if (mine != ~0ull) atomicMin(a.bkey + i, mine);
 }
 
 // search_group for the instance's periodic axes: FP32 has builds for the
@@ -1222,11 +1444,14 @@ k_search(StepArgs<real> a) {
 // The fast records of split c-bins, in a launch of their own after k_search
 // (FP32 keys combine with atomicMin in any order; in FP64 each fast record
 // writes its own partner), so that the slow records' search keeps its
-// register budget.  Threads stride over each instance's fast records; the
-// search's work counters go to the block-table entry holding the record.
+// register budget.  FP32 strides over the task list of fast_tasks; FP64 runs
+// one fast record per wave (fast_record).  The search's work counters are
+// summed per work-group and instance, and added to the instance's first
+// block-table entry.
 template <typename real, bool HALF, bool MIX = false>
 __global__ void __launch_bounds__(256) k_search_fast(StepArgs<real> a, int n_inst) {
     __shared__ double lds[16];
+    const int lane = threadIdx.x & (kWave - 1);
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t nth = (int64_t)gridDim.x * blockDim.x;
     double mt = 0.0;
@@ -1238,15 +1463,37 @@ __global__ void __launch_bounds__(256) k_search_fast(StepArgs<real> a, int n_ins
         const int64_t f0 = base + a.start[I.cell_off + I.Cf];
         const int64_t live_end = base + a.start[I.cell_off + I.C];
         const int64_t f1 = live_end < I.off + I.cnt ? live_end : I.off + I.cnt;
-        for (int64_t r = f0 + tid; r < f1; r += nth) {
-            double t = 0.0, c = 0.0;
-            fast_records<real, HALF, MIX>(a, I, base, (int32_t)r, 1, t, c, n_s0, n_c1);
-            if constexpr (MIX) {
-                mt += t;
-            } else {
-                double* gp = a.gpart + (int64_t)(I.blk0 + (r - I.off) / kBlock) * kGPart;
-                if (t > 0.0) unsafeAtomicAdd(gp + GP_TESTS2, 2.0 * t);
-                if (c > 0.0) unsafeAtomicAdd(gp + GP_CAND, c);
+        double t = 0.0, c = 0.0;
+        if constexpr (HALF) {
+            // Rows per fast record: the fine rows within the largest reach
+            // of this step's fastest particle, then the nine coarse rows.
+            const double reach = fast_reach(I, I.vmax2_d);
+            const bool per1 = I.bc[1] == TPKMC_BC_PERIODIC, per2 = I.bc[2] == TPKMC_BC_PERIODIC;
+            const int rmax = fast_span_len(I, 1, reach, per1) * fast_span_len(I, 2, reach, per2);
+            const int per_rec = rmax + 9;
+            const int64_t ntask = (f1 - f0) * per_rec;
+            for (int64_t q0 = tid - lane; q0 < ntask; q0 += nth)  // wave-uniform
+                fast_tasks<MIX>(a, I, base, f0, ntask, per_rec, rmax, q0 + lane, lane, t, c, n_s0, n_c1);
+        } else {
+            const int64_t wave = tid / kWave, nwaves = nth / kWave;
+            for (int64_t r = f0 + wave; r < f1; r += nwaves) {
+                double tr = 0.0, cr = 0.0;
+                const int32_t ri = __builtin_amdgcn_readfirstlane((int32_t)r);  // wave-uniform
+                fast_record<real, MIX>(a, I, base, ri, lane, tr, cr, n_s0, n_c1);
+                t += lane == 0 ? tr : 0.0;
+                c += lane == 0 ? cr : 0.0;
+            }
+        }
+        if constexpr (MIX) {
+            mt += t;
+        } else {
+            // Uniform over the work-group (the instance loop is), so every
+            // thread takes part in the sums.
+            const double ts = block_sum(t, lds), cs = block_sum(c, lds);
+            if (threadIdx.x == 0) {
+                double* gp = a.gpart + (int64_t)I.blk0 * kGPart;
+                if (ts > 0.0) unsafeAtomicAdd(gp + GP_TESTS2, 2.0 * ts);
+                if (cs > 0.0) unsafeAtomicAdd(gp + GP_CAND, cs);
             }
         }
     }
@@ -1471,7 +1718,7 @@ __device__ __forceinline__ void global_acc_add(ObAcc& G, int k, long long v) {
 // accumulators once per work-group: exponent maxima in the move, value sums
 // in the moment pass.
 constexpr int kSlots = 64;       // exponent table (the move's 256 records)
-constexpr int kMomSlots = 64;    // value table (the moment pass's 256 records)
+constexpr int kMomSlots = 256;   // value table (the moment pass's kMomEntries * 256 records)
 constexpr int kTabWords = kAccVals + 2;  // values, particle count, collider count
 struct MomentTable {
     static constexpr int kN = kMomSlots;
@@ -1865,76 +2112,88 @@ __device__ __forceinline__ void value_flush(MomentTable& tab, const StepArgs<rea
     }
 }
 
+// Block-table entries (kBlock records each) per work-group of the moment
+// pass.  The global sums take one set of atomics per (work-group, o-bin); a
+// work-group of one entry meets each o-bin along a fraction of one row of
+// c-bins, one of eight entries along several neighbouring rows, whose
+// records of one o-bin it sums first (16M Sedov blast on 189^3 c-bins and
+// 64^3 o-bins: 39 o-bins per 256 records against 17 on 128^3 c-bins).
+constexpr int kMomEntries = 8;
+
 template <typename real>
 __global__ void __launch_bounds__(kBlock) k_moments(StepArgs<real> a) {
     __shared__ MomentTable tab;
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
-    const Blk bt = a.blk[lb];
-    const Inst<real>& I = a.inst[bt.inst];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int64_t end = I.off + I.cnt;
-    const bool reorder = (I.flags & TPKMC_ALLOW_REORDER) != 0;
-    const bool has_mass = (I.flags & kHasMass) != 0;
     for (int t = tid; t < kMomSlots; t += kBlock) tab.key[t] = -1;
     for (int t = tid; t < kMomSlots * kTabWords; t += kBlock) (&tab.val[0][0])[t] = 0;
     __syncthreads();
-    const int64_t i = (int64_t)bt.first + tid;
-    int ob = -1;
-    long long q[kAccVals];
+    for (int e = 0; e < kMomEntries; ++e) {
+        const int entry = lb * kMomEntries + e;
+        if (entry >= a.nblk) break;  // uniform
+        const Blk bt = a.blk[entry];
+        const Inst<real>& I = a.inst[bt.inst];
+        const int64_t end = I.off + I.cnt;
+        const bool reorder = (I.flags & TPKMC_ALLOW_REORDER) != 0;
+        const bool has_mass = (I.flags & kHasMass) != 0;
+        const int64_t i = (int64_t)bt.first + tid;
+        int ob = -1;
+        long long q[kAccVals];
 #pragma unroll
-    for (int k = 0; k < kAccVals; ++k) q[k] = 0;
-    uint32_t cnt = 0, coll = 0;
-    if (i < end) {
-        // The same particles as the move's moment terms: alive after the
-        // step (not absorbed), finite, with a valid mass.
-        const int64_t p = reorder ? i : (int64_t)a.src[i];
-        const bool alive = a.alive ? a.alive[p] != 0 : true;
-        const real x = a.x[p], y = a.y[p], z = a.z[p], vx = a.vx[p], vy = a.vy[p], vz = a.vz[p];
-        const real mi = has_mass ? a.mass[p] : I.mass;
-        const bool fin = finite3(x, y, z) && finite3(vx, vy, vz) &&
-                         (!has_mass || (mi > real(0) && mi < real(INFINITY)));
-        if (alive && fin) {
-            ob = obin_of(I, x, y, z);
-            const bool c = a.coll[p] != 0;
-            double vir[3] = {0.0, 0.0, 0.0};
-            if (c) {
-                vir[0] = (double)a.vir[3 * p];
-                vir[1] = (double)a.vir[3 * p + 1];
-                vir[2] = (double)a.vir[3 * p + 2];
-            }
-            const double m = has_mass ? (double)mi : I.mass_d;
-            const double* S = a.shift + (int64_t)ob * 3;
-            double t[kAccVals];
-            moment_terms(m, (double)vx, (double)vy, (double)vz, S, vir[0], vir[1], vir[2], t);
-            const ObAcc& G = a.macc[ob];
-            const double s0 = fixed_scale(G.e[0]), s1 = fixed_scale(G.e[1]);
+        for (int k = 0; k < kAccVals; ++k) q[k] = 0;
+        uint32_t cnt = 0, coll = 0;
+        if (i < end) {
+            // The same particles as the move's moment terms: alive after the
+            // step (not absorbed), finite, with a valid mass.
+            const int64_t p = reorder ? i : (int64_t)a.src[i];
+            const bool alive = a.alive ? a.alive[p] != 0 : true;
+            const real x = a.x[p], y = a.y[p], z = a.z[p], vx = a.vx[p], vy = a.vy[p], vz = a.vz[p];
+            const real mi = has_mass ? a.mass[p] : I.mass;
+            const bool fin = finite3(x, y, z) && finite3(vx, vy, vz) &&
+                             (!has_mass || (mi > real(0) && mi < real(INFINITY)));
+            if (alive && fin) {
+                ob = obin_of(I, x, y, z);
+                const bool c = a.coll[p] != 0;
+                double vir[3] = {0.0, 0.0, 0.0};
+                if (c) {
+                    vir[0] = (double)a.vir[3 * p];
+                    vir[1] = (double)a.vir[3 * p + 1];
+                    vir[2] = (double)a.vir[3 * p + 2];
+                }
+                const double m = has_mass ? (double)mi : I.mass_d;
+                const double* S = a.shift + (int64_t)ob * 3;
+                double t[kAccVals];
+                moment_terms(m, (double)vx, (double)vy, (double)vz, S, vir[0], vir[1], vir[2], t);
+                const ObAcc& G = a.macc[ob];
+                const double s0 = fixed_scale(G.e[0]), s1 = fixed_scale(G.e[1]);
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                q[k] = to_fixed(t[k], s0);
-                q[3 + k] = to_fixed(t[3 + k], s1);
-            }
-            if (c) {
-                const double s2 = fixed_scale(G.e[2]);
+                for (int k = 0; k < 3; ++k) {
+                    q[k] = to_fixed(t[k], s0);
+                    q[3 + k] = to_fixed(t[3 + k], s1);
+                }
+                if (c) {
+                    const double s2 = fixed_scale(G.e[2]);
 #pragma unroll
-                for (int k = 6; k < 9; ++k) q[k] = to_fixed(t[k], s2);
+                    for (int k = 6; k < 9; ++k) q[k] = to_fixed(t[k], s2);
+                }
+                if (has_mass) q[9] = to_fixed(t[9], fixed_scale(G.e[3]));
+                cnt = 1;
+                coll = c ? 1 : 0;
             }
-            if (has_mass) q[9] = to_fixed(t[9], fixed_scale(G.e[3]));
-            cnt = 1;
-            coll = c ? 1 : 0;
         }
-    }
-    bool head;
-    const int lim = row_lim(ob, lane, head);
-    const bool anyc = __ballot(coll != 0) != 0;
+        bool head;
+        const int lim = row_lim(ob, lane, head);
+        const bool anyc = __ballot(coll != 0) != 0;
 #pragma unroll
-    for (int k = 0; k < kAccVals; ++k) {
-        if ((k >= 6 && k <= 8 && !anyc) || (k == 9 && !has_mass)) continue;  // wave-uniform
-        q[k] = row_sum64(q[k], lim);
+        for (int k = 0; k < kAccVals; ++k) {
+            if ((k >= 6 && k <= 8 && !anyc) || (k == 9 && !has_mass)) continue;  // wave-uniform
+            q[k] = row_sum64(q[k], lim);
+        }
+        cnt = row_sum32(cnt, lim);
+        if (anyc) coll = row_sum32(coll, lim);
+        if ((head || (lane & 15) == 0) && ob >= 0) value_flush(tab, a, ob, q, cnt, coll);
     }
-    cnt = row_sum32(cnt, lim);
-    if (anyc) coll = row_sum32(coll, lim);
-    if ((head || (lane & 15) == 0) && ob >= 0) value_flush(tab, a, ob, q, cnt, coll);
     __syncthreads();
     // The table to the global sums: one thread per (slot, table word).
     for (int t = tid; t < kMomSlots * kTabWords; t += kBlock) {
@@ -1949,7 +2208,8 @@ __global__ void __launch_bounds__(kBlock) k_moments(StepArgs<real> a) {
 }
 
 // Per instance, from the work-group maxima of |v|^2 left by the key kernel:
-// the step's largest speed; with ADAPTIVE_DT the time step of Sec. 3,
+// the step's largest speed (with split c-bins it bounds the fast particles'
+// reach in the search); with ADAPTIVE_DT the time step of Sec. 3,
 // dt = dx / v_max (dx of the configured c-bins), the caller's dt being the
 // cap.  gridDim.x work-groups per instance fold the maxima into a running
 // maximum (a single work-group would wait on its loads one after another);
@@ -1959,7 +2219,7 @@ __global__ void __launch_bounds__(256) k_prep(Inst<real>* inst, const double* gp
     __shared__ double lds[16];
     __shared__ bool last;
     Inst<real>& I = inst[blockIdx.y];
-    if (!(I.flags & TPKMC_ADAPTIVE_DT)) return;  // whole work-group
+    if (!(I.flags & (TPKMC_ADAPTIVE_DT | kSplit))) return;  // whole work-group
     double v = 0.0;
     const double* g0 = gpart + (int64_t)I.blk0 * kGPart;
     for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < I.nblk; b += gridDim.x * blockDim.x)
@@ -1988,28 +2248,32 @@ __global__ void __launch_bounds__(256) k_prep(Inst<real>* inst, const double* gp
     }
 }
 
-// Tuning statistics of the speeds: per work-group, the sum of |v|^2 and the
-// count of live particles with a finite state, in the slots GP_PX and GP_PY
-// (free until the move writes them).
+// Tuning statistics of the speeds: per work-group, over the live particles
+// with a finite state, the sum of |v|^2, their count, and the sum of |v|^2
+// over those with |v|^2 above the instance's vc2 (0 when vc2 is 0), in the
+// slots GP_PX, GP_PY and GP_PZ (free until the move writes them).
 template <typename real>
 __global__ void __launch_bounds__(kBlock) k_speed_stats(StepArgs<real> a) {
     __shared__ double lds[16];
     const Blk bt = a.blk[blockIdx.x];
     const Inst<real>& I = a.inst[bt.inst];
     const int64_t p = (int64_t)bt.first + threadIdx.x;
-    double v2 = 0.0, n = 0.0;
+    double v2 = 0.0, n = 0.0, hot = 0.0;
     if (p < I.off + I.cnt && (a.alive == nullptr || a.alive[p] != 0)) {
         const double vx = (double)a.vx[p], vy = (double)a.vy[p], vz = (double)a.vz[p];
         if (finite3((double)a.x[p], (double)a.y[p], (double)a.z[p]) && finite3(vx, vy, vz)) {
             v2 = speed2(vx, vy, vz);
             n = 1.0;
+            hot = I.vc2 > real(0) && v2 > (double)I.vc2 ? v2 : 0.0;
         }
     }
     v2 = block_sum(v2, lds);
     n = block_sum(n, lds);
+    hot = block_sum(hot, lds);
     if (threadIdx.x == 0) {
         a.gpart[(int64_t)blockIdx.x * kGPart + GP_PX] = v2;
         a.gpart[(int64_t)blockIdx.x * kGPart + GP_PY] = n;
+        a.gpart[(int64_t)blockIdx.x * kGPart + GP_PZ] = hot;
     }
 }
 
@@ -2071,7 +2335,8 @@ void launch_move(const StepArgs<real>& a, hipStream_t s) {
 }
 template <typename real>
 void launch_moments(const StepArgs<real>& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_moments<real>, dim3(a.nblk), dim3(kBlock), 0, s, a);
+    const unsigned grid = (unsigned)((a.nblk + kMomEntries - 1) / kMomEntries);
+    hipLaunchKernelGGL(k_moments<real>, dim3(grid), dim3(kBlock), 0, s, a);
 }
 
 }  // namespace tpkmc

@@ -11,7 +11,8 @@ neighbourhood; nothing but the search's work changes, at any speeds.
    axes including one of three configured c-bins, absorbing walls, the
    plane, contact-time ranking); a tube whose speeds are raised after tuning.
  - Random partners (their draw depends on the c-bin) keep the configured
-   c-bins; a planar grid keeps one c-bin on z.
+   c-bins; a planar grid keeps one c-bin on z; a point blast, whose fast
+   particles hold most of the energy, keeps the configured c-bins.
  - FP32: the tuned handle's pairs equal an untuned handle's, also through a
    captured graph, with fast particles, and inside a batch."""
 import numpy as np
@@ -93,7 +94,7 @@ def test_random_partners_and_plane_keep_their_cells(T):
     eng.close()
 
 
-def fast_box(n, seed, ncell, bc, planar=False, rank_time=False, fast_frac=0.01, fast_speed=20.0):
+def fast_box(n, seed, ncell, bc, planar=False, rank_time=False, fast_frac=0.002, fast_speed=10.0):
     """A Gaussian gas (unit speed per component) with a fraction of fast
     particles at fast_speed, isotropic; D is a quarter of the smallest
     configured c-bin and the gas moves 2% of it per step, so the slow
@@ -169,7 +170,26 @@ def test_fp64_split_with_fast_particles_equals_oracle(T, oracle, case):
     print(case, "configured", w.grid["ncell"], "tuned", cells, "speed bound", vc, "fast", n_fast, flush=True)
     refined = [a for a in range(3) if cells[a] > w.grid["ncell"][a]]
     assert len(refined) >= 2 and vc > 0.0
-    assert n_fast > 100
+    assert n_fast > 60
+
+
+def test_blast_keeps_the_configured_cells(T):
+    """A point blast: its few fast particles hold nearly all the kinetic
+    energy, which collisions will spread over many more particles above the
+    speed bound, so the autotuner keeps the configured c-bins (a thermal gas
+    of the same size is split)."""
+    w = W.sedov(n=30_000, seed=3, kn=1e-2, ncell=8, nobin=4)
+    eng = engine(T, w, T.FP32)
+    dst = T.to_device(w.state, T.FP32)
+    eng.autotune(dst, [(0, w.n, w.grid, w.params)])
+    assert eng.tuned_cells(0) == tuple(w.grid["ncell"]) and eng.tuned_speed(0) == 0.0
+    eng.close()
+    g = fast_box(n=30_000, seed=4, ncell=(8, 8, 8), bc=(R, R, R), fast_frac=0.0)
+    eng = engine(T, g, T.FP32)
+    dst = T.to_device(g.state, T.FP32)
+    eng.autotune(dst, [(0, g.n, g.grid, g.params)])
+    assert np.prod(eng.tuned_cells(0)) > np.prod(g.grid["ncell"]) and eng.tuned_speed(0) > 0.0
+    eng.close()
 
 
 def test_fp64_speeds_raised_after_tuning_equal_oracle(T, oracle):
