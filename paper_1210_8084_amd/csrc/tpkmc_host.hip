@@ -844,24 +844,26 @@ int grow_cells(tpkmc_handle* h, int64_t need) {
 // fast particles keep the configured c-bins and neighbourhood (the search's
 // fast particle pass), so the step's results are the configured grid's
 // whatever the speeds do later; only the search's work changes.  The bound
-// is v_c = 3 v_rms over the instance's live particles: a Maxwellian gas has
-// about 6e-6 of its particles above it, and an isolated gas keeps its
-// root-mean-square speed as it thermalises (its energy is conserved), while
-// its largest speed grows with the tail of the distribution.  The split is
-// used only when the particles above v_c hold less than a tenth of the
-// kinetic energy: where they hold most of it (a point blast), collisions
-// share it out and lift many more particles above the bound later in the
-// run, whose searches then cost more than the refinement saves.  Per
-// instance (not with random partners, whose draw depends on the c-bin) and
-// per axis, the slow particles' c-bins are the largest count whose width
-// keeps a factor 1 + 1/64 over that reach (the rounding of the binning and
-// of the pair test), used when it is at least 1.25 times the configured
-// count (3 or more on periodic axes, never on a planar z), with at most one
-// c-bin per two particles.
-constexpr double kSpeedBound = 3.0;
+// is v_c = 2 v_rms over the instance's live particles, set for the gas as it
+// will be once thermalised: an isolated gas keeps its root-mean-square speed
+// (its energy is conserved) while its largest speed grows with the tail of
+// the distribution, and a Maxwellian has 0.7% of its particles above 2 v_rms
+// in three dimensions (1.8% in two), few enough that the finer c-bins of
+// the rest more than pay for their searches.  The split is used only when
+// the particles above v_c hold less than half of the kinetic energy (a
+// Maxwellian: 3.5% in three dimensions, 9% in two, 26% in one): where they
+// hold most of it (a point blast), collisions share it out and lift many
+// more particles above the bound later in the run, whose searches then cost
+// more than the refinement saves.  Per instance (not with random partners,
+// whose draw depends on the c-bin) and per axis, the slow particles' c-bins
+// are the largest count whose width keeps a factor 1 + 1/64 over that reach
+// (the rounding of the binning and of the pair test), used when it is at
+// least 1.25 times the configured count (3 or more on periodic axes, never
+// on a planar z), with at most one c-bin per two particles.
+constexpr double kSpeedBound = 2.0;
 constexpr double kReachMargin = 1.0 + 1.0 / 64.0;
 constexpr double kMinRefine = 1.25;
-constexpr double kHotEnergy = 0.1;
+constexpr double kHotEnergy = 0.5;
 template <typename real>
 int choose_cells(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance* in, int n_inst, hipStream_t st) {
     h->cells.clear();

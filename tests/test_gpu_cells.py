@@ -94,7 +94,7 @@ def test_random_partners_and_plane_keep_their_cells(T):
     eng.close()
 
 
-def fast_box(n, seed, ncell, bc, planar=False, rank_time=False, fast_frac=0.002, fast_speed=10.0):
+def fast_box(n, seed, ncell, bc, planar=False, rank_time=False, fast_frac=0.001, fast_speed=10.0):
     """A Gaussian gas (unit speed per component) with a fraction of fast
     particles at fast_speed, isotropic; D is a quarter of the smallest
     configured c-bin and the gas moves 2% of it per step, so the slow
@@ -175,9 +175,9 @@ def test_fp64_split_with_fast_particles_equals_oracle(T, oracle, case):
 
 def test_blast_keeps_the_configured_cells(T):
     """A point blast: its few fast particles hold nearly all the kinetic
-    energy, which collisions will spread over many more particles above the
-    speed bound, so the autotuner keeps the configured c-bins (a thermal gas
-    of the same size is split)."""
+    energy (more than half of it above the speed bound), which collisions
+    will spread over many more particles above the bound, so the autotuner
+    keeps the configured c-bins; a thermal gas of the same size is split."""
     w = W.sedov(n=30_000, seed=3, kn=1e-2, ncell=8, nobin=4)
     eng = engine(T, w, T.FP32)
     dst = T.to_device(w.state, T.FP32)

@@ -285,7 +285,11 @@ def test_graph_run_equals_plain_steps(T, oracle):
     torch.cuda.synchronize()
     h1, h2 = T.to_host(d1), T.to_host(d2)
     assert_state_equal(h1, h2)
-    assert o1.host()["counters"].tolist() == o2.host()["counters"].tolist()
+    # The first run tunes the handle, whose c-bins may be split by speed:
+    # every counter but the search's work counters is the plain steps'.
+    c1, c2 = o1.host()["counters"], o2.host()["counters"]
+    keep = [k for name, k in T.CNT.items() if name not in ("tests", "cand")]
+    assert c1[:, keep].tolist() == c2[:, keep].tolist()
     for k, w in enumerate(ws):
         ref_state = W.copy_state(w.state)
         ref_state["id"] = st["id"][specs[k][0]:specs[k][0] + w.n].copy()
