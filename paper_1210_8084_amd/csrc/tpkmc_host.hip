@@ -1185,7 +1185,17 @@ int step_noalloc_impl(int device, const tpkmc_grid* g, const tpkmc_params* p, co
     hipLaunchKernelGGL(k_setup_one<real>, dim3(sgrid), dim3(256), 0, st, d, (Inst<real>*)Bf.inst, Bf.blk, nblk,
                        Bf.chunks, nchunk, Bf.shift, nshift, Bf.status);
     const bool random = (p->flags & TPKMC_PAIR_RANDOM) != 0;
-    const Shape P{1, nblk, nchunk, ncell_tot, B, B, (p->flags & TPKMC_ADAPTIVE_DT) != 0, !random, random};
+    Shape P{};
+    P.n_inst = 1;
+    P.nblk = nblk;
+    P.nchunk = nchunk;
+    P.ncell_tot = ncell_tot;
+    P.nob_tot = B;
+    P.max_nob = B;
+    P.prep = (p->flags & TPKMC_ADAPTIVE_DT) != 0;
+    P.any_search = !random;
+    P.any_random = random;
+    P.split = false;
     StepArgs<real> a = make_args<real>(Bf, s, o, nblk);
     enqueue_step<real>(nullptr, Bf, a, o, P, kWave, 2, st, false, 0);
     return hipGetLastError() == hipSuccess ? TPKMC_OK : TPKMC_EHIP;

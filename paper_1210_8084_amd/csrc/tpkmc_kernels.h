@@ -1718,7 +1718,7 @@ __device__ __forceinline__ void global_acc_add(ObAcc& G, int k, long long v) {
 // accumulators once per work-group: exponent maxima in the move, value sums
 // in the moment pass.
 constexpr int kSlots = 64;       // exponent table (the move's 256 records)
-constexpr int kMomSlots = 256;   // value table (the moment pass's kMomEntries * 256 records)
+constexpr int kMomSlots = 64;    // value table (the moment pass's 256 records)
 constexpr int kTabWords = kAccVals + 2;  // values, particle count, collider count
 struct MomentTable {
     static constexpr int kN = kMomSlots;
@@ -2112,88 +2112,76 @@ __device__ __forceinline__ void value_flush(MomentTable& tab, const StepArgs<rea
     }
 }
 
-// Block-table entries (kBlock records each) per work-group of the moment
-// pass.  The global sums take one set of atomics per (work-group, o-bin); a
-// work-group of one entry meets each o-bin along a fraction of one row of
-// c-bins, one of eight entries along several neighbouring rows, whose
-// records of one o-bin it sums first (16M Sedov blast on 189^3 c-bins and
-// 64^3 o-bins: 39 o-bins per 256 records against 17 on 128^3 c-bins).
-constexpr int kMomEntries = 8;
-
 template <typename real>
 __global__ void __launch_bounds__(kBlock) k_moments(StepArgs<real> a) {
     __shared__ MomentTable tab;
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    const Blk bt = a.blk[lb];
+    const Inst<real>& I = a.inst[bt.inst];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
+    const int64_t end = I.off + I.cnt;
+    const bool reorder = (I.flags & TPKMC_ALLOW_REORDER) != 0;
+    const bool has_mass = (I.flags & kHasMass) != 0;
     for (int t = tid; t < kMomSlots; t += kBlock) tab.key[t] = -1;
     for (int t = tid; t < kMomSlots * kTabWords; t += kBlock) (&tab.val[0][0])[t] = 0;
     __syncthreads();
-    for (int e = 0; e < kMomEntries; ++e) {
-        const int entry = lb * kMomEntries + e;
-        if (entry >= a.nblk) break;  // uniform
-        const Blk bt = a.blk[entry];
-        const Inst<real>& I = a.inst[bt.inst];
-        const int64_t end = I.off + I.cnt;
-        const bool reorder = (I.flags & TPKMC_ALLOW_REORDER) != 0;
-        const bool has_mass = (I.flags & kHasMass) != 0;
-        const int64_t i = (int64_t)bt.first + tid;
-        int ob = -1;
-        long long q[kAccVals];
+    const int64_t i = (int64_t)bt.first + tid;
+    int ob = -1;
+    long long q[kAccVals];
 #pragma unroll
-        for (int k = 0; k < kAccVals; ++k) q[k] = 0;
-        uint32_t cnt = 0, coll = 0;
-        if (i < end) {
-            // The same particles as the move's moment terms: alive after the
-            // step (not absorbed), finite, with a valid mass.
-            const int64_t p = reorder ? i : (int64_t)a.src[i];
-            const bool alive = a.alive ? a.alive[p] != 0 : true;
-            const real x = a.x[p], y = a.y[p], z = a.z[p], vx = a.vx[p], vy = a.vy[p], vz = a.vz[p];
-            const real mi = has_mass ? a.mass[p] : I.mass;
-            const bool fin = finite3(x, y, z) && finite3(vx, vy, vz) &&
-                             (!has_mass || (mi > real(0) && mi < real(INFINITY)));
-            if (alive && fin) {
-                ob = obin_of(I, x, y, z);
-                const bool c = a.coll[p] != 0;
-                double vir[3] = {0.0, 0.0, 0.0};
-                if (c) {
-                    vir[0] = (double)a.vir[3 * p];
-                    vir[1] = (double)a.vir[3 * p + 1];
-                    vir[2] = (double)a.vir[3 * p + 2];
-                }
-                const double m = has_mass ? (double)mi : I.mass_d;
-                const double* S = a.shift + (int64_t)ob * 3;
-                double t[kAccVals];
-                moment_terms(m, (double)vx, (double)vy, (double)vz, S, vir[0], vir[1], vir[2], t);
-                const ObAcc& G = a.macc[ob];
-                const double s0 = fixed_scale(G.e[0]), s1 = fixed_scale(G.e[1]);
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    q[k] = to_fixed(t[k], s0);
-                    q[3 + k] = to_fixed(t[3 + k], s1);
-                }
-                if (c) {
-                    const double s2 = fixed_scale(G.e[2]);
-#pragma unroll
-                    for (int k = 6; k < 9; ++k) q[k] = to_fixed(t[k], s2);
-                }
-                if (has_mass) q[9] = to_fixed(t[9], fixed_scale(G.e[3]));
-                cnt = 1;
-                coll = c ? 1 : 0;
+    for (int k = 0; k < kAccVals; ++k) q[k] = 0;
+    uint32_t cnt = 0, coll = 0;
+    if (i < end) {
+        // The same particles as the move's moment terms: alive after the
+        // step (not absorbed), finite, with a valid mass.
+        const int64_t p = reorder ? i : (int64_t)a.src[i];
+        const bool alive = a.alive ? a.alive[p] != 0 : true;
+        const real x = a.x[p], y = a.y[p], z = a.z[p], vx = a.vx[p], vy = a.vy[p], vz = a.vz[p];
+        const real mi = has_mass ? a.mass[p] : I.mass;
+        const bool fin = finite3(x, y, z) && finite3(vx, vy, vz) &&
+                         (!has_mass || (mi > real(0) && mi < real(INFINITY)));
+        if (alive && fin) {
+            ob = obin_of(I, x, y, z);
+            const bool c = a.coll[p] != 0;
+            double vir[3] = {0.0, 0.0, 0.0};
+            if (c) {
+                vir[0] = (double)a.vir[3 * p];
+                vir[1] = (double)a.vir[3 * p + 1];
+                vir[2] = (double)a.vir[3 * p + 2];
             }
-        }
-        bool head;
-        const int lim = row_lim(ob, lane, head);
-        const bool anyc = __ballot(coll != 0) != 0;
+            const double m = has_mass ? (double)mi : I.mass_d;
+            const double* S = a.shift + (int64_t)ob * 3;
+            double t[kAccVals];
+            moment_terms(m, (double)vx, (double)vy, (double)vz, S, vir[0], vir[1], vir[2], t);
+            const ObAcc& G = a.macc[ob];
+            const double s0 = fixed_scale(G.e[0]), s1 = fixed_scale(G.e[1]);
 #pragma unroll
-        for (int k = 0; k < kAccVals; ++k) {
-            if ((k >= 6 && k <= 8 && !anyc) || (k == 9 && !has_mass)) continue;  // wave-uniform
-            q[k] = row_sum64(q[k], lim);
+            for (int k = 0; k < 3; ++k) {
+                q[k] = to_fixed(t[k], s0);
+                q[3 + k] = to_fixed(t[3 + k], s1);
+            }
+            if (c) {
+                const double s2 = fixed_scale(G.e[2]);
+#pragma unroll
+                for (int k = 6; k < 9; ++k) q[k] = to_fixed(t[k], s2);
+            }
+            if (has_mass) q[9] = to_fixed(t[9], fixed_scale(G.e[3]));
+            cnt = 1;
+            coll = c ? 1 : 0;
         }
-        cnt = row_sum32(cnt, lim);
-        if (anyc) coll = row_sum32(coll, lim);
-        if ((head || (lane & 15) == 0) && ob >= 0) value_flush(tab, a, ob, q, cnt, coll);
     }
+    bool head;
+    const int lim = row_lim(ob, lane, head);
+    const bool anyc = __ballot(coll != 0) != 0;
+#pragma unroll
+    for (int k = 0; k < kAccVals; ++k) {
+        if ((k >= 6 && k <= 8 && !anyc) || (k == 9 && !has_mass)) continue;  // wave-uniform
+        q[k] = row_sum64(q[k], lim);
+    }
+    cnt = row_sum32(cnt, lim);
+    if (anyc) coll = row_sum32(coll, lim);
+    if ((head || (lane & 15) == 0) && ob >= 0) value_flush(tab, a, ob, q, cnt, coll);
     __syncthreads();
     // The table to the global sums: one thread per (slot, table word).
     for (int t = tid; t < kMomSlots * kTabWords; t += kBlock) {
@@ -2335,8 +2323,7 @@ void launch_move(const StepArgs<real>& a, hipStream_t s) {
 }
 template <typename real>
 void launch_moments(const StepArgs<real>& a, hipStream_t s) {
-    const unsigned grid = (unsigned)((a.nblk + kMomEntries - 1) / kMomEntries);
-    hipLaunchKernelGGL(k_moments<real>, dim3(grid), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(k_moments<real>, dim3(a.nblk), dim3(kBlock), 0, s, a);
 }
 
 }  // namespace tpkmc
