@@ -44,6 +44,7 @@ def _run(w, precision, steps, progress=None, rank_time=False, pair_random=False)
     glob = torch.zeros((steps, 8), dtype=torch.float64, device="cuda")
     cnt = torch.zeros((steps, 8), dtype=torch.int64, device="cuda")
     eng.autotune(dst, [(0, w.n, g, p)])
+    cells, speed_bound = list(eng.tuned_cells(0)), eng.tuned_speed(0)
     t0 = time.perf_counter()
     for s in range(steps):
         o = T.DeviceOutputs(counters=cnt[s:s + 1], globals=glob[s:s + 1], moments=out.moments, pairs=None,
@@ -57,7 +58,8 @@ def _run(w, precision, steps, progress=None, rank_time=False, pair_random=False)
     status = eng.status()
     host = T.to_host(dst)
     res = dict(state=host, moments=out.moments.cpu().numpy(), globals=glob.cpu().numpy(),
-               counters=cnt.cpu().numpy().view(np.uint64), wall=wall, status=status)
+               counters=cnt.cpu().numpy().view(np.uint64), wall=wall, status=status, cells=cells,
+               speed_bound=speed_bound)
     eng.close()
     del dst
     torch.cuda.empty_cache()
@@ -137,6 +139,7 @@ def sod(precision, n=4_000_000, steps=500, kn=1e-3, planar=False, seed=1, rank_t
         fn = fc / ((fe[1] - fe[0]) * (w.info["side"] if planar else 0.05 * 0.05))
         width, x_fit = _tanh_width(0.5 * (fe[1:] + fe[:-1]), fn, x_s, nr, n2)
     return dict(workload=f"{w.name} n={n} kn={kn}", steps=steps, t=t, wall_s=r["wall"],
+                cells=r["cells"], speed_bound=r["speed_bound"], status=r["status"],
                 rank="random partners" if pair_random else "contact time" if rank_time else "closest approach",
                 shock_x_exact=x_s, shock_x_fit=x_fit, shock_width=width,
                 shock_width_mfp=None if width is None else width / lam,
@@ -175,7 +178,8 @@ def noh(precision, n=8_000_000, steps=800, planar=False, seed=1, kn=1e-3, ncell=
     if core.sum() > 100:
         dv2 = sum((st[k][core] - st[k][core].mean()) ** 2 for k in ("vx", "vy", "vz")[:f])
         t_core = float(w.params["mass"] * dv2.mean() / f)
-    return dict(workload=f"{w.name} n={n}", steps=steps, t=t, wall_s=r["wall"], r_shock=rs,
+    return dict(workload=f"{w.name} n={n}", steps=steps, t=t, wall_s=r["wall"],
+                cells=r["cells"], speed_bound=r["speed_bound"], status=r["status"], r_shock=rs,
                 l1_density=float(np.mean(np.abs(n_ - na)) / w.info["n0"]),
                 shocked_density_over_n0=float(np.mean(n_[inside]) / w.info["n0"]) if inside.any() else None,
                 analytic_shocked=((gamma + 1.0) / (gamma - 1.0)) ** 2,
@@ -208,7 +212,8 @@ def noh3d(precision, n=8_000_000, steps=160, seed=1):
     if core.sum() > 100:
         dv2 = sum((st[k][core] - st[k][core].mean()) ** 2 for k in ("vx", "vy", "vz"))
         t_core = float(w.params["mass"] * dv2.mean() / 3.0)
-    return dict(workload=f"{w.name} n={n}", steps=steps, t=t, wall_s=r["wall"], r_shock=rs,
+    return dict(workload=f"{w.name} n={n}", steps=steps, t=t, wall_s=r["wall"],
+                cells=r["cells"], speed_bound=r["speed_bound"], status=r["status"], r_shock=rs,
                 l1_density=float(np.mean(np.abs(n_ - na)) / w.info["n0"]),
                 shocked_density_over_n0=float(np.mean(n_[inside]) / w.info["n0"]) if inside.any() else None,
                 analytic_shocked=((gamma + 1.0) / (gamma - 1.0)) ** 3,
@@ -256,7 +261,8 @@ def sedov(precision, n=16_000_000, steps=600, planar=False, seed=1, rank_time=Fa
         return float("nan")
     width = float(outer_cross(1.0 + 0.1 * (top - 1.0)) - outer_cross(1.0 + 0.9 * (top - 1.0)))
     lam = w.info.get("lam", 1e-3)
-    return dict(workload=f"{w.name} n={n}", steps=steps, t=t, wall_s=r["wall"], r_shock_analytic=R,
+    return dict(workload=f"{w.name} n={n}", steps=steps, t=t, wall_s=r["wall"],
+                cells=r["cells"], speed_bound=r["speed_bound"], status=r["status"], r_shock_analytic=R,
                 rank="random partners" if pair_random else "contact time" if rank_time else "closest approach",
                 central_density=float(rho[rc < 0.05].mean()),
                 front_width=width, front_width_mfp=width / lam,
