@@ -77,7 +77,7 @@ def phase_bytes(rs, n, ncell_tot, nobin, reorder, colliders=0):
     pass (listed also on their own)."""
     rec = 8 * rs
     pkey = 8 if rs == 4 else 4   # FP32: 64-bit (d_min^2, partner) key; FP64: partner index
-    acc = 192                    # exact sums of one o-bin
+    acc = 128                    # exact sums of one o-bin
     src = 0 if reorder else 4
     # record, own and partner's partner key in; state, id, alive, collided flag
     # out; colliders' virial terms out

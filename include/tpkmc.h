@@ -266,7 +266,7 @@ const char* tpkmc_strerror(int code);
 
 /* Allocates a handle and all its device scratch on cfg->device (memory is
  * sized from the capacities: about 73 B per particle in FP32, 113 B in FP64,
- * 8 B per c-bin, 216 B per o-bin).  *out is NULL on failure. */
+ * 8 B per c-bin, 152 B per o-bin).  *out is NULL on failure. */
 int tpkmc_create(const tpkmc_config* cfg, tpkmc_handle** out);
 
 /* Waits for the handle's work, frees everything.  NULL is a no-op. */
@@ -293,7 +293,7 @@ int tpkmc_step(tpkmc_handle* h, const tpkmc_grid* g, const tpkmc_params* p,
  *              results equal those of tpkmc_step on a new handle.
  * Returns TPKMC_ECAPACITY, before anything is launched, when the step's
  * scratch exceeds the array: about 105 B per particle in FP64 (113 with
- * per-particle masses), 69 B in FP32 (73), plus 4 B per c-bin and 216 B per
+ * per-particle masses), 69 B in FP32 (73), plus 4 B per c-bin and 152 B per
  * o-bin, so at most about 0.6M particles in FP64 and 0.9M in FP32.
  * Every call on a GPU uses that GPU's one array, and the array keeps the
  * last call's contents (the call clears what must start at zero), so calls

@@ -226,25 +226,10 @@ __global__ void __launch_bounds__(256) k_finalize(Inst<real>* inst, const double
 
 // Exact shifted o-bin sums -> the moments of the output: momentum and central
 // second moments; the bin mean becomes the shift of the next step, so the
-// sums stay small next time.  Each sum is converted to double by an
-// error-free sum of its top parts plus the rest (the result is within an
-// ulp of the exact sum, and a function of it only).
+// sums stay small next time.  Each integer sum is rounded once to double (a
+// function of the exact sum only) and scaled by its power-of-two quantum.
 // Each work-group (256 threads) stages its 256 o-bins' output rows through
 // LDS, so the stores are coalesced; every output value is written.
-__device__ __forceinline__ double fx_to_double(unsigned long long lo, long long hi, double inv_scale) {
-    // The exact value hi 2^32 + lo as hh 2^64 + (hl + lh) 2^32 + ll, three
-    // exactly representable parts.
-    const long long hh = hi >> 32;
-    const unsigned long long mid = (unsigned long long)(uint32_t)hi + (lo >> 32);
-    const double a = (double)hh * 0x1p64;
-    const double b = (double)mid * 0x1p32;
-    const double c = (double)(uint32_t)lo;
-    const double s = a + b;  // and its rounding error, exactly
-    const double bp = s - a;
-    const double e = (a - (s - bp)) + (b - bp);
-    return (s + (e + c)) * inv_scale;
-}
-
 template <typename real>
 __global__ void __launch_bounds__(256) k_moments_final(const Inst<real>* inst, const ObAcc* macc, double* moments,
                                                        double* shift) {
@@ -260,16 +245,19 @@ __global__ void __launch_bounds__(256) k_moments_final(const Inst<real>* inst, c
         const ObAcc& A = macc[ob];
         double* M = rows + threadIdx.x * TPKMC_MOMENT_STRIDE;
         double* S = shift + ob * 3;
-        const unsigned long long cnt = A.cnt;
+        const unsigned long long cnt = A.nc & 0xffffffffull, coll = A.nc >> 32;
         for (int k = 0; k < TPKMC_MOMENT_STRIDE; ++k) M[k] = 0.0;
         if (cnt > 0) {
-            double inv[4];  // quanta 2^(E-50) of the four kinds (as in the moment pass)
+            // Quanta 2^(E-50+h) of the four kinds (as in the moment pass); each
+            // integer sum is rounded once to double, then scaled exactly.
+            const int h = acc_headroom(cnt);
+            double inv[4];
             for (int k = 0; k < 4; ++k) {
                 const int e = A.e[k] > 0 ? A.e[k] - kExpBias : 0;
-                inv[k] = ldexp(1.0, max(e, -969) - 50);
+                inv[k] = ldexp(1.0, max(e, -969) - 50 + h);
             }
             double v[kAccVals];
-            for (int k = 0; k < kAccVals; ++k) v[k] = fx_to_double(A.lo[k], A.hi[k], inv[acc_kind(k)]);
+            for (int k = 0; k < kAccVals; ++k) v[k] = (double)A.sum[k] * inv[acc_kind(k)];
             // Without per-particle masses the moment pass leaves the mass sum out.
             const double mass = (I.flags & kHasMass) ? v[9] : (double)cnt * I.mass_d;
             M[0] = (double)cnt;
@@ -281,7 +269,7 @@ __global__ void __launch_bounds__(256) k_moments_final(const Inst<real>* inst, c
                 M[7 + ax] = v[6 + ax];
                 S[ax] = S[ax] + mean_off;
             }
-            M[10] = (double)A.coll;
+            M[10] = (double)coll;
             M[11] = mass;
         }
     }
@@ -323,7 +311,7 @@ struct Buffers {
     Chunk* chunks;
     unsigned long long* bkey;
     double *gpart, *cpart, *shift;
-    ObAcc* macc;      // exact o-bin sums, 192 B per o-bin
+    ObAcc* macc;      // exact o-bin sums, 128 B per o-bin
     void* vir;        // colliders' virial terms, 3 reals per particle
     uint8_t* coll;    // collided flags, 1 B per particle
     unsigned long long* pair_count;

@@ -22,28 +22,32 @@ enum GPart {
 };
 
 // Exact o-bin sums, in two passes over the particles.  The move records,
-// per o-bin and kind of term, the exponent E of a power of two above every
-// term (|x| < 2^E, an integer maximum, so the order does not matter).  The
-// moment pass then rounds each term once to an integer q, a multiple of
-// 2^(E-50) (|q| < 2^50): a work-group sums its at most 2048 terms per o-bin
-// in one int64 per value, and the global sums split each work-group sum S
-// into its low 32-bit digit (S mod 2^32) and the signed rest S >> 32,
-// summed in separate 64-bit words: 2^32 work-group sums fit, no carry
-// passes between the words, and integer sums do not depend on the order of
-// the terms.  Kinds: 0 m (v - shift) per axis, 1 m (v - shift)^2 per axis,
-// 2 virial terms, 3 mass.  Per o-bin: values 0..2 momentum, 3..5 spread,
-// 6..8 virial, 9 mass (per-particle masses only), the particle and
-// collider counts, and the four exponents (biased by kExpBias; 0: no
-// nonzero term).
+// per o-bin, the exponent E per kind of term of a power of two above every
+// term (|x| < 2^E, an integer maximum, so the order does not matter) and the
+// counts of particles and colliders.  The moment pass then rounds each term
+// once to an integer q, a multiple of 2^(E-50+h) (|q| <= 2^(50-h)), where
+// the headroom h = max(0, ceil(log2 n) - 12) grows with the o-bin's n
+// particles (none up to 4096): the n integers of a value sum to less than
+// 2^62 in magnitude, so every partial and the total fit one int64, and
+// integer sums do not depend on the order of the terms.  Kinds: 0 m (v -
+// shift) per axis, 1 m (v - shift)^2 per axis, 2 virial terms, 3 mass.  Per
+// o-bin: values 0..2 momentum, 3..5 spread, 6..8 virial, 9 mass
+// (per-particle masses only); the particle count in the low 32 bits of nc
+// and the collider count in its high 32 bits (at most 2^32 - 1 particles
+// per o-bin); the four exponents (biased by kExpBias; 0: no nonzero term).
 constexpr int kAccVals = 10;
 constexpr int kExpBias = 1100;
 struct ObAcc {
-    unsigned long long lo[kAccVals];  // sums of the low digits
-    long long hi[kAccVals];           // sums of the high parts
-    unsigned long long cnt, coll;
+    long long sum[kAccVals];
+    unsigned long long nc;
     int32_t e[4];
+    unsigned long long pad[3];
 };
-static_assert(sizeof(ObAcc) == 192, "one o-bin accumulator is 192 B");
+static_assert(sizeof(ObAcc) == 128, "one o-bin accumulator is 128 B");
+__host__ __device__ inline int acc_headroom(unsigned long long n) {
+    const int c = n <= 1 ? 0 : 64 - __builtin_clzll(n - 1);  // ceil(log2 n)
+    return c > 12 ? c - 12 : 0;
+}
 __host__ __device__ constexpr int acc_kind(int k) { return k < 3 ? 0 : k < 6 ? 1 : k < 9 ? 2 : 3; }
 
 // Instance descriptor on the device.  Derived grid quantities are computed

@@ -1690,10 +1690,10 @@ __device__ __forceinline__ long long to_fixed(double x, double scale) {
     return __double_as_longlong(fma(x, scale, kMagic)) - 0x4338000000000000ll;
 }
 
-// 2^(50-E) for a biased exponent, kept a normal double.
-__device__ __forceinline__ double fixed_scale(int eb) {
+// 2^(50-h-E) for a biased exponent E and headroom h, kept a normal double.
+__device__ __forceinline__ double fixed_scale(int eb, int h) {
     const int e = eb > 0 ? eb - kExpBias : 0;
-    return ldexp(1.0, 50 - max(e, -969));
+    return ldexp(1.0, 50 - h - max(e, -969));
 }
 
 template <int CTRL>
@@ -1704,14 +1704,10 @@ __device__ __forceinline__ long long dpp_move64(long long v) {
     return (long long)(((unsigned long long)l1 << 32) | l0);
 }
 
-// Adds one work-group (or lane) sum of a value to the global sums of an
-// o-bin: the low digit and the rest into separate words (see ObAcc).
+// Adds one work-group (or lane) sum of a value to the global sum of an
+// o-bin (one int64; see ObAcc for the bound).
 __device__ __forceinline__ void global_acc_add(ObAcc& G, int k, long long v) {
-    if (v == 0) return;
-    const unsigned long long lo = (uint32_t)v;
-    const long long hi = v >> 32;
-    if (lo) atomicAdd(&G.lo[k], lo);
-    if (hi) atomicAdd((unsigned long long*)&G.hi[k], (unsigned long long)hi);
+    if (v) atomicAdd((unsigned long long*)&G.sum[k], (unsigned long long)v);
 }
 
 // Work-group tables keyed by o-bin (open addressing), flushed to the global
@@ -1719,7 +1715,7 @@ __device__ __forceinline__ void global_acc_add(ObAcc& G, int k, long long v) {
 // in the moment pass.
 constexpr int kSlots = 64;       // exponent table (the move's 256 records)
 constexpr int kMomSlots = 64;    // value table (the moment pass's 256 records)
-constexpr int kTabWords = kAccVals + 2;  // values, particle count, collider count
+constexpr int kTabWords = kAccVals;  // the values' integer sums
 struct MomentTable {
     static constexpr int kN = kMomSlots;
     int key[kN];
@@ -1729,6 +1725,7 @@ struct ExpTable {
     static constexpr int kN = kSlots;
     int key[kN];
     int e[kN][4];
+    uint32_t n[kN][2];  // particles, colliders
 };
 
 template <typename Table>
@@ -1810,10 +1807,11 @@ __device__ __forceinline__ int row_max32(int v, int lim) {
 constexpr int kMoveRec = 1;
 constexpr int kMoveLanes = kBlock / kMoveRec;
 
-// A lane's run maxima of one o-bin into the work-group table, or straight
-// into the global accumulators when the table is full.
+// A lane's run maxima and counts of one o-bin into the work-group table, or
+// straight into the global accumulators when the table is full.
 template <typename real>
-__device__ __forceinline__ void exp_flush(ExpTable& tab, const StepArgs<real>& a, int ob, const int* e) {
+__device__ __forceinline__ void exp_flush(ExpTable& tab, const StepArgs<real>& a, int ob, const int* e, uint32_t cnt,
+                                          uint32_t coll) {
     const int slot = table_slot(tab, ob);
     int* d = slot >= 0 ? tab.e[slot] : nullptr;
 #pragma unroll
@@ -1821,6 +1819,12 @@ __device__ __forceinline__ void exp_flush(ExpTable& tab, const StepArgs<real>& a
         if (!e[k]) continue;
         if (d) atomicMax(d + k, e[k]);
         else atomicMax(&a.macc[ob].e[k], e[k]);
+    }
+    if (d) {
+        if (cnt) atomicAdd(&tab.n[slot][0], cnt);
+        if (coll) atomicAdd(&tab.n[slot][1], coll);
+    } else if (cnt) {
+        atomicAdd(&a.macc[ob].nc, (unsigned long long)cnt | ((unsigned long long)coll << 32));
     }
 }
 
@@ -1842,6 +1846,7 @@ __global__ void __launch_bounds__(kMoveLanes) k_move(StepArgs<real> a) {
         for (int t = tid; t < kSlots; t += kMoveLanes) {
             tab.key[t] = -1;
             for (int k = 0; k < 4; ++k) tab.e[t][k] = 0;
+            tab.n[t][0] = tab.n[t][1] = 0;
         }
         __syncthreads();
     }
@@ -1849,6 +1854,7 @@ __global__ void __launch_bounds__(kMoveLanes) k_move(StepArgs<real> a) {
     int mob = -1;                              // o-bin of the run
     double sh[3] = {0.0, 0.0, 0.0};            // its velocity shift
     int me[4] = {0, 0, 0, 0};                  // its exponent maxima per kind
+    uint32_t mcnt = 0, mcoll = 0;              // its particles and colliders
     // The next record and its partner key are loaded while the current one
     // is processed (two records in flight per lane).
     const int64_t i_first = (int64_t)bt.first + kMoveRec * tid;
@@ -2003,13 +2009,16 @@ __global__ void __launch_bounds__(kMoveLanes) k_move(StepArgs<real> a) {
                     if (a.macc) {
                         const int ob = obin_of(I, nx, ny, nz);
                         if (ob != mob) {
-                            if (mob >= 0) exp_flush(tab, a, mob, me);
+                            if (mob >= 0) exp_flush(tab, a, mob, me, mcnt, mcoll);
                             const double* S = a.shift + (int64_t)ob * 3;
                             sh[0] = S[0]; sh[1] = S[1]; sh[2] = S[2];
                             mob = ob;
 #pragma unroll
                             for (int k = 0; k < 4; ++k) me[k] = 0;
+                            mcnt = mcoll = 0;
                         }
+                        mcnt += 1;
+                        mcoll += mutual ? 1u : 0u;
                         double t[kAccVals];
                         moment_terms(m, dvx, dvy, dvz, sh, virx, viry, virz, t);
                         me[0] = max(me[0], exp_above(fmax(fmax(fabs(t[0]), fabs(t[1])), fabs(t[2]))));
@@ -2054,12 +2063,20 @@ __global__ void __launch_bounds__(kMoveLanes) k_move(StepArgs<real> a) {
         const int lim = row_lim(mob, lane, head);
 #pragma unroll
         for (int k = 0; k < 4; ++k) me[k] = row_max32(me[k], lim);
-        if ((head || (lane & 15) == 0) && mob >= 0) exp_flush(tab, a, mob, me);
+        mcnt = row_sum32(mcnt, lim);
+        mcoll = row_sum32(mcoll, lim);
+        if ((head || (lane & 15) == 0) && mob >= 0) exp_flush(tab, a, mob, me, mcnt, mcoll);
         __syncthreads();
-        for (int t = tid; t < kSlots * 4; t += kMoveLanes) {
-            const int slot = t >> 2, k = t & 3;
+        for (int t = tid; t < kSlots * 5; t += kMoveLanes) {
+            const int slot = t / 5, k = t % 5;
             const int ob = tab.key[slot];
-            if (ob >= 0 && tab.e[slot][k]) atomicMax(&a.macc[ob].e[k], tab.e[slot][k]);
+            if (ob < 0) continue;
+            if (k < 4) {
+                if (tab.e[slot][k]) atomicMax(&a.macc[ob].e[k], tab.e[slot][k]);
+            } else if (tab.n[slot][0]) {
+                atomicAdd(&a.macc[ob].nc,
+                          (unsigned long long)tab.n[slot][0] | ((unsigned long long)tab.n[slot][1] << 32));
+            }
         }
     }
     double v[11] = {gpx, gpy, gpz, gek, gvm, gvir, gm, galive, gpairs, gabs, ghave};
@@ -2093,22 +2110,17 @@ __global__ void __launch_bounds__(kMoveLanes) k_move(StepArgs<real> a) {
 // measured fastest on the sparse 16M Sedov blast; several consecutive
 // records per lane lose more to their strided loads than they save.
 template <typename real>
-__device__ __forceinline__ void value_flush(MomentTable& tab, const StepArgs<real>& a, int ob, const long long* q,
-                                            uint32_t cnt, uint32_t coll) {
+__device__ __forceinline__ void value_flush(MomentTable& tab, const StepArgs<real>& a, int ob, const long long* q) {
     const int slot = table_slot(tab, ob);
     if (slot >= 0) {
         unsigned long long* T = reinterpret_cast<unsigned long long*>(tab.val[slot]);
 #pragma unroll
         for (int k = 0; k < kAccVals; ++k)
             if (q[k]) atomicAdd(T + k, (unsigned long long)q[k]);
-        atomicAdd(T + kAccVals, (unsigned long long)cnt);
-        if (coll) atomicAdd(T + kAccVals + 1, (unsigned long long)coll);
     } else {
         ObAcc& G = a.macc[ob];
 #pragma unroll
         for (int k = 0; k < kAccVals; ++k) global_acc_add(G, k, q[k]);
-        atomicAdd(&G.cnt, (unsigned long long)cnt);
-        if (coll) atomicAdd(&G.coll, (unsigned long long)coll);
     }
 }
 
@@ -2131,7 +2143,7 @@ __global__ void __launch_bounds__(kBlock) k_moments(StepArgs<real> a) {
     long long q[kAccVals];
 #pragma unroll
     for (int k = 0; k < kAccVals; ++k) q[k] = 0;
-    uint32_t cnt = 0, coll = 0;
+    bool coll = false;
     if (i < end) {
         // The same particles as the move's moment terms: alive after the
         // step (not absorbed), finite, with a valid mass.
@@ -2154,44 +2166,40 @@ __global__ void __launch_bounds__(kBlock) k_moments(StepArgs<real> a) {
             const double* S = a.shift + (int64_t)ob * 3;
             double t[kAccVals];
             moment_terms(m, (double)vx, (double)vy, (double)vz, S, vir[0], vir[1], vir[2], t);
+            // The quanta of the o-bin: its exponents and the headroom of its
+            // particle count, both from the move.
             const ObAcc& G = a.macc[ob];
-            const double s0 = fixed_scale(G.e[0]), s1 = fixed_scale(G.e[1]);
+            const int h = acc_headroom(G.nc & 0xffffffffull);
+            const double s0 = fixed_scale(G.e[0], h), s1 = fixed_scale(G.e[1], h);
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 q[k] = to_fixed(t[k], s0);
                 q[3 + k] = to_fixed(t[3 + k], s1);
             }
             if (c) {
-                const double s2 = fixed_scale(G.e[2]);
+                const double s2 = fixed_scale(G.e[2], h);
 #pragma unroll
                 for (int k = 6; k < 9; ++k) q[k] = to_fixed(t[k], s2);
             }
-            if (has_mass) q[9] = to_fixed(t[9], fixed_scale(G.e[3]));
-            cnt = 1;
-            coll = c ? 1 : 0;
+            if (has_mass) q[9] = to_fixed(t[9], fixed_scale(G.e[3], h));
+            coll = c;
         }
     }
     bool head;
     const int lim = row_lim(ob, lane, head);
-    const bool anyc = __ballot(coll != 0) != 0;
+    const bool anyc = __ballot(coll) != 0;
 #pragma unroll
     for (int k = 0; k < kAccVals; ++k) {
         if ((k >= 6 && k <= 8 && !anyc) || (k == 9 && !has_mass)) continue;  // wave-uniform
         q[k] = row_sum64(q[k], lim);
     }
-    cnt = row_sum32(cnt, lim);
-    if (anyc) coll = row_sum32(coll, lim);
-    if ((head || (lane & 15) == 0) && ob >= 0) value_flush(tab, a, ob, q, cnt, coll);
+    if ((head || (lane & 15) == 0) && ob >= 0) value_flush(tab, a, ob, q);
     __syncthreads();
-    // The table to the global sums: one thread per (slot, table word).
+    // The table to the global sums: one thread per (slot, value).
     for (int t = tid; t < kMomSlots * kTabWords; t += kBlock) {
         const int slot = t / kTabWords, wd = t % kTabWords;
         const int o = tab.key[slot];
-        if (o < 0) continue;
-        const long long v = tab.val[slot][wd];
-        ObAcc& G = a.macc[o];
-        if (wd < kAccVals) global_acc_add(G, wd, v);
-        else if (v) atomicAdd(wd == kAccVals ? &G.cnt : &G.coll, (unsigned long long)v);
+        if (o >= 0) global_acc_add(a.macc[o], wd, tab.val[slot][wd]);
     }
 }
 
