@@ -328,9 +328,9 @@ int tpkmc_run(tpkmc_handle* h, const tpkmc_particles* s,
  *    speed at most v_c that meet the criteria of Sec. 2.4 within a step start
  *    at most D + 2 v_c dt apart, so on c-bins at least that wide the stencil
  *    holds every such pair.  Per instance, with v_c = 2 times the
- *    root-mean-square speed of its live particles on this state (split only
- *    while the particles above v_c hold less than half of the kinetic
- *    energy, which excludes a point blast), the slow
+ *    root-mean-square speed v_rms of its live particles on this state (6
+ *    v_rms when the particles above 2 v_rms hold more than half of the
+ *    kinetic energy, as in a point blast), the slow
  *    particles (|v| <= v_c, decided every step) are binned on c-bins refined
  *    per axis to the largest count that keeps a factor 1 + 1/64 over that
  *    reach, when that is at least 1.25 times the configured count (3 or more

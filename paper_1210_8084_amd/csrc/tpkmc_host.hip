@@ -837,18 +837,22 @@ int grow_cells(tpkmc_handle* h, int64_t need) {
 // (its energy is conserved) while its largest speed grows with the tail of
 // the distribution, and a Maxwellian has 0.7% of its particles above 2 v_rms
 // in three dimensions (1.8% in two), few enough that the finer c-bins of
-// the rest more than pay for their searches.  The split is used only when
-// the particles above v_c hold less than half of the kinetic energy (a
-// Maxwellian: 3.5% in three dimensions, 9% in two, 26% in one): where they
-// hold most of it (a point blast), collisions share it out and lift many
-// more particles above the bound later in the run, whose searches then cost
-// more than the refinement saves.  Per instance (not with random partners,
+// the rest more than pay for their searches.  Where the particles above
+// 2 v_rms hold more than half of the kinetic energy (a Maxwellian: 3.5% in
+// three dimensions, 9% in two, 26% in one), the gas is far from thermal (a
+// point blast): collisions share that energy out and lift many more
+// particles above 2 v_rms later in the run.  There the bound is 6 v_rms,
+// above which at most 1/36 of the particles can ever be, as long as the
+// energy is conserved (Markov's inequality on |v|^2; the 16M Sedov blast:
+// 3.11 ms/step, against 3.17 with sqrt(20) v_rms and 3.35 unsplit).  Per
+// instance (not with random partners,
 // whose draw depends on the c-bin) and per axis, the slow particles' c-bins
 // are the largest count whose width keeps a factor 1 + 1/64 over that reach
 // (the rounding of the binning and of the pair test), used when it is at
 // least 1.25 times the configured count (3 or more on periodic axes, never
 // on a planar z), with at most one c-bin per two particles.
-constexpr double kSpeedBound = 2.0;
+constexpr double kSpeedBound = 2.0;      // thermal gases
+constexpr double kSpeedBoundHot = 6.0;   // far from thermal
 constexpr double kReachMargin = 1.0 + 1.0 / 64.0;
 constexpr double kMinRefine = 1.25;
 constexpr double kHotEnergy = 0.5;
@@ -898,13 +902,13 @@ int choose_cells(tpkmc_handle* h, const tpkmc_particles* s, const tpkmc_instance
         const tpkmc_instance& q = in[k];
         tpkmc_handle::Cells c{q.grid, q.params.sigma, q.params.dt, q.params.flags & kCellKey,
                               {q.grid.ncell[0], q.grid.ncell[1], q.grid.ncell[2]}, 0.0};
-        const double vc = nlive[k] > 0.0 ? kSpeedBound * sqrt(v2sum[k] / nlive[k]) : 0.0;
+        const bool thermal = !(hot[k] > kHotEnergy * v2sum[k]);
+        const double vc = nlive[k] > 0.0 ? (thermal ? kSpeedBound : kSpeedBoundHot) * sqrt(v2sum[k] / nlive[k]) : 0.0;
         const double reach = sqrt((double)I[k].D2) + 2.0 * vc * q.params.dt;
         const bool planar = (q.params.flags & TPKMC_PLANAR) != 0;
         int64_t cfg = 1;
         for (int a = 0; a < 3; ++a) cfg *= q.grid.ncell[a];
-        const bool cold = !(hot[k] > kHotEnergy * v2sum[k]);
-        if (!(q.params.flags & TPKMC_PAIR_RANDOM) && q.count > 0 && reach > 0.0 && std::isfinite(reach) && cold) {
+        if (!(q.params.flags & TPKMC_PAIR_RANDOM) && q.count > 0 && reach > 0.0 && std::isfinite(reach)) {
             const int64_t cap = std::max<int64_t>(cfg, q.count / 2);
             int32_t lo[3];
             for (int a = 0; a < 3; ++a) {

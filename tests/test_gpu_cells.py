@@ -11,10 +11,12 @@ neighbourhood; nothing but the search's work changes, at any speeds.
    axes including one of three configured c-bins, absorbing walls, the
    plane, contact-time ranking); a tube whose speeds are raised after tuning.
  - Random partners (their draw depends on the c-bin) keep the configured
-   c-bins; a planar grid keeps one c-bin on z; a point blast, whose fast
-   particles hold most of the energy, keeps the configured c-bins.
+   c-bins; a planar grid keeps one c-bin on z; the speed bound is 2 v_rms
+   for a thermal gas and 6 v_rms for a point blast (bit-exact too).
  - FP32: the tuned handle's pairs equal an untuned handle's, also through a
    captured graph, with fast particles, and inside a batch."""
+import math
+
 import numpy as np
 import pytest
 
@@ -173,23 +175,34 @@ def test_fp64_split_with_fast_particles_equals_oracle(T, oracle, case):
     assert n_fast > 60
 
 
-def test_blast_keeps_the_configured_cells(T):
-    """A point blast: its few fast particles hold nearly all the kinetic
-    energy (more than half of it above the speed bound), which collisions
-    will spread over many more particles above the bound, so the autotuner
-    keeps the configured c-bins; a thermal gas of the same size is split."""
-    w = W.sedov(n=30_000, seed=3, kn=1e-2, ncell=8, nobin=4)
-    eng = engine(T, w, T.FP32)
-    dst = T.to_device(w.state, T.FP32)
-    eng.autotune(dst, [(0, w.n, w.grid, w.params)])
-    assert eng.tuned_cells(0) == tuple(w.grid["ncell"]) and eng.tuned_speed(0) == 0.0
-    eng.close()
-    g = fast_box(n=30_000, seed=4, ncell=(8, 8, 8), bc=(R, R, R), fast_frac=0.0)
-    eng = engine(T, g, T.FP32)
-    dst = T.to_device(g.state, T.FP32)
-    eng.autotune(dst, [(0, g.n, g.grid, g.params)])
-    assert np.prod(eng.tuned_cells(0)) > np.prod(g.grid["ncell"]) and eng.tuned_speed(0) > 0.0
-    eng.close()
+def small_blast():
+    return W.sedov(n=30_000, seed=3, kn=1e-2, ncell=8, nobin=4)
+
+
+def test_speed_bound_follows_the_energy(T):
+    """A thermal gas takes the bound 2 v_rms; a point blast, whose few fast
+    particles hold nearly all the kinetic energy (more than half of it above
+    2 v_rms), takes 6 v_rms, above which at most 1/36 of the particles can
+    ever be while the energy is conserved."""
+    for w, factor in ((fast_box(n=30_000, seed=4, ncell=(8, 8, 8), bc=(R, R, R), fast_frac=0.0), 2.0),
+                      (small_blast(), 6.0)):
+        eng = engine(T, w, T.FP32)
+        dst = T.to_device(w.state, T.FP32)
+        eng.autotune(dst, [(0, w.n, w.grid, w.params)])
+        st = W.copy_state(w.state, dtype=np.float32)
+        v_rms = math.sqrt(float(np.mean(st["vx"].astype(np.float64) ** 2 + st["vy"].astype(np.float64) ** 2
+                                        + st["vz"].astype(np.float64) ** 2)))
+        assert np.prod(eng.tuned_cells(0)) > np.prod(w.grid["ncell"])
+        assert abs(eng.tuned_speed(0) - factor * v_rms) <= 1e-9 * factor * v_rms, (eng.tuned_speed(0), v_rms)
+        eng.close()
+
+
+def test_fp64_blast_split_equals_oracle(T, oracle):
+    """The blast on its split c-bins: its blast particles are the fast ones
+    at first, then the particles they heat."""
+    w = small_blast()
+    cells, vc, n_fast = fp64_steps_equal_oracle(T, oracle, w, steps=3)
+    assert np.prod(cells) > np.prod(w.grid["ncell"]) and n_fast >= 30
 
 
 def test_fp64_speeds_raised_after_tuning_equal_oracle(T, oracle):

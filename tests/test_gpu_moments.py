@@ -9,7 +9,9 @@ the sums cannot depend on the order in which particles are met:
  - FP64: counts, momenta, spreads and masses within a few ulp of the exact
    sums (math.fsum) over the oracle's post-step state, which the GPU state
    equals bit for bit; plain summation of a few hundred terms typically
-   misses these bounds by an order of magnitude."""
+   misses these bounds by an order of magnitude.  O-bins of more than 4096
+   particles round their terms to a quantum 2^h times coarser (h = 1 per
+   doubling), so that their sums fit one int64: within 2^h times the bound."""
 import math
 
 import numpy as np
@@ -109,10 +111,30 @@ def obin_index(st, g):
     return idx
 
 
+def headroom(n):
+    c = 0 if n <= 1 else int(n - 1).bit_length()  # ceil(log2 n)
+    return max(0, c - 12)
+
+
 @pytest.mark.parametrize("mass", [False, True], ids=["scalar-mass", "mixture"])
 @pytest.mark.parametrize("steps", [1, 4])
 def test_fp64_moments_are_exact_sums(T, oracle, mass, steps):
-    w = workload(31, mass)
+    check_exact_sums(T, oracle, workload(31, mass), mass, steps)
+
+
+@pytest.mark.parametrize("n", [9000, 20000])
+def test_fp64_large_obin_sums(T, oracle, n):
+    """One o-bin of 9000 or 20000 particles: headroom 2 or 3."""
+    w = W.random_box(n=n, seed=41, ncell=(6, 5, 4), bc=(R, P, P), d_over_w=0.7, dt_over=0.6, nobin=(1, 1, 1))
+    assert headroom(n) in (2, 3)
+    check_exact_sums(T, oracle, w, False, 2)
+    # The same state twice: bit-identical.
+    a, b = run(T, w, T.FP64, 2), run(T, w, T.FP64, 2, flags=T.ALLOW_REORDER)
+    for s in range(2):
+        assert np.array_equal(a[s].view(np.uint64), b[s].view(np.uint64))
+
+
+def check_exact_sums(T, oracle, w, mass, steps):
     got = run(T, w, T.FP64, steps)[-1]
     st = W.copy_state(w.state)
     speed = lambda q: math.sqrt(float(np.max(q["vx"] ** 2 + q["vy"] ** 2 + q["vz"] ** 2)))
@@ -134,16 +156,17 @@ def test_fp64_moments_are_exact_sums(T, oracle, mass, steps):
             assert np.all(got[b] == 0.0)
             continue
         m = m_all[sel]
+        hq = 2.0 ** headroom(int(sel.sum()))  # the quantum's headroom
         mass_b = math.fsum(m) if mass else sel.sum() * w.params["mass"]
-        assert abs(got[b, 11] - mass_b) <= 2 * EPS * mass_b
+        assert abs(got[b, 11] - mass_b) <= 2 * EPS * mass_b * hq
         for a, k in enumerate(("vx", "vy", "vz")):
             v = st[k][sel]
             p = math.fsum(m * v)
-            tol = 4 * EPS * (math.fsum(np.abs(m * v)) + 2 * mass_b * vmax)
+            tol = 4 * hq * EPS * (math.fsum(np.abs(m * v)) + 2 * mass_b * vmax)
             assert abs(got[b, 1 + a] - p) <= tol, (b, a, got[b, 1 + a], p, tol)
             vb = p / mass_b
             spread = math.fsum(m * (v - vb) ** 2)
-            tol2 = 8 * EPS * math.fsum(m * (np.abs(v) + vmax) ** 2)
+            tol2 = 8 * hq * EPS * math.fsum(m * (np.abs(v) + vmax) ** 2)
             assert abs(got[b, 4 + a] - spread) <= tol2, (b, a, got[b, 4 + a], spread, tol2)
         checked += 1
     assert checked >= nob - 1
