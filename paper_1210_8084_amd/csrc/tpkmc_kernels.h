@@ -698,6 +698,12 @@ __device__ __forceinline__ void for_neighbourhood(const int32_t* start, const In
     for (int k = 0; k < 9; ++k) neighbourhood_row<HALF, COARSE>(start, I, base, n, per, cx, cy, cz, i, k, visit);
 }
 
+// Records per chunk of a wave's staging buffer in LDS (the staged lane mode
+// of the FP32 search, search_staged): kStageCap positions, then kStageCap
+// velocities.
+constexpr int kStageCap = 128;
+constexpr int kStageBytesPerWave = 2 * kStageCap * 16;
+
 // Closest-candidate search with register blocking: one lane owns up to G
 // consecutive records and tests every neighbour record it loads against all
 // of them, so a load serves up to G pair tests.  The lane walks the union of
@@ -891,7 +897,32 @@ __device__ __forceinline__ void search_group(const StepArgs<real>& a, const Inst
                 bool take[G];
 #pragma unroll
                 for (int k = 0; k < G; ++k) take[k] = hi[k] > lo[k];
-                for (int32_t j = jm; j < u1; ++j) visit(j, take);
+                int32_t j = jm;
+                if constexpr (G == 1) {
+                    // Two neighbours per iteration, one vote: the second's
+                    // loads are in flight with the first's, as a second
+                    // record per lane would do for G = 2.
+                    for (; j + 1 < u1; j += 2) {
+                        real xa_, ya_, za_, vxa, vya, vza, xb_, yb_, zb_, vxb, vyb, vzb;
+                        uint32_t ida, idb;
+                        RecU<real>::load(a.rec, j, xa_, ya_, za_, ida, vxa, vya, vza);
+                        RecU<real>::load(a.rec, j + 1, xb_, yb_, zb_, idb, vxb, vyb, vzb);
+                        Screen<real> SA, SB;
+                        const bool pa = PairTest<real, PM>::stage1(G_, xi[0], yi[0], zi[0], vxi[0], vyi[0], vzi[0],
+                                                                   xa_, ya_, za_, vxa, vya, vza, SA) & take[0];
+                        const bool pb = PairTest<real, PM>::stage1(G_, xi[0], yi[0], zi[0], vxi[0], vyi[0], vzi[0],
+                                                                   xb_, yb_, zb_, vxb, vyb, vzb, SB) & take[0];
+                        if constexpr (MIX) {
+                            n_s0 += (take[0] && SA.s0 < real(0)) ? 1u : 0u;
+                            n_s0 += (take[0] && SB.s0 < real(0)) ? 1u : 0u;
+                            n_c1 += (pa ? 1u : 0u) + (pb ? 1u : 0u);
+                        }
+                        if (__builtin_amdgcn_ballot_w64(pa | pb) == 0) continue;
+                        if (pa && PairTest<real, PM>::stage2(G_, SA)) hit(0, j, ida, SA);
+                        if (pb && PairTest<real, PM>::stage2(G_, SB)) hit(0, j + 1, idb, SB);
+                    }
+                }
+                for (; j < u1; ++j) visit(j, take);
             }
         }
     } else {
@@ -950,6 +981,138 @@ __device__ __forceinline__ void search_group(const StepArgs<real>& a, const Inst
     // Ordered scans see every pair twice and count the record itself once.
     tests = HALF ? (double)seen : 0.5 * (double)(seen - nrec);
     cand = HALF ? 2.0 * (double)nc : (double)nc;
+}
+
+// Lane mode of the FP32 half scans, staged through LDS.  A wave that owns
+// 64 G consecutive records takes them in G passes of 64, one record per lane
+// (record wbase + 64 p + lane in pass p), so that its registers are those of
+// one record whatever G is; G > 1 pays off in the wave-uniform mode instead.
+// In each pass, the lanes whose records share one row walk every neighbour
+// row together: the wave copies the union of their ranges in that row, a
+// contiguous run of records, into its LDS buffer in chunks of kStageCap, and
+// each lane reads its own part of each chunk from there.  A neighbour record
+// is then fetched from memory once per wave instead of once per lane whose
+// range holds it.  Records whose x-neighbourhood wraps around a periodic
+// axis walk their own rows with global loads.  The pairs tested, the
+// arithmetic and the combination of the keys are those of search_group, so
+// the results are too.  Called by every lane of a wave holding a live slow
+// record; stop ends the slow records.
+template <int PM, int G, bool MIX>
+__device__ __forceinline__ void search_staged(const StepArgs<float>& a, const Inst<float>& I, int64_t base,
+                                              int32_t wbase, int32_t stop, double& tests, double& cand,
+                                              uint32_t& n_s0, uint32_t& n_c1) {
+    const Geo<float> G_(I);
+    const int n[3] = {I.n[0], I.n[1], I.n[2]};
+    extern __shared__ float4 tpkmc_stage[];
+    float4* const sp = tpkmc_stage + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) * (2 * kStageCap);
+    float4* const sv = sp + kStageCap;
+    const int lane = (int)(threadIdx.x & 63);
+    const bool by_time = (I.flags & TPKMC_RANK_TIME) != 0;
+    int32_t seen = 0, nc = 0;
+    for (int p = 0; p < G; ++p) {
+        const int32_t i = wbase + p * kWave + lane;
+        const bool valid = i < stop;
+        if (__ballot(valid) == 0) break;  // uniform: later passes start further on
+        float xi, yi, zi, vxi, vyi, vzi;
+        Rec<float>::load6(a.rec, (uint32_t)(valid ? i : wbase), xi, yi, zi, vxi, vyi, vzi);
+        const int cx = axis_bin(xi, I.lo[0], I.inv_w[0], n[0]);
+        const int cy = axis_bin(yi, I.lo[1], I.inv_w[1], n[1]);
+        const int cz = axis_bin(zi, I.lo[2], I.inv_w[2], n[2]);
+        int xa[2], xb[2];
+        const bool joint = valid && x_ranges(cx, n[0], G_.per[0], xa, xb) == 1;
+        unsigned long long mine = ~0ull;
+        auto screen = [&](int32_t j, float xj, float yj, float zj, float vxj, float vyj, float vzj, bool take) {
+            Screen<float> S;
+            const bool p1 = PairTest<float, PM>::stage1(G_, xi, yi, zi, vxi, vyi, vzi, xj, yj, zj, vxj, vyj, vzj,
+                                                        S) & take;
+            if constexpr (MIX) {
+                n_s0 += (take && S.s0 < 0.0f) ? 1u : 0u;
+                n_c1 += p1 ? 1u : 0u;
+            }
+            if (__builtin_amdgcn_ballot_w64(p1) == 0) return;
+            if (p1 && PairTest<float, PM>::stage2(G_, S)) {
+                const float d2 = PairTest<float, PM>::finish(G_, S);
+                if (d2 >= 0.0f) {
+                    ++nc;
+                    const float key = by_time ? PairTest<float, PM>::contact(G_, S) : d2;
+                    const unsigned long long hi = (unsigned long long)sortable(key) << 32;
+                    atomicMin(a.bkey + j, hi | (uint32_t)i);
+                    const unsigned long long kk = hi | (uint32_t)j;
+                    mine = kk < mine ? kk : mine;
+                }
+            }
+        };
+        // Lanes taking part in the copies: all of the wave's.
+        const int own_row_l = row_of(I, cy, cz);
+        uint64_t pending = __ballot(joint);
+        while (pending) {
+            // One group of lanes per row.  Records are in c-bin order, so the
+            // group's lanes are consecutive and their x-bins non-decreasing:
+            // the first lane holds the union's lower end, the last its upper.
+            const int lead = __ffsll((long long)pending) - 1;
+            const int R = __builtin_amdgcn_readlane(own_row_l, lead);
+            const bool in = joint && own_row_l == R;
+            const uint64_t gm = __ballot(in);
+            pending &= ~gm;
+            const int last = 63 - __clzll((long long)gm);
+            const int gcy = __builtin_amdgcn_readlane(cy, lead);
+            const int gcz = __builtin_amdgcn_readlane(cz, lead);
+            const int ga = __builtin_amdgcn_readlane(xa[0], lead);
+            const int gb = __builtin_amdgcn_readlane(xb[0], last);
+            const int32_t gi = __builtin_amdgcn_readlane(i, lead);
+            for (int rr = 0; rr < 9; ++rr) {
+                int y, z;
+                if (!axis_nb(gcz, rr / 3 - 1, n[2], G_.per[2], z)) continue;
+                if (!axis_nb(gcy, rr % 3 - 1, n[1], G_.per[1], y)) continue;
+                const int row_idx = row_of(I, y, z);
+                if (row_idx < R) continue;  // half scans: rows of larger index, and own
+                const bool own = row_idx == R;
+                const int64_t row = I.cell_off + (int64_t)n[0] * row_idx;
+                int32_t lo = 0, hi = 0;  // the lane's range in this row
+                if (in) {
+                    lo = own ? i + 1 : (int32_t)(base + a.start[row + xa[0]]);
+                    hi = (int32_t)(base + a.start[row + xb[0] + 1]);
+                    seen += hi > lo ? hi - lo : 0;
+                }
+                const int32_t u0 = own ? gi + 1 : (int32_t)(base + a.start[row + ga]);
+                const int32_t u1 = (int32_t)(base + a.start[row + gb + 1]);
+                for (int32_t c0 = u0; c0 < u1; c0 += kStageCap) {
+                    const int32_t c1 = u1 - c0 < kStageCap ? u1 : c0 + kStageCap;
+                    // Copy [c0, c1): each record's position and velocity
+                    // quads.  The previous chunk's reads have all returned:
+                    // their values were used before its loop ended.
+                    const float4* src = reinterpret_cast<const float4*>(a.rec) + 2 * (int64_t)c0;
+                    for (int t = lane; t < c1 - c0; t += kWave) {
+                        sp[t] = src[2 * t];
+                        sv[t] = src[2 * t + 1];
+                    }
+                    // The wave's own writes, complete before any lane reads.
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                    __builtin_amdgcn_s_waitcnt(0xc07f);
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                    const int32_t j0 = lo > c0 ? lo : c0;
+                    const int32_t j1 = hi < c1 ? hi : c1;
+                    for (int32_t j = j0; j < j1; ++j) {
+                        const float4 pj = sp[j - c0], vj = sv[j - c0];
+                        screen(j, pj.x, pj.y, pj.z, vj.x, vj.y, vj.z, true);
+                    }
+                }
+            }
+        }
+        if (valid && !joint) {
+            for_neighbourhood<true>(a.start, I, base, n, G_.per, cx, cy, cz, i, [&](int32_t j0, int32_t j1) {
+                seen += j1 > j0 ? j1 - j0 : 0;
+                for (int32_t j = j0; j < j1; ++j) {
+                    float xj, yj, zj, vxj, vyj, vzj;
+                    Rec<float>::load6(a.rec, (uint32_t)j, xj, yj, zj, vxj, vyj, vzj);
+                    screen(j, xj, yj, zj, vxj, vyj, vzj, true);
+                }
+            });
+        }
+        if (valid && mine != ~0ull) atomicMin(a.bkey + i, mine);
+    }
+    tests = (double)seen;
+    cand = 2.0 * (double)nc;
 }
 
 // ---------------------------------------------------------------- 4a. fast particles of split c-bins
@@ -1342,8 +1505,24 @@ __device__ __forceinline__ void search_for_axes(int pm, const StepArgs<real>& a,
 #undef TPKMC_SEARCH
 }
 
+template <int G, bool MIX>
+__device__ __forceinline__ void search_staged_for_axes(int pm, const StepArgs<float>& a, const Inst<float>& I,
+                                                       int64_t base, int32_t wbase, int32_t stop, double& tests,
+                                                       double& cand, uint32_t& n_s0, uint32_t& n_c1) {
+#define TPKMC_STAGED(PMV) search_staged<PMV, G, MIX>(a, I, base, wbase, stop, tests, cand, n_s0, n_c1)
+    switch (pm) {
+        case 0: TPKMC_STAGED(0); break;
+        case 4: TPKMC_STAGED(4); break;
+        case 6: TPKMC_STAGED(6); break;
+        case 7: TPKMC_STAGED(7); break;
+        default: TPKMC_STAGED(-1); break;
+    }
+#undef TPKMC_STAGED
+}
+
 // One table entry (kBlock records) is covered by kBlock / G lanes, split
-// into work-groups of blockDim.x lanes.
+// into work-groups of blockDim.x lanes.  FP32 launches carry one LDS staging
+// buffer per wave (kStageBytesPerWave of dynamic LDS).
 // The FP32 two-records-per-lane shape (the usual autotuner choice) is held to
 // at most 72 VGPRs, 7 waves per SIMD instead of 6 at 78: the extra wave hides
 // more of the neighbour-load latency (measured 3-4% on the search).
@@ -1403,6 +1582,11 @@ k_search(StepArgs<real> a) {
         if (nslow > 0)
             search_for_axes<real, HALF, G, true, MIX>(pm, a, I, base, (int32_t)i0, nslow, wfirst, wub, tests, cand,
                                                       n_s0, n_c1);
+    } else if constexpr (HALF) {
+        if (live) {  // wave-uniform: every lane of the wave takes part
+            const int32_t wbase = (int32_t)(i0 - (int64_t)(threadIdx.x & 63) * G);
+            search_staged_for_axes<G, MIX>(pm, a, I, base, wbase, (int32_t)slow_stop, tests, cand, n_s0, n_c1);
+        }
     } else if (nslow > 0) {
         search_for_axes<real, HALF, G, false, MIX>(pm, a, I, base, (int32_t)i0, nslow, 0, 0, tests, cand, n_s0,
                                                    n_c1);
@@ -2307,9 +2491,10 @@ void launch_search(const StepArgs<real>& a, int block, int group, hipStream_t s)
     const int lanes = kBlock / group;
     const int bs = block < lanes ? block : lanes;
     const unsigned grid = (unsigned)a.nblk * (unsigned)(lanes / bs);
-    if (group == 4) hipLaunchKernelGGL((k_search<real, half, 4>), dim3(grid), dim3(bs), 0, s, a);
-    else if (group == 2) hipLaunchKernelGGL((k_search<real, half, 2>), dim3(grid), dim3(bs), 0, s, a);
-    else hipLaunchKernelGGL((k_search<real, half, 1>), dim3(grid), dim3(bs), 0, s, a);
+    const size_t lds = half ? (size_t)(bs / kWave) * kStageBytesPerWave : 0;  // staging buffers
+    if (group == 4) hipLaunchKernelGGL((k_search<real, half, 4>), dim3(grid), dim3(bs), lds, s, a);
+    else if (group == 2) hipLaunchKernelGGL((k_search<real, half, 2>), dim3(grid), dim3(bs), lds, s, a);
+    else hipLaunchKernelGGL((k_search<real, half, 1>), dim3(grid), dim3(bs), lds, s, a);
 }
 template <typename real>
 void launch_search_mix(const StepArgs<real>& a, int block, int n_inst, bool split, hipStream_t s) {
@@ -2317,7 +2502,8 @@ void launch_search_mix(const StepArgs<real>& a, int block, int n_inst, bool spli
     const int lanes = kBlock / 2;
     const int bs = block < lanes ? block : lanes;
     const unsigned grid = (unsigned)a.nblk * (unsigned)(lanes / bs);
-    hipLaunchKernelGGL((k_search<real, half, 2, true>), dim3(grid), dim3(bs), 0, s, a);
+    const size_t lds = half ? (size_t)(bs / kWave) * kStageBytesPerWave : 0;
+    hipLaunchKernelGGL((k_search<real, half, 2, true>), dim3(grid), dim3(bs), lds, s, a);
     if (split) {
         const unsigned fg = (unsigned)std::max(1, std::min(2048, a.nblk));
         hipLaunchKernelGGL((k_search_fast<real, half, true>), dim3(fg), dim3(256), 0, s, a, n_inst);

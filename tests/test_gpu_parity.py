@@ -38,9 +38,11 @@ def engine_for(T, w, precision, n_inst=1):
                     precision=precision, max_instances=n_inst)
 
 
-def gpu_steps(T, w, precision, steps=1, flags=None, pair_cap=None, state=None):
+def gpu_steps(T, w, precision, steps=1, flags=None, pair_cap=None, state=None, shape=None):
     flags = T.EMIT_PAIRS if flags is None else flags
     eng = engine_for(T, w, precision)
+    if shape is not None:
+        eng.set_search(*shape)
     dst = T.to_device(w.state if state is None else state, precision)
     cap = w.n // 2 + 1 if pair_cap is None else pair_cap
     out = T.make_outputs(1, T.nobins(w.grid), pair_cap=cap)
@@ -129,6 +131,24 @@ def test_fp64_one_step_bit_exact(T, oracle, case, n):
     assert_outputs_match(gouts[0], routs[0], w.params["mass"])
     assert routs[0]["counters"][1] > 50
     assert status & T.STATUS_PAIR_OVERFLOW == 0
+
+
+@pytest.mark.parametrize("case", [CASES[0], CASES[3], CASES[4], CASES[6]],
+                         ids=lambda c: f"s{c['seed']}-{c['ncell']}-{c['bc']}")
+@pytest.mark.parametrize("shape", [(1, 64), (1, 256)], ids=lambda s: f"{s[0]}x{s[1]}")
+def test_fp64_one_record_per_lane_bit_exact(T, oracle, case, shape):
+    """One record per lane: on dense bins the wave-uniform walk takes two
+    neighbours per iteration, on sparse ones each lane walks its own rows;
+    two steps stay bit-identical to the oracle."""
+    w = W.random_box(n=2999, seed=case["seed"] + 30, ncell=case["ncell"], bc=case["bc"], d_over_w=0.7,
+                     dt_over=0.6, nobin=(3, 2, 1))
+    _say(f"one-record case {case} shape {shape}")
+    got, gouts, _ = gpu_steps(T, w, T.FP64, steps=2, shape=shape)
+    want, routs = oracle_steps(oracle, w, steps=2)
+    assert_state_equal(got, want)
+    for go, ro in zip(gouts, routs):
+        assert_outputs_match(go, ro, w.params["mass"])
+    assert routs[0]["counters"][1] > 50
 
 
 def test_fp64_trajectory_bit_exact(T, oracle):
