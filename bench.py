@@ -346,6 +346,9 @@ def main():
     ap.add_argument("--search", default="auto",
                     help="'auto': the autotuner's results-neutral choice of c-bins and search launch shape; or a "
                          "fixed shape 'G,B' (records per lane, lanes per work-group) on the configured c-bins")
+    ap.add_argument("--search-order", type=int, default=None,
+                    help="search work-group order in place of the tuned one: 0 contiguous per XCD, S > 0 chunks "
+                         "of S work-groups dealt round-robin")
     ap.add_argument("--batch-scale", type=float, default=1.0, help="batched ensemble: scale every instance size")
     ap.add_argument("--batch-steps", type=int, default=10, help="batched ensemble: timed steps")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -404,6 +407,8 @@ def main():
         eng.autotune(dst, [(0, w.n, g, p)], stream=stream)
     else:
         eng.set_search(*[int(v) for v in args.search.split(",")])
+    if args.search_order is not None:
+        eng.set_search_order(args.search_order)
     for k in range(Wm):
         step(k, 0)
     torch.cuda.synchronize()
@@ -479,6 +484,7 @@ def main():
     peak = PEAK_FLOPS[args.precision]
     shape = eng.get_search()
     shape = (shape[0], min(shape[1], 256 // shape[0]))
+    order = eng.search_order()
     cbins = list(eng.tuned_cells(0)) if args.search == "auto" else list(g["ncell"])
     traffic = read_traffic(args.workload, args.precision, shape, cbins)
     bytes_per = phase_bytes(rs, w.n, int(np.prod(cbins)) + 1, nob, True, colliders=2 * pairs / max(K, 1))
@@ -535,6 +541,7 @@ def main():
                      "frac": achieved / peak, "traffic": traffic,
                      "algorithmic_bytes": bytes_per["search"],
                      "search_shape": list(shape),
+                     "search_order": order,
                      "avg_launch_ms": search_ms / max(search_n, 1),
                      "flop_per_pair_test": flops / max(tests, 1.0),
                      "flop_model": f"{FLOP_S0} per test + {FLOP_S1} per approaching pair + {FLOP_DMIN} per pair "

@@ -347,10 +347,12 @@ int tpkmc_run(tpkmc_handle* h, const tpkmc_particles* s,
  *  - the launch shape (work-group size and particles per work-item): timed,
  *    the default kept unless another is at least 5% faster;
  *  - the order in which the search's work-groups are dealt to the XCDs:
- *    contiguous ranges (the default: neighbouring work-groups share an L2)
- *    or chunks of 1, 16 or 128 work-groups round-robin (balance when the
- *    work per work-group varies, as across a batch of instances), timed in
- *    the chosen shape and kept when at least 3% faster.
+ *    chunks of 16 work-groups dealt round-robin over the XCDs (the default:
+ *    balance when the work per work-group varies along the c-bin order, as
+ *    across a batch of instances or in a dense shocked region), contiguous
+ *    ranges per XCD (neighbouring work-groups share an L2), or chunks of 1
+ *    or 128; another order is timed in the chosen shape and kept when at
+ *    least 5% faster.
  * Runs the binning and search kernels only; the particle state is not
  * modified.  Synchronises the stream. */
 int tpkmc_autotune(tpkmc_handle* h, const tpkmc_particles* s,
@@ -361,7 +363,7 @@ int tpkmc_autotune(tpkmc_handle* h, const tpkmc_particles* s,
 int tpkmc_search_order(tpkmc_handle* h, int32_t* order);
 
 /* Sets that order (0, or a chunk of 1..4096 work-groups); results do not
- * depend on it. */
+ * depend on it.  tpkmc_set_search resets it to the default, 16. */
 int tpkmc_set_search_order(tpkmc_handle* h, int32_t order);
 
 /* The slow particles' c-bins per axis that tpkmc_autotune chose for batch

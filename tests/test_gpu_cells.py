@@ -312,7 +312,7 @@ def test_search_order_is_results_neutral(T):
             pairs.append(sorted(map(tuple, out.host()["pairs"].tolist())))
         got = T.to_host(dst)
         eng.set_search(2, 64)
-        assert eng.search_order() == 0  # fixing the shape resets the order
+        assert eng.search_order() == 16  # fixing the shape resets the order to the default
         eng.close()
         if ref is None:
             ref = (got, pairs)
