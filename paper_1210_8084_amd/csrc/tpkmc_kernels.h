@@ -699,11 +699,12 @@ __device__ __forceinline__ void for_neighbourhood(const int32_t* start, const In
 }
 
 // Records per chunk of a wave's staging buffer in LDS (the staged lane mode
-// of the FP32 search, search_staged): kStageCap quads (x, y, z, vx), then
-// kStageCap pairs (vy, vz), 24 B per record (measured against the records'
-// own 32 B layout: Sedov 16M search 1.27 against 1.34 ms).
+// of the FP32 search, search_staged).  Each record takes 32 B: the quad
+// (x, y, z, vx), then the pair (vy, vz) 16 B further, so that one address
+// serves both reads and the loop reads 24 B per neighbour (two quads per
+// neighbour, 32 B read, took the 16M Sedov search from 1.27 to 1.34 ms).
 constexpr int kStageCap = 128;
-constexpr int kStageBytesPerWave = kStageCap * 24;
+constexpr int kStageBytesPerWave = kStageCap * 32;
 static_assert(kStageBytesPerWave % 16 == 0, "each wave's buffer starts on a quad");
 
 // Closest-candidate search with register blocking: one lane owns up to G
@@ -1008,7 +1009,6 @@ __device__ __forceinline__ void search_staged(const StepArgs<float>& a, const In
     extern __shared__ float4 tpkmc_stage[];
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     float4* const sp = tpkmc_stage + wave * (kStageBytesPerWave / 16);
-    float2* const sv = reinterpret_cast<float2*>(sp + kStageCap);
     const int lane = (int)(threadIdx.x & 63);
     const bool by_time = (I.flags & TPKMC_RANK_TIME) != 0;
     int32_t seen = 0, nc = 0;
@@ -1026,20 +1026,30 @@ __device__ __forceinline__ void search_staged(const StepArgs<float>& a, const In
         unsigned long long mine = ~0ull;
         auto screen = [&](int32_t j, float xj, float yj, float zj, float vxj, float vyj, float vzj, bool take) {
             Screen<float> S;
-            const bool p1 = PairTest<float, PM>::stage1(G_, xi, yi, zi, vxi, vyi, vzi, xj, yj, zj, vxj, vyj, vzj,
-                                                        S) & take;
+            // Criterion 1 as two votes on the compares themselves, so that
+            // the wave's decision stays in scalar masks.
+            (void)PairTest<float, PM>::stage1(G_, xi, yi, zi, vxi, vyi, vzi, xj, yj, zj, vxj, vyj, vzj, S);
+            const bool a0 = take & (S.s0 < 0.0f);
+            const bool a1 = fmaf(S.vv, G_.dt, S.s0) > 0.0f;
+            const uint64_t m = __builtin_amdgcn_ballot_w64(a0) & __builtin_amdgcn_ballot_w64(a1);
+            const bool p1 = a0 & a1;
             if constexpr (MIX) {
                 n_s0 += (take && S.s0 < 0.0f) ? 1u : 0u;
                 n_c1 += p1 ? 1u : 0u;
             }
-            if (__builtin_amdgcn_ballot_w64(p1) == 0) return;
+            if (m == 0) return;
             if (p1 && PairTest<float, PM>::stage2(G_, S)) {
                 const float d2 = PairTest<float, PM>::finish(G_, S);
                 if (d2 >= 0.0f) {
                     ++nc;
                     const float key = by_time ? PairTest<float, PM>::contact(G_, S) : d2;
                     const unsigned long long hi = (unsigned long long)sortable(key) << 32;
-                    atomicMin(a.bkey + j, hi | (uint32_t)i);
+                    // An empty barrier on j keeps the compiler from carrying
+                    // a 64-bit key pointer through the whole loop for this
+                    // rare path.
+                    int32_t jh = j;
+                    asm volatile("" : "+v"(jh));
+                    atomicMin(a.bkey + jh, hi | (uint32_t)i);
                     const unsigned long long kk = hi | (uint32_t)j;
                     mine = kk < mine ? kk : mine;
                 }
@@ -1087,8 +1097,8 @@ __device__ __forceinline__ void search_staged(const StepArgs<float>& a, const In
                     const float4* src = reinterpret_cast<const float4*>(a.rec) + 2 * (int64_t)c0;
                     for (int t = lane; t < c1 - c0; t += kWave) {
                         const float4 qa = src[2 * t], qb = src[2 * t + 1];
-                        sp[t] = make_float4(qa.x, qa.y, qa.z, qb.x);
-                        sv[t] = make_float2(qb.y, qb.z);
+                        sp[2 * t] = make_float4(qa.x, qa.y, qa.z, qb.x);
+                        *reinterpret_cast<float2*>(sp + 2 * t + 1) = make_float2(qb.y, qb.z);
                     }
                     // The wave's own writes, complete before any lane reads.
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -1097,8 +1107,8 @@ __device__ __forceinline__ void search_staged(const StepArgs<float>& a, const In
                     const int32_t j0 = lo > c0 ? lo : c0;
                     const int32_t j1 = hi < c1 ? hi : c1;
                     for (int32_t j = j0; j < j1; ++j) {
-                        const float4 pj = sp[j - c0];
-                        const float2 vj = sv[j - c0];
+                        const float4 pj = sp[2 * (j - c0)];
+                        const float2 vj = *reinterpret_cast<const float2*>(sp + 2 * (j - c0) + 1);
                         screen(j, pj.x, pj.y, pj.z, pj.w, vj.x, vj.y, true);
                     }
                 }
