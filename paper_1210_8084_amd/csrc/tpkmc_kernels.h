@@ -699,10 +699,14 @@ __device__ __forceinline__ void for_neighbourhood(const int32_t* start, const In
 }
 
 // Records per chunk of a wave's staging buffer in LDS (the staged lane mode
-// of the FP32 search, search_staged).  Each record takes 32 B: the quad
-// (x, y, z, vx), then the pair (vy, vz) 16 B further, so that one address
-// serves both reads and the loop reads 24 B per neighbour (two quads per
-// neighbour, 32 B read, took the 16M Sedov search from 1.27 to 1.34 ms).
+// of the FP32 search, search_staged): kStageCap quads (x, y, z, vx), then
+// kStageCap pairs (vy, vz) in 16-byte slots, so that one address serves
+// both reads (the pair kStageCap slots further on) and the loop reads 24 B
+// per neighbour at a 16-byte stride.  Measured on the 16M Sedov search:
+// 1.34 ms reading two quads per neighbour, 1.27 with the pairs packed at an
+// 8-byte stride (two addresses), 1.24 with quad and pair interleaved in
+// 32-byte slots (one address, four times the LDS bank conflicts), 1.23
+// with this layout.
 constexpr int kStageCap = 128;
 constexpr int kStageBytesPerWave = kStageCap * 32;
 static_assert(kStageBytesPerWave % 16 == 0, "each wave's buffer starts on a quad");
@@ -1097,8 +1101,8 @@ __device__ __forceinline__ void search_staged(const StepArgs<float>& a, const In
                     const float4* src = reinterpret_cast<const float4*>(a.rec) + 2 * (int64_t)c0;
                     for (int t = lane; t < c1 - c0; t += kWave) {
                         const float4 qa = src[2 * t], qb = src[2 * t + 1];
-                        sp[2 * t] = make_float4(qa.x, qa.y, qa.z, qb.x);
-                        *reinterpret_cast<float2*>(sp + 2 * t + 1) = make_float2(qb.y, qb.z);
+                        sp[t] = make_float4(qa.x, qa.y, qa.z, qb.x);
+                        *reinterpret_cast<float2*>(sp + kStageCap + t) = make_float2(qb.y, qb.z);
                     }
                     // The wave's own writes, complete before any lane reads.
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -1107,8 +1111,8 @@ __device__ __forceinline__ void search_staged(const StepArgs<float>& a, const In
                     const int32_t j0 = lo > c0 ? lo : c0;
                     const int32_t j1 = hi < c1 ? hi : c1;
                     for (int32_t j = j0; j < j1; ++j) {
-                        const float4 pj = sp[2 * (j - c0)];
-                        const float2 vj = *reinterpret_cast<const float2*>(sp + 2 * (j - c0) + 1);
+                        const float4 pj = sp[j - c0];
+                        const float2 vj = *reinterpret_cast<const float2*>(sp + kStageCap + (j - c0));
                         screen(j, pj.x, pj.y, pj.z, pj.w, vj.x, vj.y, true);
                     }
                 }
