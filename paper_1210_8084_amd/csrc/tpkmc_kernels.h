@@ -1543,8 +1543,9 @@ __device__ __forceinline__ void search_staged_for_axes(int pm, const StepArgs<fl
 // into work-groups of blockDim.x lanes.  FP32 launches carry one LDS staging
 // buffer per wave (kStageBytesPerWave of dynamic LDS).
 // The FP32 two-records-per-lane shape (the usual autotuner choice) is held to
-// at most 72 VGPRs, 7 waves per SIMD instead of 6 at 78: the extra wave hides
-// more of the neighbour-load latency (measured 3-4% on the search).
+// at most 72 VGPRs, 7 waves per SIMD (with a lane mode walking both records
+// at once it needed 78, and the seventh wave was worth 3-4% on the search);
+// with the staged lane mode, one record per pass, it needs 68.
 template <typename real, bool HALF, int G, bool MIX = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((HALF && G == 2) ? 7 : 1, 8)))
 k_search(StepArgs<real> a) {
