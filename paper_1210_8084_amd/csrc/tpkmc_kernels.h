@@ -1059,6 +1059,42 @@ __device__ __forceinline__ void search_staged(const StepArgs<float>& a, const In
                 }
             }
         };
+        // Two neighbours j and j + 1 of the staged chunk, one vote: the two
+        // tests are independent, so their LDS reads and arithmetic overlap
+        // (the loop takes neighbours in pairs; measured on the 16M Sedov
+        // search 1.23 -> 1.18 ms, the Noh and Sod searches 2-3% faster).
+        auto screen2 = [&](int32_t j, const float4& pa, const float2& va, const float4& pb, const float2& vb) {
+            Screen<float> SA, SB;
+            (void)PairTest<float, PM>::stage1(G_, xi, yi, zi, vxi, vyi, vzi, pa.x, pa.y, pa.z, pa.w, va.x, va.y, SA);
+            (void)PairTest<float, PM>::stage1(G_, xi, yi, zi, vxi, vyi, vzi, pb.x, pb.y, pb.z, pb.w, vb.x, vb.y, SB);
+            const bool qa0 = SA.s0 < 0.0f, qa1 = fmaf(SA.vv, G_.dt, SA.s0) > 0.0f;
+            const bool qb0 = SB.s0 < 0.0f, qb1 = fmaf(SB.vv, G_.dt, SB.s0) > 0.0f;
+            const uint64_t m = (__builtin_amdgcn_ballot_w64(qa0) & __builtin_amdgcn_ballot_w64(qa1)) |
+                               (__builtin_amdgcn_ballot_w64(qb0) & __builtin_amdgcn_ballot_w64(qb1));
+            const bool pa1 = qa0 & qa1, pb1 = qb0 & qb1;
+            if constexpr (MIX) {
+                n_s0 += (qa0 ? 1u : 0u) + (qb0 ? 1u : 0u);
+                n_c1 += (pa1 ? 1u : 0u) + (pb1 ? 1u : 0u);
+            }
+            if (m == 0) return;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const Screen<float>& S = h ? SB : SA;
+                if ((h ? pb1 : pa1) && PairTest<float, PM>::stage2(G_, S)) {
+                    const float d2 = PairTest<float, PM>::finish(G_, S);
+                    if (d2 >= 0.0f) {
+                        ++nc;
+                        const float key = by_time ? PairTest<float, PM>::contact(G_, S) : d2;
+                        const unsigned long long hk = (unsigned long long)sortable(key) << 32;
+                        int32_t jh = j + h;  // see screen
+                        asm volatile("" : "+v"(jh));
+                        atomicMin(a.bkey + jh, hk | (uint32_t)i);
+                        const unsigned long long kk = hk | (uint32_t)(j + h);
+                        mine = kk < mine ? kk : mine;
+                    }
+                }
+            }
+        };
         // Lanes taking part in the copies: all of the wave's.
         const int own_row_l = row_of(I, cy, cz);
         uint64_t pending = __ballot(joint);
@@ -1110,7 +1146,14 @@ __device__ __forceinline__ void search_staged(const StepArgs<float>& a, const In
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
                     const int32_t j0 = lo > c0 ? lo : c0;
                     const int32_t j1 = hi < c1 ? hi : c1;
-                    for (int32_t j = j0; j < j1; ++j) {
+                    int32_t j = j0;
+                    for (; j + 1 < j1; j += 2) {
+                        const float4 pa = sp[j - c0], pb = sp[j + 1 - c0];
+                        const float2 va = *reinterpret_cast<const float2*>(sp + kStageCap + (j - c0));
+                        const float2 vb = *reinterpret_cast<const float2*>(sp + kStageCap + (j + 1 - c0));
+                        screen2(j, pa, va, pb, vb);
+                    }
+                    if (j < j1) {
                         const float4 pj = sp[j - c0];
                         const float2 vj = *reinterpret_cast<const float2*>(sp + kStageCap + (j - c0));
                         screen(j, pj.x, pj.y, pj.z, pj.w, vj.x, vj.y, true);
