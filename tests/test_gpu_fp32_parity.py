@@ -204,9 +204,10 @@ def check_against_oracle(T, oracle, w, flags=0, min_pairs=100, shape=None):
     return len(gs ^ os_)
 
 
-# Launch shapes: (records per lane, lanes per work-group).  One record per
-# lane runs the balanced reach walk on sparse c-bins; two and four run the
-# per-lane walk.
+# Launch shapes: (records per lane, lanes per work-group).  Every shape walks
+# sparse c-bins in the staged lane mode (one record per lane per pass, the
+# neighbour rows copied to LDS) and dense ones in lock-step; records per lane
+# set the passes of the one and the register blocking of the other.
 SHAPES = [(2, 64), (1, 64), (1, 256)]
 
 
