@@ -20,7 +20,9 @@ oracle's step on the same input:
 
 The dense cases (hundreds to thousands of records per c-bin) run the
 wave-uniform walk with its split at the last lane's lower end; the sparse
-one runs the per-lane walk."""
+ones run the staged lane walk, whose neighbour rows are copied to LDS in
+chunks of 128 records (several chunks per row at about 40 records per
+c-bin), and records next to a periodic x seam walk their own rows."""
 import math
 import sys
 
@@ -213,8 +215,8 @@ SHAPES = [(2, 64), (1, 64), (1, 256)]
 
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: f"{s[0]}x{s[1]}")
 def test_sparse_box_lane_walk(T, oracle, shape):
-    """About 50 records per c-bin at most; per-lane walks, or the balanced
-    reach walk with one record per lane."""
+    """About 40 records per c-bin: the staged lane walk, its row unions
+    longer than one LDS chunk in the two-records-per-lane shape."""
     w = W.random_box(n=20000, seed=4, ncell=(10, 8, 6), bc=(R, P, P), d_over_w=0.7, dt_over=0.5)
     check_against_oracle(T, oracle, w, shape=shape)
 
