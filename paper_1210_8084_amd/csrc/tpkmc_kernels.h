@@ -715,7 +715,8 @@ static_assert(kStageBytesPerWave % 16 == 0, "each wave's buffer starts on a quad
 // consecutive records and tests every neighbour record it loads against all
 // of them, so a load serves up to G pair tests.  The lane walks the union of
 // its records' neighbourhoods row by row; record k only takes the records in
-// its own range of that row.
+// its own range of that row.  It serves the wave-uniform mode of both
+// precisions and the lane mode of FP64; the FP32 lane mode is search_staged.
 //
 // HALF (FP32): every unordered pair is tested once -- bins of larger index
 // and, in a record's own bin, the records after it -- and a candidate lowers
@@ -1615,7 +1616,8 @@ k_search(StepArgs<real> a) {
     const int nslow = i0 < slow_stop ? (int)(slow_stop - i0 < nrec ? slow_stop - i0 : nrec) : 0;
     // Wave-uniform mode when the wave's live slow records lie in at most two
     // neighbouring bins of one row (dense bins): decided on the first and
-    // last of them, so the branch is uniform.
+    // last of them, so the branch is uniform.  Otherwise the lane mode:
+    // staged through LDS in FP32 (search_staged), per lane in FP64.
     const uint64_t live = __ballot(nslow > 0);
     bool uni = false;
     int32_t wfirst = 0;
